@@ -1,0 +1,29 @@
+"""ORACLE -- test infrastructure, not part of the product.
+
+A plain, slow, obviously correct CPU implementation of what the MBE-FCI hot
+path computes, written from the paper (Eriksen & Gauss, "Many-Body Expanded
+Full Configuration Interaction. II. Strongly Correlated Regime"):
+
+* ``fci``  -- the energy of one CASCI problem (Sec. 2: the energy of the
+  composite space of the reference space and a tuple of expansion orbitals,
+  all other occupied orbitals frozen) as the lowest eigenvalue of the
+  Slater-Condon Hamiltonian over full-orbital-space determinants (``sc.c``);
+  dense ``numpy.linalg.eigvalsh`` on small spaces, ARPACK Lanczos
+  (``scipy.sparse.linalg.eigsh``) on a matrix-free product above that.
+* ``mbe``  -- the increment recursion of Eq. 3 over orbital tuples that are
+  supersets of the reference space [Pi] (Eq. 1-3), the screening rule and the
+  order sums.
+* ``rdm``  -- one- and two-particle density matrices by explicit operator
+  action, the adjoint weights of the increment recursion and the gradient of
+  the summed MBE energy with respect to h_pq and (pq|rs).
+
+Only ``tests/``, the smoke check of ``__graft_entry__`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the HIP path; the only common module is ``synth`` (seeded inputs).
+
+Parity unpinned: the screening constants and rule (``mbe.screen_threshold`` and
+the child-generation rule) are a reading, since the paper only names the
+screening threshold a; they are pinned only by agreement between the two
+implementations.
+"""
+from . import fci, mbe, rdm  # noqa: F401
