@@ -1,0 +1,222 @@
+/*
+ * mbefci.h -- C ABI of the MI355X MBE-FCI library (libmbefci.so).
+ *
+ * What the library computes (Eriksen & Gauss, "Many-Body Expanded Full
+ * Configuration Interaction. II. Strongly Correlated Regime"):
+ *
+ *   * Sec. 2, Eq. 3: for every tuple S of expansion orbitals, the CASCI energy
+ *     eps(S) in the composite space A = [Pi] u S of the reference space [Pi] and
+ *     the tuple, every other occupied orbital frozen doubly occupied; and the
+ *     increment d_eps(S) = eps(S) - sum_{T proper subtuple of S} d_eps(T) with
+ *     d_eps({}) = eps([Pi]).
+ *   * Eq. 1: the order sums E^(k) = sum_{|S| = k} d_eps(S) and their total.
+ *   * The screening threshold a (Sec. 4.1, "a = 5.0" / "a = 2.5"); the rule is
+ *     a reading, stated at mbefci_options.a.
+ *
+ * Conventions that hold for every call:
+ *   * Every function returns mbefci_status: 0 on success, < 0 on error; no C++
+ *     exception crosses the ABI.  mbefci_last_error() gives a message.
+ *   * Orbital indices are 0-based.  Occupied orbitals are chosen by index:
+ *     alpha 0..nalpha-1, doubly occupied 0..nbeta-1 (nalpha >= nbeta).  The
+ *     singly occupied orbitals nbeta..nalpha-1 must lie in [Pi] (the paper's
+ *     open-shell case (b)).  Orbitals 0..nfrozen-1 are frozen (Sec. 3).
+ *     Expansion space X = all orbitals outside the frozen set and [Pi].
+ *   * For a tuple S: A = [Pi] u S (ascending), core C = frozen u (docc \ A),
+ *     active electrons nalpha - |C| and nbeta - |C|.
+ *   * Determinants of a CAS are ordered alpha-string-major: index
+ *     ia * n_beta_strings + ib, strings ascending as bit masks over the
+ *     positions of A, determinant = core creators, then active alpha creators
+ *     (ascending), then active beta creators (ascending).  Against creators
+ *     ordered over the whole orbital space a determinant differs by the sign
+ *     (-1)^(pairs of an active electron below a core orbital, per spin); the
+ *     spectrum is the same.
+ *   * The caller owns every host array and the device workspace.  The library
+ *     copies what it keeps (integrals, spaces, options).  All device work is
+ *     enqueued on the stream given at creation; host outputs are complete
+ *     (stream synchronised) when a call returns.
+ *   * Energies are in hartree, FP64 end to end.
+ */
+#ifndef MBEFCI_H
+#define MBEFCI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbefci_ctx mbefci_ctx;         /* opaque; create/destroy below */
+typedef struct mbefci_result mbefci_result;   /* opaque; owned until mbefci_result_free */
+
+typedef enum {
+    MBEFCI_OK = 0,
+    MBEFCI_EINVAL = -1,     /* bad argument (non-finite or non-symmetric h, bad tuple, ...) */
+    MBEFCI_ENOMEM = -2,     /* device workspace too small for even one tuple */
+    MBEFCI_EDEVICE = -3,    /* a HIP runtime call failed */
+    MBEFCI_ENOCONV = -4,    /* at least one tuple did not converge; per-tuple status filled */
+    MBEFCI_ESTATE = -5,     /* call out of order (no Hamiltonian, host-only context, ...) */
+    MBEFCI_ETOOLARGE = -6   /* a CAS exceeds the kernels' limits (more than 13 active orbitals) */
+} mbefci_status;
+
+/* per-tuple solve status */
+enum {
+    MBEFCI_TUPLE_OK = 0,        /* converged */
+    MBEFCI_TUPLE_MAXITER = 1,   /* iteration limit reached */
+    MBEFCI_TUPLE_NONFINITE = 2, /* NaN/Inf met in the iteration */
+    MBEFCI_TUPLE_STALLED = 3    /* correction vector fell inside the subspace before convergence */
+};
+
+typedef enum {
+    MBEFCI_ERI_FULL = 0,        /* n^4 row-major, eri[((p*n+q)*n+r)*n+s] = (pq|rs) */
+    MBEFCI_ERI_PACKED8 = 1      /* unique elements: P = p(p+1)/2+q (p>=q), R likewise,
+                                   element [P(P+1)/2 + R] for P >= R */
+} mbefci_eri_layout;
+
+typedef struct {
+    /* Screening (a reading: the paper names the threshold a, larger a = more
+     * aggressive).  tau_k = 1e-10 * a^(k-1) for increments of order k; an
+     * order-(k+1) tuple is computed iff at least one of its k-subtuples was
+     * computed at order k with |d_eps| >= tau_k.  Order 1 is never screened.
+     * a <= 0 disables screening. */
+    double a;
+    int32_t max_order;      /* highest order; <= 0 means |X| (full order) */
+    double e_tol;           /* Davidson: |theta - theta_prev| bound (default 1e-11) */
+    double r_tol;           /* Davidson: residual 2-norm bound (default 1e-6; the Ritz value
+                               then lies within about r_tol^2 / gap of the eigenvalue) */
+    int32_t max_iter;       /* Davidson iterations per tuple (default 200) */
+    int32_t max_space;      /* subspace vectors before restart, 2..32 (default 12) */
+    int32_t batched;        /* 1: every tuple of a shape class in one batch of launches;
+                               0: one tuple per launch sequence (the per-solve path) */
+    int32_t keep_vectors;   /* reserved for the backward pass; 0 */
+    int32_t profile;        /* 1: time every sigma launch with HIP events (mbefci_get_stats) */
+    int32_t reserved[7];
+} mbefci_options;
+
+typedef struct {
+    int64_t ntuples;            /* tuples solved by the last solve/run call */
+    int64_t sigma_calls;        /* sigma applications (one per tuple per iteration) */
+    int64_t sigma_launches;     /* launches of the dominant sigma kernel */
+    double sigma_flops;         /* algorithmic FLOPs, 2 * P_A^2 * dim per application */
+    double sigma_bytes;         /* algorithmic bytes, 16 * dim + 8 * P_A^2 per application */
+    double sigma_ms;            /* HIP-event time of the dominant sigma kernel (profile = 1) */
+    double sigma_total_ms;      /* HIP-event time of all sigma kernels (profile = 1) */
+    int64_t iterations_total;   /* Davidson iterations summed over tuples */
+    int64_t iterations_max;
+    double solve_ms;            /* host wall time inside solve/run */
+} mbefci_stats;
+
+/* Library version string. */
+const char *mbefci_version(void);
+
+/* Fill `opt` with the defaults listed at mbefci_options. */
+void mbefci_default_options(mbefci_options *opt);
+
+/* Create a context on HIP device `hip_device` (>= 0) using `hip_stream`
+ * (a hipStream_t, NULL = the default stream).  hip_device = -1 creates a
+ * host-only context: the planner (mbefci_run_host) works, device calls return
+ * MBEFCI_ESTATE. */
+mbefci_status mbefci_create(mbefci_ctx **ctx, int32_t hip_device, void *hip_stream);
+void mbefci_destroy(mbefci_ctx *ctx);
+
+/* Message of the last failing call on `ctx` (valid until the next call). */
+const char *mbefci_last_error(const mbefci_ctx *ctx);
+
+/* Hamiltonian in an orthonormal MO basis: h1 (norb*norb, symmetric within
+ * 1e-12, finite), eri in `layout` (8-fold symmetric), constant e_const.
+ * Copied; on a device context the integrals are kept resident on the device
+ * (n^4 doubles, allocated by the library).  EINVAL on norb < 1 or > 64,
+ * non-finite or non-symmetric input. */
+mbefci_status mbefci_set_hamiltonian(mbefci_ctx *ctx, int32_t norb, const double *h1,
+                                     const double *eri, mbefci_eri_layout layout,
+                                     double e_const);
+
+/* Electrons (totals, frozen core included), frozen orbitals 0..nfrozen-1 and
+ * the reference space [Pi] (ref_orbs[0..nref-1], any order, no duplicates,
+ * disjoint from the frozen set; nref may be 0).  EINVAL when a singly occupied
+ * orbital is outside [Pi] or a frozen orbital is not doubly occupied. */
+mbefci_status mbefci_set_spaces(mbefci_ctx *ctx, int32_t nalpha, int32_t nbeta, int32_t nfrozen,
+                                const int32_t *ref_orbs, int32_t nref);
+
+mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *opt);
+
+/* Device bytes needed to solve the given tuples: *min_bytes holds the
+ * largest single tuple (one at a time), *want_bytes every tuple of the largest
+ * shape class in one batch.  tuples: host int16, ntup rows of `order`
+ * ascending expansion orbitals. */
+mbefci_status mbefci_workspace_query(mbefci_ctx *ctx, int32_t order, int64_t ntup,
+                                     const int16_t *tuples, size_t *min_bytes,
+                                     size_t *want_bytes);
+
+/* CASCI energies eps(S) (Sec. 2) of `ntup` tuples of one order.  d_workspace
+ * is device memory of ws_bytes (e.g. a torch uint8 tensor) that must outlive
+ * the call; tuples are split into batches that fit it.  energies/status are
+ * host outputs of length ntup.  EINVAL for an unsorted or duplicated tuple, an
+ * orbital outside X; ENOMEM if one tuple does not fit; ENOCONV if a tuple
+ * failed (its status says why; its energy is the last Ritz value). */
+mbefci_status mbefci_solve_tuples(mbefci_ctx *ctx, int32_t order, int64_t ntup,
+                                  const int16_t *tuples, void *d_workspace, size_t ws_bytes,
+                                  double *energies, int32_t *status);
+
+/* The whole expansion (Eq. 1-3): order 0 ([Pi] alone), then orders 1.. up to
+ * max_order, |X| or until screening leaves no tuple.  *out receives a result
+ * owned by the caller (mbefci_result_free).  ENOCONV leaves *out valid. */
+mbefci_status mbefci_run(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes,
+                         mbefci_result **out);
+
+/* Host-only variant of mbefci_run: the same tuple generation, screening and
+ * increment assembly, with tuple energies supplied by `energy` (called once per
+ * order with that order's tuple list; return 0 on success).  Works on a
+ * host-only context. */
+typedef int (*mbefci_energy_fn)(void *user, int32_t order, int64_t ntup,
+                                const int16_t *tuples, double *energies);
+mbefci_status mbefci_run_host(mbefci_ctx *ctx, mbefci_energy_fn energy, void *user,
+                              mbefci_result **out);
+
+int32_t mbefci_result_norders(const mbefci_result *res);     /* orders 0..norders-1 */
+/* Views of order k (valid until mbefci_result_free): tuples [ntup*k] int16
+ * lexicographic, eps, d_eps and status [ntup], order sum E^(k), and the host
+ * wall time of the order in ms (tuple list ready -> increments assembled). */
+mbefci_status mbefci_result_order(const mbefci_result *res, int32_t k, int64_t *ntup,
+                                  const int16_t **tuples, const double **eps,
+                                  const double **dinc, const int32_t **status,
+                                  double *order_sum, double *wall_ms);
+double mbefci_result_total(const mbefci_result *res);       /* sum of the order sums */
+void mbefci_result_free(mbefci_result *res);
+
+/* sigma = H c for the CAS of one tuple (E_core and E_const included, so H is
+ * the projected full Hamiltonian), for `nvec` vectors stored one after the
+ * other (dim doubles each) at device pointers d_c / d_sigma (non-overlapping).
+ * The kernels are the ones the Davidson solver uses. */
+mbefci_status mbefci_tuple_sigma(mbefci_ctx *ctx, int32_t order, const int16_t *tuple,
+                                 void *d_workspace, size_t ws_bytes, const double *d_c,
+                                 double *d_sigma, int32_t nvec);
+
+/* Diagonal H_II (E_core included) of the CAS of one tuple into d_hdiag [dim]. */
+mbefci_status mbefci_tuple_hdiag(mbefci_ctx *ctx, int32_t order, const int16_t *tuple,
+                                 void *d_workspace, size_t ws_bytes, double *d_hdiag);
+
+/* Host query of one tuple's CAS: number of alpha and beta strings (dim is
+ * their product), active orbitals and active electrons. */
+mbefci_status mbefci_tuple_shape(mbefci_ctx *ctx, int32_t order, const int16_t *tuple,
+                                 int64_t *n_alpha_strings, int64_t *n_beta_strings,
+                                 int32_t *n_active, int32_t *n_alpha_active,
+                                 int32_t *n_beta_active);
+
+/* String and single-excitation tables of one shape (host only, no context):
+ * the C(norb_active, nel) strings as ascending bit masks, and for every string
+ * I its n_entries = nel*(norb_active-nel) + nel entries (p, q) with q in I and
+ * p not in I or p = q, encoding E_pq|I> = sign |J>: bits 0-19 = J, bits 20-29
+ * = pair index P = max(p,q)(max(p,q)+1)/2 + min(p,q), bit 31 = 1 for sign -1.
+ * Pass NULL arrays to query n_strings / n_entries only. */
+mbefci_status mbefci_string_tables(int32_t norb_active, int32_t nel, int64_t *n_strings,
+                                   int32_t *n_entries, uint32_t *strings, uint32_t *links);
+
+/* Counters of the last solve/run call. */
+mbefci_status mbefci_get_stats(const mbefci_ctx *ctx, mbefci_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBEFCI_H */

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host planner (mbefci.cpp) and the HIP
+// kernels (kernels.hip) of libmbefci.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbefci {
+
+constexpr int kMaxActive = 13;     // n_A limit: the sigma kernel stages (P x P) in LDS
+constexpr int kMaxSpace = 32;      // Davidson subspace limit
+constexpr int kTile = 64;          // determinants per sigma tile
+
+// Davidson per-tuple status codes (device side); the public codes are derived.
+enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_STALLED = 4 };
+
+inline int pair_count(int n) { return n * (n + 1) / 2; }
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Offsets (in doubles) inside one tuple's parameter block.
+struct ParamLayout {
+    int nA, P, Ppad, Kpad, ldE;
+    int off_ecore, off_k, off_hd1, off_J, off_K, off_eri, stride;
+    void init(int nA_) {
+        nA = nA_;
+        P = pair_count(nA);
+        Ppad = round_up(P > 0 ? P : 1, 16);
+        Kpad = round_up(P > 0 ? P : 1, 4);
+        ldE = Kpad + 1;                       // odd row stride against LDS bank conflicts
+        off_ecore = 0;
+        off_k = 1;
+        off_hd1 = off_k + P;
+        off_J = off_hd1 + nA;
+        off_K = off_J + nA * nA;
+        off_eri = round_up(off_K + nA * nA, 2);
+        stride = round_up(off_eri + Ppad * Kpad, 32);
+    }
+};
+
+// A reference to one vector per tuple: base + t*tstride + idx[t]*dim (idx may
+// be null, then idx_const is used).
+struct VecRef {
+    double *base;
+    int64_t tstride;
+    const int32_t *idx;
+    int32_t idx_const;
+};
+
+// Everything the kernels of one batch need (device pointers).
+struct Batch {
+    int B;                  // tuples in the batch
+    int nA, na, nb, nC;     // active orbitals, active electrons, core orbitals
+    int64_t Na, Nb, dim;    // strings and determinants
+    int nentA, nentB;       // link entries per string
+    ParamLayout pl;
+    int norb;
+    double e_const;
+    const double *h, *eri;  // resident integrals (n^2, n^4)
+    const uint32_t *strA, *strB, *linkA, *linkB;
+    const int32_t *act;     // [B * nA] active orbitals (ascending)
+    const int32_t *core;    // [B * nC] core orbitals
+    double *params;         // [B * pl.stride]
+    // Davidson state
+    int max_space, max_iter;
+    double e_tol, r_tol;
+    double *V, *S;          // [B][max_space][dim]
+    double *Hd, *T;         // [B][dim]
+    double *W;              // [B][P][dim] sigma intermediate
+    int nblk;               // blocks per tuple for vector kernels
+    double *part;           // [B][nblk][kMaxSpace + 1] block partial sums
+    double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix
+    double *y, *coef;       // [B][kMaxSpace]
+    double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
+    int32_t *status, *m, *iter, *restart, *out_status; // [B]
+    int32_t *counter;       // [1] running tuples
+};
+
+// kernels.hip
+hipError_t init_kernels();
+hipError_t launch_gather(const Batch &b, hipStream_t s);
+hipError_t launch_hdiag(const Batch &b, double *out, int64_t ostride, int add_ecore, hipStream_t s);
+hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done,
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2);
+hipError_t launch_guess(const Batch &b, hipStream_t s);
+hipError_t launch_init_state(const Batch &b, hipStream_t s);
+hipError_t launch_dots(const Batch &b, VecRef y, int nx_extra, hipStream_t s);
+hipError_t launch_iter_head(const Batch &b, hipStream_t s);
+hipError_t launch_orthonormalize(const Batch &b, hipStream_t s);
+hipError_t launch_finalize(const Batch &b, hipStream_t s);
+size_t sigma_lds_bytes(const ParamLayout &pl);
+
+}  // namespace mbefci

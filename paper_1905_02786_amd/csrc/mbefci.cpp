@@ -1,0 +1,902 @@
+// Host side of libmbefci.so: context, validation, string tables, the MBE
+// planner (tuple generation, screening, increment assembly; Eq. 1-3) and the
+// batch driver of the Davidson solver whose kernels live in kernels.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mbefci.h"
+#include "internal.h"
+
+using namespace mbefci;
+
+namespace {
+
+struct Tables {
+    int nA = 0, nel = 0, nent = 0;
+    int64_t nstr = 0;
+    std::vector<uint32_t> strings;   // ascending bit masks
+    std::vector<uint32_t> links;     // [nstr][nent]
+};
+
+// Strings with `nel` of `nA` bits set, ascending; for each string I the
+// entries (p, q) with q in I and (p not in I or p == q): diagonal entries
+// first (p ascending), then q ascending, p ascending.  E_pq|I> = sign |J> with
+// sign = (-1)^(number of occupied orbitals strictly between p and q).
+void build_tables(int nA, int nel, Tables &T) {
+    T.nA = nA;
+    T.nel = nel;
+    T.nent = nel * (nA - nel) + nel;
+    std::vector<int32_t> rank((size_t)1 << nA, -1);
+    T.strings.clear();
+    for (uint32_t m = 0; m < (1u << nA); ++m)
+        if (__builtin_popcount(m) == nel) {
+            rank[m] = (int32_t)T.strings.size();
+            T.strings.push_back(m);
+        }
+    T.nstr = (int64_t)T.strings.size();
+    T.links.assign((size_t)T.nstr * T.nent, 0);
+    for (int64_t I = 0; I < T.nstr; ++I) {
+        const uint32_t m = T.strings[I];
+        uint32_t *out = &T.links[(size_t)I * T.nent];
+        int e = 0;
+        for (int p = 0; p < nA; ++p)
+            if (m >> p & 1u) out[e++] = (uint32_t)I | ((uint32_t)(p * (p + 1) / 2 + p) << 20);
+        for (int q = 0; q < nA; ++q) {
+            if (!(m >> q & 1u)) continue;
+            for (int p = 0; p < nA; ++p) {
+                if (m >> p & 1u) continue;
+                const uint32_t J = (m & ~(1u << q)) | (1u << p);
+                const int lo = std::min(p, q), hi = std::max(p, q);
+                const uint32_t between = m & (((1u << hi) - 1u) & ~((1u << (lo + 1)) - 1u));
+                const uint32_t neg = (uint32_t)(__builtin_popcount(between) & 1);
+                const int P = hi * (hi + 1) / 2 + lo;
+                out[e++] = (uint32_t)rank[J] | ((uint32_t)P << 20) | (neg << 31);
+            }
+        }
+    }
+}
+
+struct ClassKey {
+    int nA, na, nb;
+    bool operator<(const ClassKey &o) const {
+        if (nA != o.nA) return nA < o.nA;
+        if (na != o.na) return na < o.na;
+        return nb < o.nb;
+    }
+};
+
+struct Result {
+    struct Order {
+        int k;
+        std::vector<int16_t> tuples;
+        std::vector<double> eps, dinc;
+        std::vector<int32_t> status;
+        double sum = 0.0, wall_ms = 0.0;
+    };
+    std::vector<Order> orders;
+    double total = 0.0;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct mbefci_result {
+    Result r;
+};
+
+struct mbefci_ctx {
+    int device = -1;
+    bool host_only = true;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::string err;
+    // Hamiltonian
+    int norb = 0;
+    bool ham_set = false;
+    std::vector<double> h, eri;
+    double e_const = 0.0;
+    double *d_h = nullptr, *d_eri = nullptr;
+    // spaces
+    bool spaces_set = false;
+    int nalpha = 0, nbeta = 0, nfrozen = 0;
+    std::vector<int> ref, X;
+    std::vector<char> inX;
+    mbefci_options opt{};
+    mbefci_stats stats{};
+    bool sigma_pending = false;   // profile: events of the last sigma not read yet
+    std::map<std::pair<int, int>, Tables> tables;
+
+    mbefci_status fail(mbefci_status s, const std::string &m) {
+        err = m;
+        return s;
+    }
+    const Tables &table(int nA, int nel) {
+        auto key = std::make_pair(nA, nel);
+        auto it = tables.find(key);
+        if (it != tables.end()) return it->second;
+        Tables &T = tables[key];
+        build_tables(nA, nel, T);
+        return T;
+    }
+};
+
+#define HIPCHK(x)                                                                     \
+    do {                                                                              \
+        hipError_t e_ = (x);                                                          \
+        if (e_ != hipSuccess)                                                         \
+            return ctx->fail(MBEFCI_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+// Shape of one tuple's CAS (Sec. 2 partition).
+struct TupleShape {
+    ClassKey key;
+    int nC;
+    std::vector<int32_t> act, core;
+};
+
+mbefci_status tuple_shape(mbefci_ctx *ctx, int order, const int16_t *tup, TupleShape &ts) {
+    for (int i = 0; i < order; ++i) {
+        const int p = tup[i];
+        if (p < 0 || p >= ctx->norb || !ctx->inX[p])
+            return ctx->fail(MBEFCI_EINVAL, "tuple orbital " + std::to_string(p) + " is not an expansion orbital");
+        if (i > 0 && tup[i - 1] >= p) return ctx->fail(MBEFCI_EINVAL, "tuple not strictly ascending");
+    }
+    ts.act.clear();
+    std::vector<char> inA(ctx->norb, 0);
+    for (int p : ctx->ref) inA[p] = 1;
+    for (int i = 0; i < order; ++i) inA[tup[i]] = 1;
+    for (int p = 0; p < ctx->norb; ++p)
+        if (inA[p]) ts.act.push_back(p);
+    ts.core.clear();
+    for (int p = 0; p < ctx->nbeta; ++p)
+        if (!inA[p]) ts.core.push_back(p);   // frozen orbitals are < nbeta and never active
+    int na = 0, nb = 0;
+    for (int p : ts.act) {
+        na += p < ctx->nalpha;
+        nb += p < ctx->nbeta;
+    }
+    ts.key = ClassKey{(int)ts.act.size(), na, nb};
+    ts.nC = (int)ts.core.size();
+    if (ts.key.nA > kMaxActive)
+        return ctx->fail(MBEFCI_ETOOLARGE, "CAS with " + std::to_string(ts.key.nA) + " active orbitals exceeds " +
+                                               std::to_string(kMaxActive));
+    return MBEFCI_OK;
+}
+
+int nblk_for(int64_t dim) {
+    int64_t g = (dim + 1023) / 1024;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(256, g));
+}
+
+struct ClassPlan {
+    ClassKey key;
+    int nC;
+    const Tables *ta, *tb;
+    int64_t dim;
+    ParamLayout pl;
+    int nblk;
+    size_t fixed_bytes, per_tuple;
+};
+
+void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, bool davidson) {
+    cp.key = key;
+    cp.nC = nC;
+    cp.ta = &ctx->table(key.nA, key.na);
+    cp.tb = &ctx->table(key.nA, key.nb);
+    cp.dim = cp.ta->nstr * cp.tb->nstr;
+    cp.pl.init(key.nA);
+    cp.nblk = nblk_for(cp.dim);
+    cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
+                     align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
+                     align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) + 64 * 256;
+    const int ms = davidson ? ctx->opt.max_space : 0;
+    size_t pt = 0;
+    pt += 8 * (size_t)cp.pl.stride;                          // params
+    pt += 4 * (size_t)(key.nA + nC + 2);                      // act, core
+    pt += 8 * (size_t)cp.dim * (2 * ms + (davidson ? 2 : 0)); // V, S, Hd, T
+    pt += 8 * (size_t)cp.pl.P * cp.dim;                      // W
+    pt += 8 * (size_t)cp.nblk * (kMaxSpace + 1);             // partials
+    pt += 8 * (size_t)(kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 6;
+    cp.per_tuple = pt + 256;
+}
+
+// Bump allocator over the caller's workspace.
+struct Carver {
+    char *base;
+    size_t size, off = 0;
+    bool ok = true;
+    template <class T> T *take(size_t count) {
+        size_t bytes = align256(count * sizeof(T));
+        if (off + bytes > size) {
+            ok = false;
+            return nullptr;
+        }
+        T *p = reinterpret_cast<T *>(base + off);
+        off += bytes;
+        return p;
+    }
+};
+
+// Fill the table and batch pointers; returns false if it does not fit.
+bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch &b, bool davidson) {
+    b = Batch{};
+    b.B = B;
+    b.nA = cp.key.nA;
+    b.na = cp.key.na;
+    b.nb = cp.key.nb;
+    b.nC = cp.nC;
+    b.Na = cp.ta->nstr;
+    b.Nb = cp.tb->nstr;
+    b.dim = cp.dim;
+    b.nentA = cp.ta->nent;
+    b.nentB = cp.tb->nent;
+    b.pl = cp.pl;
+    b.norb = ctx->norb;
+    b.e_const = ctx->e_const;
+    b.h = ctx->d_h;
+    b.eri = ctx->d_eri;
+    b.strA = cv.take<uint32_t>(b.Na);
+    b.strB = cv.take<uint32_t>(b.Nb);
+    b.linkA = cv.take<uint32_t>((size_t)b.Na * b.nentA);
+    b.linkB = cv.take<uint32_t>((size_t)b.Nb * b.nentB);
+    b.act = cv.take<int32_t>((size_t)B * b.nA + 1);
+    b.core = cv.take<int32_t>((size_t)B * b.nC + 1);
+    b.params = cv.take<double>((size_t)B * cp.pl.stride);
+    b.max_space = davidson ? ctx->opt.max_space : 0;
+    b.max_iter = ctx->opt.max_iter;
+    b.e_tol = ctx->opt.e_tol;
+    b.r_tol = ctx->opt.r_tol;
+    if (davidson) {
+        b.V = cv.take<double>((size_t)B * b.max_space * b.dim);
+        b.S = cv.take<double>((size_t)B * b.max_space * b.dim);
+        b.Hd = cv.take<double>((size_t)B * b.dim);
+        b.T = cv.take<double>((size_t)B * b.dim);
+    }
+    b.W = cv.take<double>((size_t)B * cp.pl.P * b.dim + 1);
+    b.nblk = cp.nblk;
+    b.part = cv.take<double>((size_t)B * b.nblk * (kMaxSpace + 1));
+    b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
+    b.y = cv.take<double>((size_t)B * kMaxSpace);
+    b.coef = cv.take<double>((size_t)B * kMaxSpace);
+    b.theta = cv.take<double>(B);
+    b.theta_prev = cv.take<double>(B);
+    b.rnorm = cv.take<double>(B);
+    b.tnorm0 = cv.take<double>(B);
+    b.out_e = cv.take<double>(B);
+    b.status = cv.take<int32_t>(B);
+    b.m = cv.take<int32_t>(B);
+    b.iter = cv.take<int32_t>(B);
+    b.restart = cv.take<int32_t>(B);
+    b.out_status = cv.take<int32_t>(B);
+    b.counter = cv.take<int32_t>(1);
+    return cv.ok;
+}
+
+mbefci_status upload_tables(mbefci_ctx *ctx, const ClassPlan &cp, const Batch &b) {
+    HIPCHK(hipMemcpyAsync((void *)b.strA, cp.ta->strings.data(), 4 * b.Na, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync((void *)b.strB, cp.tb->strings.data(), 4 * b.Nb, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync((void *)b.linkA, cp.ta->links.data(), 4 * (size_t)b.Na * b.nentA, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync((void *)b.linkB, cp.tb->links.data(), 4 * (size_t)b.Nb * b.nentB, hipMemcpyHostToDevice,
+                          ctx->stream));
+    return MBEFCI_OK;
+}
+
+mbefci_status upload_shapes(mbefci_ctx *ctx, const Batch &b, const std::vector<const TupleShape *> &shapes) {
+    std::vector<int32_t> act((size_t)b.B * b.nA + 1, 0), core((size_t)b.B * b.nC + 1, 0);
+    for (int t = 0; t < b.B; ++t) {
+        std::copy(shapes[t]->act.begin(), shapes[t]->act.end(), act.begin() + (size_t)t * b.nA);
+        std::copy(shapes[t]->core.begin(), shapes[t]->core.end(), core.begin() + (size_t)t * b.nC);
+    }
+    HIPCHK(hipMemcpyAsync((void *)b.act, act.data(), 4 * act.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync((void *)b.core, core.data(), 4 * core.size(), hipMemcpyHostToDevice, ctx->stream));
+    return MBEFCI_OK;
+}
+
+double sigma_flops(const Batch &b) { return 2.0 * (double)b.pl.P * b.pl.P * (double)b.dim; }
+double sigma_bytes(const Batch &b) { return 16.0 * (double)b.dim + 8.0 * (double)b.pl.P * b.pl.P; }
+
+// Accumulate the HIP-event time of the last sigma launch pair (profile mode).
+// Called only after a stream synchronisation, so the events are complete.
+void flush_sigma_time(mbefci_ctx *ctx) {
+    if (!ctx->sigma_pending) return;
+    ctx->sigma_pending = false;
+    float ms_w = 0.f, ms_all = 0.f;
+    if (hipEventElapsedTime(&ms_w, ctx->ev[0], ctx->ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&ms_all, ctx->ev[0], ctx->ev[2]) == hipSuccess) {
+        ctx->stats.sigma_ms += ms_w;
+        ctx->stats.sigma_total_ms += ms_all;
+    }
+}
+
+mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, double shift, bool skip_done,
+                        int64_t napps) {
+    const bool prof = ctx->opt.profile != 0;
+    if (prof && ctx->sigma_pending) {   // a sigma whose events were not read yet
+        HIPCHK(hipEventSynchronize(ctx->ev[2]));
+        flush_sigma_time(ctx);
+    }
+    hipError_t e = launch_sigma(b, c, s, shift, skip_done, ctx->stream, prof ? ctx->ev[0] : nullptr,
+                                prof ? ctx->ev[1] : nullptr, prof ? ctx->ev[2] : nullptr);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, std::string("sigma launch: ") + hipGetErrorString(e));
+    ctx->stats.sigma_launches += 1;
+    ctx->stats.sigma_calls += napps;
+    ctx->stats.sigma_flops += napps * sigma_flops(b);
+    ctx->stats.sigma_bytes += napps * sigma_bytes(b);
+    ctx->sigma_pending = prof;
+    return MBEFCI_OK;
+}
+
+// Davidson for one batch; energies/status (public codes) written at out[t].
+mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out) {
+    hipStream_t s = ctx->stream;
+    hipError_t e;
+    if ((e = launch_gather(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    if ((e = launch_hdiag(b, b.Hd, b.dim, 0, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    if ((e = launch_init_state(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    if ((e = launch_guess(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    const int64_t tstride = (int64_t)b.max_space * b.dim;
+    VecRef vm{b.V, tstride, b.m, 0}, sm{b.S, tstride, b.m, 0};
+    mbefci_status rc = run_sigma(ctx, b, vm, sm, 0.0, true, b.B);
+    if (rc != MBEFCI_OK) return rc;
+    if ((e = launch_dots(b, sm, 1, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    int32_t running = b.B;
+    int iters = 0;
+    for (int it = 0; it <= b.max_iter; ++it) {
+        HIPCHK(hipMemsetAsync(b.counter, 0, sizeof(int32_t), s));
+        if ((e = launch_iter_head(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        HIPCHK(hipMemcpyAsync(&running, b.counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        flush_sigma_time(ctx);
+        ++iters;
+        if (running == 0) break;
+        if ((e = launch_orthonormalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        rc = run_sigma(ctx, b, vm, sm, 0.0, true, running);
+        if (rc != MBEFCI_OK) return rc;
+        if ((e = launch_dots(b, sm, 1, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    }
+    if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    std::vector<int32_t> dst(b.B), dit(b.B);
+    HIPCHK(hipMemcpyAsync(e_out, b.out_e, 8 * (size_t)b.B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dst.data(), b.out_status, 4 * (size_t)b.B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dit.data(), b.iter, 4 * (size_t)b.B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    flush_sigma_time(ctx);
+    for (int t = 0; t < b.B; ++t) {
+        const int32_t d = dst[t];
+        st_out[t] = d == ST_DONE ? MBEFCI_TUPLE_OK
+                    : d == ST_MAXITER ? MBEFCI_TUPLE_MAXITER
+                    : d == ST_NONFINITE ? MBEFCI_TUPLE_NONFINITE
+                    : d == ST_STALLED ? MBEFCI_TUPLE_STALLED : MBEFCI_TUPLE_MAXITER;
+        ctx->stats.iterations_total += dit[t];
+        ctx->stats.iterations_max = std::max<int64_t>(ctx->stats.iterations_max, dit[t]);
+    }
+    (void)iters;
+    return MBEFCI_OK;
+}
+
+mbefci_status check_device(mbefci_ctx *ctx) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (ctx->host_only) return ctx->fail(MBEFCI_ESTATE, "host-only context");
+    if (!ctx->ham_set) return ctx->fail(MBEFCI_ESTATE, "no Hamiltonian set");
+    if (!ctx->spaces_set) return ctx->fail(MBEFCI_ESTATE, "no spaces set");
+    HIPCHK(hipSetDevice(ctx->device));
+    return MBEFCI_OK;
+}
+
+// Solve a list of tuples (device).  Groups by shape class, batches within
+// the workspace, writes energies/status in input order.
+mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16_t *tuples, void *ws, size_t wsb,
+                           double *energies, int32_t *status) {
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    if (ntup < 0 || (ntup > 0 && order > 0 && !tuples)) return ctx->fail(MBEFCI_EINVAL, "bad tuple list");
+    if (!ws) return ctx->fail(MBEFCI_EINVAL, "null workspace");
+    std::vector<TupleShape> shapes(ntup);
+    std::map<std::pair<ClassKey, int>, std::vector<int64_t>> groups;
+    for (int64_t i = 0; i < ntup; ++i) {
+        rc = tuple_shape(ctx, order, tuples + (size_t)i * order, shapes[i]);
+        if (rc != MBEFCI_OK) return rc;
+        groups[{shapes[i].key, shapes[i].nC}].push_back(i);
+    }
+    bool failed = false;
+    for (auto &g : groups) {
+        ClassPlan cp;
+        plan_class(ctx, g.first.first, g.first.second, cp, true);
+        if (cp.fixed_bytes + cp.per_tuple > wsb)
+            return ctx->fail(MBEFCI_ENOMEM, "workspace of " + std::to_string(wsb) + " bytes cannot hold one tuple (" +
+                                                std::to_string(cp.fixed_bytes + cp.per_tuple) + " needed)");
+        int64_t Bmax = ctx->opt.batched ? (int64_t)((wsb - cp.fixed_bytes) / cp.per_tuple) : 1;
+        Bmax = std::max<int64_t>(1, std::min<int64_t>(Bmax, 65535));
+        const std::vector<int64_t> &idx = g.second;
+        for (size_t start = 0; start < idx.size(); start += Bmax) {
+            const int B = (int)std::min<size_t>(Bmax, idx.size() - start);
+            Carver cv{(char *)ws, wsb};
+            Batch b;
+            if (!carve_batch(ctx, cp, B, cv, b, true)) return ctx->fail(MBEFCI_ENOMEM, "workspace carve failed");
+            if ((rc = upload_tables(ctx, cp, b)) != MBEFCI_OK) return rc;
+            std::vector<const TupleShape *> sh(B);
+            for (int t = 0; t < B; ++t) sh[t] = &shapes[idx[start + t]];
+            if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) return rc;
+            std::vector<double> e(B);
+            std::vector<int32_t> st(B);
+            if ((rc = davidson_batch(ctx, b, e.data(), st.data())) != MBEFCI_OK) return rc;
+            for (int t = 0; t < B; ++t) {
+                energies[idx[start + t]] = e[t];
+                status[idx[start + t]] = st[t];
+                failed |= st[t] != MBEFCI_TUPLE_OK;
+            }
+        }
+    }
+    ctx->stats.ntuples += ntup;
+    return failed ? ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge") : MBEFCI_OK;
+}
+
+// ----------------------------------------------------------------- planner --
+
+// all k-combinations of X in lexicographic order
+void combinations(const std::vector<int> &X, int k, std::vector<int16_t> &out) {
+    out.clear();
+    const int n = (int)X.size();
+    if (k > n) return;
+    std::vector<int> ix(k);
+    for (int i = 0; i < k; ++i) ix[i] = i;
+    while (true) {
+        for (int i = 0; i < k; ++i) out.push_back((int16_t)X[ix[i]]);
+        int i = k - 1;
+        while (i >= 0 && ix[i] == n - k + i) --i;
+        if (i < 0) break;
+        ++ix[i];
+        for (int j = i + 1; j < k; ++j) ix[j] = ix[j - 1] + 1;
+    }
+}
+
+uint64_t tuple_mask(const int16_t *t, int k) {
+    uint64_t m = 0;
+    for (int i = 0; i < k; ++i) m |= (uint64_t)1 << t[i];
+    return m;
+}
+
+double screen_threshold(double a, int k) { return 1.0e-10 * std::pow(a, (double)(k - 1)); }
+
+// Children of the order-(k-1) tuples with |d_eps| >= tau: every T u {x},
+// x in X \ T, deduplicated, lexicographic.
+void children(const Result::Order &prev, const std::vector<int> &X, double tau, std::vector<int16_t> &out) {
+    const int kp = prev.k, k = kp + 1;
+    const int64_t np = (int64_t)prev.dinc.size();
+    std::vector<uint64_t> masks;
+    for (int64_t i = 0; i < np; ++i) {
+        if (!(std::fabs(prev.dinc[i]) >= tau)) continue;
+        const int16_t *T = prev.tuples.data() + (size_t)i * kp;
+        const uint64_t mT = tuple_mask(T, kp);
+        for (int x : X)
+            if (!(mT >> x & 1)) masks.push_back(mT | ((uint64_t)1 << x));
+    }
+    std::sort(masks.begin(), masks.end());
+    masks.erase(std::unique(masks.begin(), masks.end()), masks.end());
+    std::vector<int16_t> rows(masks.size() * k);
+    for (size_t i = 0; i < masks.size(); ++i) {
+        int j = 0;
+        for (uint64_t m = masks[i]; m; m &= m - 1) rows[i * k + j++] = (int16_t)__builtin_ctzll(m);
+    }
+    std::vector<size_t> ord(masks.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+        return std::lexicographical_compare(rows.begin() + a * k, rows.begin() + (a + 1) * k, rows.begin() + b * k,
+                                            rows.begin() + (b + 1) * k);
+    });
+    out.resize(rows.size());
+    for (size_t i = 0; i < ord.size(); ++i) std::copy(rows.begin() + ord[i] * k, rows.begin() + (ord[i] + 1) * k,
+                                                      out.begin() + i * k);
+}
+
+// Eq. 3 for one tuple: subtuples in (size, lexicographic) order from 0.0.
+double increment(const int16_t *S, int k, double eps, const std::unordered_map<uint64_t, double> &dinc) {
+    double acc = 0.0;
+    std::vector<int> ix(k);
+    for (int m = 0; m < k; ++m) {
+        for (int i = 0; i < m; ++i) ix[i] = i;
+        while (true) {
+            uint64_t mask = 0;
+            for (int i = 0; i < m; ++i) mask |= (uint64_t)1 << S[ix[i]];
+            auto it = dinc.find(mask);
+            if (it != dinc.end()) acc += it->second;
+            int i = m - 1;
+            while (i >= 0 && ix[i] == k - m + i) --i;
+            if (i < 0) break;
+            ++ix[i];
+            for (int j = i + 1; j < m; ++j) ix[j] = ix[j - 1] + 1;
+        }
+    }
+    return eps - acc;
+}
+
+template <class EnergyFn>
+mbefci_status run_planner(mbefci_ctx *ctx, EnergyFn energy, Result &R) {
+    const int nX = (int)ctx->X.size();
+    int kmax = ctx->opt.max_order > 0 ? std::min(ctx->opt.max_order, nX) : nX;
+    std::unordered_map<uint64_t, double> dinc;
+    bool failed = false;
+    R.orders.clear();
+    R.total = 0.0;
+    for (int k = 0; k <= kmax; ++k) {
+        Result::Order o;
+        o.k = k;
+        if (k == 0) {
+            o.tuples.clear();
+        } else if (k == 1 || ctx->opt.a <= 0.0) {
+            combinations(ctx->X, k, o.tuples);
+        } else {
+            children(R.orders.back(), ctx->X, screen_threshold(ctx->opt.a, k - 1), o.tuples);
+        }
+        const int64_t nt = k == 0 ? 1 : (int64_t)(o.tuples.size() / k);
+        if (nt == 0) break;
+        const double t0 = now_ms();
+        o.eps.assign(nt, 0.0);
+        o.status.assign(nt, 0);
+        mbefci_status rc = energy(k, nt, o.tuples.data(), o.eps.data(), o.status.data());
+        if (rc == MBEFCI_ENOCONV) failed = true;
+        else if (rc != MBEFCI_OK) return rc;
+        o.dinc.resize(nt);
+        for (int64_t i = 0; i < nt; ++i) o.dinc[i] = increment(o.tuples.data() + (size_t)i * k, k, o.eps[i], dinc);
+        for (int64_t i = 0; i < nt; ++i) dinc[tuple_mask(o.tuples.data() + (size_t)i * k, k)] = o.dinc[i];
+        double s = 0.0;
+        for (double d : o.dinc) s += d;
+        o.sum = s;
+        o.wall_ms = now_ms() - t0;
+        R.orders.push_back(std::move(o));
+    }
+    double tot = 0.0;
+    for (auto &o : R.orders) tot += o.sum;
+    R.total = tot;
+    return failed ? ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge") : MBEFCI_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char *mbefci_version(void) { return "mbefci 0.1 (gfx950, FP64)"; }
+
+void mbefci_default_options(mbefci_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->a = 0.0;
+    o->max_order = 0;
+    o->e_tol = 1e-11;
+    o->r_tol = 1e-6;
+    o->max_iter = 200;
+    o->max_space = 12;
+    o->batched = 1;
+    o->keep_vectors = 0;
+    o->profile = 0;
+}
+
+mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
+    if (!out) return MBEFCI_EINVAL;
+    *out = nullptr;
+    auto ctx = std::make_unique<mbefci_ctx>();
+    mbefci_default_options(&ctx->opt);
+    if (dev >= 0) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || dev >= n) return MBEFCI_EDEVICE;
+        if (hipSetDevice(dev) != hipSuccess) return MBEFCI_EDEVICE;
+        ctx->device = dev;
+        ctx->host_only = false;
+        ctx->stream = (hipStream_t)stream;
+        for (auto &e : ctx->ev)
+            if (hipEventCreate(&e) != hipSuccess) return MBEFCI_EDEVICE;
+        if (init_kernels() != hipSuccess) return MBEFCI_EDEVICE;
+    }
+    *out = ctx.release();
+    return MBEFCI_OK;
+}
+
+void mbefci_destroy(mbefci_ctx *ctx) {
+    if (!ctx) return;
+    if (!ctx->host_only) {
+        (void)hipSetDevice(ctx->device);
+        if (ctx->d_h) (void)hipFree(ctx->d_h);
+        if (ctx->d_eri) (void)hipFree(ctx->d_eri);
+        for (auto e : ctx->ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+}
+
+const char *mbefci_last_error(const mbefci_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mbefci_status mbefci_set_hamiltonian(mbefci_ctx *ctx, int32_t n, const double *h1, const double *eri,
+                                     mbefci_eri_layout layout, double e_const) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (n < 1 || n > 64) return ctx->fail(MBEFCI_EINVAL, "norb must be in 1..64");
+    if (!h1 || !eri) return ctx->fail(MBEFCI_EINVAL, "null integrals");
+    if (!std::isfinite(e_const)) return ctx->fail(MBEFCI_EINVAL, "non-finite constant");
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) {
+            const double a = h1[p * n + q], b = h1[q * n + p];
+            if (!std::isfinite(a)) return ctx->fail(MBEFCI_EINVAL, "non-finite h1");
+            if (std::fabs(a - b) > 1e-12) return ctx->fail(MBEFCI_EINVAL, "h1 not symmetric");
+        }
+    std::vector<double> full(n4);
+    if (layout == MBEFCI_ERI_FULL) {
+        std::memcpy(full.data(), eri, n4 * sizeof(double));
+    } else if (layout == MBEFCI_ERI_PACKED8) {
+        auto pr = [](int p, int q) { return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p; };
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q)
+                for (int r = 0; r < n; ++r)
+                    for (int s = 0; s < n; ++s) {
+                        const size_t P = pr(p, q), R = pr(r, s);
+                        const size_t k = P >= R ? P * (P + 1) / 2 + R : R * (R + 1) / 2 + P;
+                        full[((size_t)(p * n + q) * n + r) * n + s] = eri[k];
+                    }
+    } else {
+        return ctx->fail(MBEFCI_EINVAL, "unknown eri layout");
+    }
+    for (double v : full)
+        if (!std::isfinite(v)) return ctx->fail(MBEFCI_EINVAL, "non-finite eri");
+    ctx->norb = n;
+    ctx->h.assign(h1, h1 + n2);
+    ctx->eri.swap(full);
+    ctx->e_const = e_const;
+    ctx->ham_set = true;
+    if (!ctx->host_only) {
+        HIPCHK(hipSetDevice(ctx->device));
+        if (ctx->d_h) (void)hipFree(ctx->d_h);
+        if (ctx->d_eri) (void)hipFree(ctx->d_eri);
+        ctx->d_h = ctx->d_eri = nullptr;
+        HIPCHK(hipMalloc((void **)&ctx->d_h, n2 * sizeof(double)));
+        HIPCHK(hipMalloc((void **)&ctx->d_eri, n4 * sizeof(double)));
+        HIPCHK(hipMemcpy(ctx->d_h, ctx->h.data(), n2 * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ctx->d_eri, ctx->eri.data(), n4 * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (ctx->spaces_set && (int)ctx->inX.size() != n) ctx->spaces_set = false;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_set_spaces(mbefci_ctx *ctx, int32_t nalpha, int32_t nbeta, int32_t nfrozen,
+                                const int32_t *ref, int32_t nref) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (!ctx->ham_set) return ctx->fail(MBEFCI_ESTATE, "set the Hamiltonian first");
+    const int n = ctx->norb;
+    if (nbeta < 0 || nalpha < nbeta || nalpha > n) return ctx->fail(MBEFCI_EINVAL, "need 0 <= nbeta <= nalpha <= norb");
+    if (nfrozen < 0 || nfrozen > nbeta) return ctx->fail(MBEFCI_EINVAL, "frozen orbitals must be doubly occupied");
+    if (nref < 0 || (nref > 0 && !ref)) return ctx->fail(MBEFCI_EINVAL, "bad reference space");
+    std::vector<char> inref(n, 0);
+    for (int i = 0; i < nref; ++i) {
+        const int p = ref[i];
+        if (p < 0 || p >= n) return ctx->fail(MBEFCI_EINVAL, "reference orbital out of range");
+        if (p < nfrozen) return ctx->fail(MBEFCI_EINVAL, "reference orbital is frozen");
+        if (inref[p]) return ctx->fail(MBEFCI_EINVAL, "duplicate reference orbital");
+        inref[p] = 1;
+    }
+    for (int p = nbeta; p < nalpha; ++p)
+        if (!inref[p]) return ctx->fail(MBEFCI_EINVAL, "singly occupied orbitals must lie in the reference space");
+    ctx->nalpha = nalpha;
+    ctx->nbeta = nbeta;
+    ctx->nfrozen = nfrozen;
+    ctx->ref.clear();
+    for (int p = 0; p < n; ++p)
+        if (inref[p]) ctx->ref.push_back(p);
+    ctx->X.clear();
+    ctx->inX.assign(n, 0);
+    for (int p = nfrozen; p < n; ++p)
+        if (!inref[p]) {
+            ctx->X.push_back(p);
+            ctx->inX[p] = 1;
+        }
+    if ((int)ctx->ref.size() > kMaxActive)
+        return ctx->fail(MBEFCI_ETOOLARGE, "reference space exceeds the active-orbital limit");
+    ctx->spaces_set = true;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
+    if (!ctx || !o) return MBEFCI_EINVAL;
+    if (!std::isfinite(o->a)) return ctx->fail(MBEFCI_EINVAL, "non-finite a");
+    if (o->max_space < 2 || o->max_space > kMaxSpace) return ctx->fail(MBEFCI_EINVAL, "max_space must be in 2..32");
+    if (o->max_iter < 1) return ctx->fail(MBEFCI_EINVAL, "max_iter must be >= 1");
+    if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
+    ctx->opt = *o;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_workspace_query(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples,
+                                     size_t *min_bytes, size_t *want_bytes) {
+    if (!ctx || !min_bytes || !want_bytes) return MBEFCI_EINVAL;
+    if (!ctx->spaces_set) return ctx->fail(MBEFCI_ESTATE, "no spaces set");
+    std::map<std::pair<ClassKey, int>, int64_t> count;
+    for (int64_t i = 0; i < ntup; ++i) {
+        TupleShape ts;
+        mbefci_status rc = tuple_shape(ctx, order, tuples + (size_t)i * order, ts);
+        if (rc != MBEFCI_OK) return rc;
+        count[{ts.key, ts.nC}]++;
+    }
+    size_t mn = 0, wt = 0;
+    for (auto &c : count) {
+        ClassPlan cp;
+        plan_class(ctx, c.first.first, c.first.second, cp, true);
+        mn = std::max(mn, cp.fixed_bytes + cp.per_tuple);
+        wt = std::max(wt, cp.fixed_bytes + cp.per_tuple * (size_t)c.second);
+    }
+    *min_bytes = mn;
+    *want_bytes = wt;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_solve_tuples(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples, void *ws,
+                                  size_t wsb, double *energies, int32_t *status) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (!energies || !status || order < 0) return ctx->fail(MBEFCI_EINVAL, "null output");
+    ctx->stats = mbefci_stats{};
+    const double t0 = now_ms();
+    mbefci_status rc = solve_device(ctx, order, ntup, tuples, ws, wsb, energies, status);
+    ctx->stats.solve_ms = now_ms() - t0;
+    return rc;
+}
+
+mbefci_status mbefci_run(mbefci_ctx *ctx, void *ws, size_t wsb, mbefci_result **out) {
+    if (!ctx || !out) return MBEFCI_EINVAL;
+    *out = nullptr;
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    ctx->stats = mbefci_stats{};
+    const double t0 = now_ms();
+    auto res = std::make_unique<mbefci_result>();
+    rc = run_planner(ctx,
+                     [&](int k, int64_t nt, const int16_t *tup, double *e, int32_t *st) {
+                         return solve_device(ctx, k, nt, tup, ws, wsb, e, st);
+                     },
+                     res->r);
+    ctx->stats.solve_ms = now_ms() - t0;
+    if (rc == MBEFCI_OK || rc == MBEFCI_ENOCONV) *out = res.release();
+    return rc;
+}
+
+mbefci_status mbefci_run_host(mbefci_ctx *ctx, mbefci_energy_fn fn, void *user, mbefci_result **out) {
+    if (!ctx || !fn || !out) return MBEFCI_EINVAL;
+    *out = nullptr;
+    if (!ctx->spaces_set) return ctx->fail(MBEFCI_ESTATE, "no spaces set");
+    auto res = std::make_unique<mbefci_result>();
+    mbefci_status rc = run_planner(ctx,
+                                   [&](int k, int64_t nt, const int16_t *tup, double *e, int32_t *st) {
+                                       for (int64_t i = 0; i < nt; ++i) st[i] = 0;
+                                       if (fn(user, k, nt, tup, e) != 0)
+                                           return ctx->fail(MBEFCI_EINVAL, "energy callback failed");
+                                       return MBEFCI_OK;
+                                   },
+                                   res->r);
+    if (rc == MBEFCI_OK) *out = res.release();
+    return rc;
+}
+
+int32_t mbefci_result_norders(const mbefci_result *res) { return res ? (int32_t)res->r.orders.size() : 0; }
+
+mbefci_status mbefci_result_order(const mbefci_result *res, int32_t k, int64_t *ntup, const int16_t **tuples,
+                                  const double **eps, const double **dinc, const int32_t **status,
+                                  double *order_sum, double *wall_ms) {
+    if (!res || k < 0 || k >= (int32_t)res->r.orders.size()) return MBEFCI_EINVAL;
+    const auto &o = res->r.orders[k];
+    if (ntup) *ntup = (int64_t)o.eps.size();
+    if (tuples) *tuples = o.tuples.data();
+    if (eps) *eps = o.eps.data();
+    if (dinc) *dinc = o.dinc.data();
+    if (status) *status = o.status.data();
+    if (order_sum) *order_sum = o.sum;
+    if (wall_ms) *wall_ms = o.wall_ms;
+    return MBEFCI_OK;
+}
+
+double mbefci_result_total(const mbefci_result *res) { return res ? res->r.total : 0.0; }
+
+void mbefci_result_free(mbefci_result *res) { delete res; }
+
+static mbefci_status single_tuple_batch(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, void *ws, size_t wsb,
+                                        Batch &b) {
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    if (order < 0 || (order > 0 && !tuple) || !ws) return ctx->fail(MBEFCI_EINVAL, "bad arguments");
+    TupleShape ts;
+    if ((rc = tuple_shape(ctx, order, tuple, ts)) != MBEFCI_OK) return rc;
+    ClassPlan cp;
+    plan_class(ctx, ts.key, ts.nC, cp, false);
+    Carver cv{(char *)ws, wsb};
+    if (!carve_batch(ctx, cp, 1, cv, b, false)) return ctx->fail(MBEFCI_ENOMEM, "workspace too small");
+    if ((rc = upload_tables(ctx, cp, b)) != MBEFCI_OK) return rc;
+    std::vector<const TupleShape *> sh{&ts};
+    if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) return rc;
+    hipError_t e = launch_gather(b, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_tuple_sigma(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, void *ws, size_t wsb,
+                                 const double *d_c, double *d_sigma, int32_t nvec) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (!d_c || !d_sigma || nvec < 1) return ctx->fail(MBEFCI_EINVAL, "bad vectors");
+    Batch b;
+    mbefci_status rc = single_tuple_batch(ctx, order, tuple, ws, wsb, b);
+    if (rc != MBEFCI_OK) return rc;
+    // energy shift E_core: read back from the gathered parameters
+    double ecore = 0.0;
+    HIPCHK(hipMemcpyAsync(&ecore, b.params + b.pl.off_ecore, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int v = 0; v < nvec; ++v) {
+        VecRef c{const_cast<double *>(d_c), 0, nullptr, v};
+        VecRef s{d_sigma, 0, nullptr, v};
+        hipError_t e = launch_sigma(b, c, s, ecore, false, ctx->stream, nullptr, nullptr, nullptr);
+        if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_tuple_hdiag(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, void *ws, size_t wsb,
+                                 double *d_hdiag) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (!d_hdiag) return ctx->fail(MBEFCI_EINVAL, "null output");
+    Batch b;
+    mbefci_status rc = single_tuple_batch(ctx, order, tuple, ws, wsb, b);
+    if (rc != MBEFCI_OK) return rc;
+    hipError_t e = launch_hdiag(b, d_hdiag, b.dim, 1, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_tuple_shape(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, int64_t *na_str,
+                                 int64_t *nb_str, int32_t *n_act, int32_t *na_act, int32_t *nb_act) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (!ctx->spaces_set) return ctx->fail(MBEFCI_ESTATE, "no spaces set");
+    if (order < 0 || (order > 0 && !tuple)) return ctx->fail(MBEFCI_EINVAL, "bad tuple");
+    TupleShape ts;
+    mbefci_status rc = tuple_shape(ctx, order, tuple, ts);
+    if (rc != MBEFCI_OK) return rc;
+    const Tables &ta = ctx->table(ts.key.nA, ts.key.na), &tb = ctx->table(ts.key.nA, ts.key.nb);
+    if (na_str) *na_str = ta.nstr;
+    if (nb_str) *nb_str = tb.nstr;
+    if (n_act) *n_act = ts.key.nA;
+    if (na_act) *na_act = ts.key.na;
+    if (nb_act) *nb_act = ts.key.nb;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_string_tables(int32_t nA, int32_t nel, int64_t *n_strings, int32_t *n_entries,
+                                   uint32_t *strings, uint32_t *links) {
+    if (nA < 0 || nA > 20 || nel < 0 || nel > nA) return MBEFCI_EINVAL;
+    Tables T;
+    build_tables(nA, nel, T);
+    if (n_strings) *n_strings = T.nstr;
+    if (n_entries) *n_entries = T.nent;
+    if (strings) std::memcpy(strings, T.strings.data(), 4 * T.strings.size());
+    if (links) std::memcpy(links, T.links.data(), 4 * T.links.size());
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_get_stats(const mbefci_ctx *ctx, mbefci_stats *s) {
+    if (!ctx || !s) return MBEFCI_EINVAL;
+    *s = ctx->stats;
+    return MBEFCI_OK;
+}
+
+}  // extern "C"

@@ -118,15 +118,21 @@ def config_plain(seed: int = 0) -> Problem:
                    meta={"seed": seed})
 
 
-def config_sweep(seed: int = 0, a: float = 5.0, max_order: int = 5) -> Problem:
+SWEEP_VEC_STD = math.sqrt(0.2 / 60.0)
+
+
+def config_sweep(seed: int = 0, a: float = 5.0, max_order: int = 5,
+                 vec_std: float = SWEEP_VEC_STD) -> Problem:
     """Batched order sweep: 24 orbitals, orbital 0 frozen, 5a+5b correlated
     electrons (6a+6b in total), water-like orbital energies over [-1.3, 2.5]:
     occupied 0..5 linspace(-1.3,-0.5), virtual 6..23 linspace(0.2,2.5);
-    off-diag N(0,0.05); 60 vectors N(0,0.1).  Reference CAS(6e,6o) = {3..8};
-    expansion over the 17 other non-frozen orbitals; orders 1..5, a = 5.0."""
+    off-diag N(0,0.05); 60 vectors N(0, sqrt(0.2/60)), i.e. the same
+    per-integral scale sum_L std^2 = 0.2 as the plain configuration (20 vectors
+    of std 0.1).  Reference CAS(6e,6o) = {3..8}; expansion over the 17 other
+    non-frozen orbitals; orders 1..5, a = 5.0."""
     n = 24
     diag = np.concatenate([np.linspace(-1.3, -0.5, 6), np.linspace(0.2, 2.5, 18)])
-    h, eri = random_hamiltonian(diag, 0.05, 60, 0.1, seed)
+    h, eri = random_hamiltonian(diag, 0.05, 60, vec_std, seed)
     return Problem("sweep-n24-cas66", h, eri, 6, 6, 1, [3, 4, 5, 6, 7, 8], a=a,
                    max_order=max_order, meta={"seed": seed})
 

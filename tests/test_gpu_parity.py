@@ -1,0 +1,250 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (FP64 end to end): sigma and the diagonal within 1e-12 relative;
+per-tuple CASCI energies within 1e-10 E_h; increments, order sums and totals
+within 1e-9 E_h; tuple lists identical."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fci, mbe as ombe
+
+torch = pytest.importorskip("torch")
+import paper_1905_02786_amd as M  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def ws():
+    _need_gpu()
+    return M.workspace(8 << 30)
+
+
+def _ctx(P, **opt):
+    ctx = M.Context.from_problem(P, device=0, **opt)
+    return ctx
+
+
+def _tuples_with_dims(P, k, limit):
+    import itertools
+    out = []
+    for S in itertools.combinations(P.expansion_space(), k):
+        if fci.cas_space(P, S).dim <= limit:
+            out.append(S)
+    return out
+
+
+def core_order_signs(sp):
+    """Diagonal basis change between the oracle's determinants (creators over
+    the full orbital space, ascending, core included) and the library's (core
+    creators first, then active alpha, then active beta): reordering gives
+    (-1)^(number of pairs (active electron, core orbital) with the electron
+    below the core orbital), per spin.  Eigenvalues are unchanged."""
+    act = sum(1 << p for p in sp.active)
+
+    def n_below(m):
+        return sum(bin(int(m) & act & ((1 << c) - 1)).count("1") for c in sp.core)
+    sa = np.array([n_below(m) for m in sp.alist])
+    sb = np.array([n_below(m) for m in sp.blist])
+    return ((-1.0) ** (sa[:, None] + sb[None, :])).reshape(-1)
+
+
+PROBLEMS = {
+    "plain": lambda: synth.config_plain(0),
+    "hubbard4": lambda: synth.config_hubbard(4.0),
+    "sweep": lambda: synth.config_sweep(0),
+    "large": lambda: synth.config_large(0),
+    "openshell": lambda: synth.small_problem(8, 4, 2, [2, 3], nfrozen=1, nvec=6, seed=3, e_const=0.5),
+}
+
+SIGMA_CASES = [
+    ("plain", ()), ("plain", (0,)), ("plain", (5,)), ("plain", (0, 9)), ("plain", (2, 5, 6)),
+    ("plain", (0, 1, 5, 6)), ("plain", (0, 1, 2, 5, 6, 7)),
+    ("hubbard4", (2, 7)), ("hubbard4", (0, 1, 6, 7, 8)),
+    ("sweep", ()), ("sweep", (1,)), ("sweep", (9, 13)), ("sweep", (1, 2, 10)),
+    ("sweep", (9, 10, 11, 12, 13)), ("large", (10, 11)),
+    ("openshell", ()), ("openshell", (1, 5)), ("openshell", (1, 4, 5, 6, 7)),
+]
+
+
+@pytest.mark.parametrize("name,S", SIGMA_CASES)
+def test_hdiag_and_sigma_match_oracle(ws, name, S):
+    P = PROBLEMS[name]()
+    ctx = _ctx(P)
+    sp = fci.cas_space(P, S)
+    print(f"case {name} {S} dim {sp.dim}", flush=True)
+    rng = np.random.default_rng(sum(S) + 7)
+    c = rng.standard_normal((2, sp.dim))
+    sg = core_order_signs(sp)
+    if sp.dim <= 2000:
+        H = fci.hamiltonian_matrix(P, sp)
+        ref = sg * ((sg * c) @ H.T)
+        ref_diag = np.diag(H)
+    else:
+        ref = np.stack([sg * fci.matvec(P, sp, sg * v) for v in c])
+        ref_diag = None
+    ct = torch.tensor(c, device="cuda:0")
+    sig = ctx.tuple_sigma(len(S), S, ct, ws).cpu().numpy()
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(sig - ref).max() <= 1e-12 * scale, np.abs(sig - ref).max()
+    hd = ctx.tuple_hdiag(len(S), S, ws).cpu().numpy()
+    if ref_diag is not None:
+        assert np.abs(hd - ref_diag).max() <= 1e-12 * max(1.0, np.abs(ref_diag).max())
+    else:
+        # diagonal element check on sampled determinants: <e_I|H|e_I>
+        for I in rng.choice(sp.dim, size=4, replace=False):
+            e = np.zeros(sp.dim)
+            e[I] = 1.0
+            assert abs(hd[I] - fci.matvec(P, sp, e)[I]) <= 1e-12 * max(1.0, abs(hd[I]))
+
+
+def test_sigma_is_symmetric_full_space(ws):
+    P = synth.config_plain(0)
+    S = tuple(P.expansion_space())
+    ctx = _ctx(P)
+    sh = ctx.tuple_shape(len(S), S)
+    assert sh["dim"] == 44100
+    rng = np.random.default_rng(3)
+    x = torch.tensor(rng.standard_normal((2, sh["dim"])), device="cuda:0")
+    sx = ctx.tuple_sigma(len(S), S, x, ws)
+    a = float(torch.dot(x[0], sx[1]))
+    b = float(torch.dot(sx[0], x[1]))
+    assert abs(a - b) <= 1e-12 * max(abs(a), 1.0)
+
+
+def test_energies_orders_0_to_3_match_oracle(ws):
+    P = synth.config_plain(0)
+    ctx = _ctx(P)
+    for k in range(0, 4):
+        tuples = _tuples_with_dims(P, k, 10 ** 9) if k else [()]
+        e, st = ctx.solve_tuples(k, tuples if k else [()], ws)
+        assert (st == 0).all()
+        ref = np.array([fci.casci_energy(P, S) for S in tuples])
+        print(f"order {k}: {len(tuples)} tuples, max |dE| = {np.abs(e - ref).max():.2e}", flush=True)
+        assert np.abs(e - ref).max() <= 1e-10
+
+
+def test_batched_and_per_solve_agree_bitwise(ws):
+    P = synth.config_plain(0)
+    tuples = _tuples_with_dims(P, 2, 10 ** 9)
+    e1, s1 = _ctx(P, batched=1).solve_tuples(2, tuples, ws)
+    e0, s0 = _ctx(P, batched=0).solve_tuples(2, tuples, ws)
+    assert (s1 == 0).all() and (s0 == 0).all()
+    assert np.array_equal(e1, e0)
+
+
+def test_repeat_runs_are_bitwise_identical(ws):
+    P = synth.config_hubbard(8.0)
+    tuples = _tuples_with_dims(P, 3, 10 ** 9)
+    ctx = _ctx(P)
+    e1, _ = ctx.solve_tuples(3, tuples, ws)
+    e2, _ = ctx.solve_tuples(3, tuples, ws)
+    assert np.array_equal(e1, e2)
+
+
+def _check_against_golden(res, g, tol_eps=1e-10, tol_inc=1e-9):
+    assert len(res.orders) == len(g["orders"])
+    for o, go in zip(res.orders, g["orders"]):
+        assert [list(map(int, t)) for t in o.tuples] == [list(t) for t in go["tuples"]] or o.k == 0
+        assert (o.status == 0).all()
+        assert np.abs(o.eps - np.array(go["eps"])).max() <= tol_eps, o.k
+        assert np.abs(o.dinc - np.array(go["dinc"])).max() <= tol_inc, o.k
+        assert abs(o.order_sum - go["order_sum"]) <= tol_inc
+    assert abs(res.total - g["total"]) <= tol_inc
+
+
+def test_plain_full_order_mbe_equals_fci(ws):
+    with open(os.path.join(GOLDEN, "plain_s0.json")) as f:
+        g = json.load(f)
+    P = synth.config_plain(0)
+    res = _ctx(P).run(ws)
+    _check_against_golden(res, g)
+    assert abs(res.total - g["fci"]) <= 1e-9
+    assert [len(o.tuples) for o in res.orders] == [1, 8, 28, 56, 70, 56, 28, 8, 1]
+
+
+@pytest.mark.parametrize("U", [2.0, 4.0, 8.0])
+def test_hubbard_chain_mbe(ws, U):
+    with open(os.path.join(GOLDEN, f"hubbard_U{U:g}.json")) as f:
+        g = json.load(f)
+    P0 = synth.config_hubbard(U)
+    res0 = _ctx(P0).run(ws)
+    _check_against_golden(res0, g["unscreened"])
+    assert abs(res0.total - g["fci"]) <= 1e-9
+    P5 = synth.config_hubbard(U, a=5.0)
+    res5 = _ctx(P5).run(ws)
+    _check_against_golden(res5, g["screened"])
+
+
+def _solve_samples(P, fname, ws):
+    path = os.path.join(GOLDEN, fname)
+    if not os.path.exists(path):
+        pytest.skip(f"{fname} not generated")
+    with open(path) as f:
+        g = json.load(f)
+    ctx = _ctx(P)
+    worst = 0.0
+    for smp in g["samples"]:
+        S = tuple(smp["tuple"])
+        e, st = ctx.solve_tuples(len(S), [S] if S else [()], ws)
+        assert st[0] == 0
+        worst = max(worst, abs(e[0] - smp["eps"]))
+        assert abs(e[0] - smp["eps"]) <= 1e-10, (S, e[0], smp["eps"])
+    print(f"{fname}: {len(g['samples'])} samples, max |dE| = {worst:.2e}")
+
+
+def test_sweep_sampled_tuples(ws):
+    _solve_samples(synth.config_sweep(0), "sweep_sample.json", ws)
+
+
+def test_large_sampled_tuples(ws):
+    _solve_samples(synth.config_large(0), "large_sample.json", ws)
+
+
+def test_screened_sweep_lists_match_oracle_assembler(ws):
+    """Orders 1-3 of the 24-orbital sweep with a = 5.0: the oracle's own
+    assembler and screening, fed the GPU energies, reproduce the GPU's tuple
+    lists and increments exactly."""
+    P = synth.config_sweep(0, max_order=3)
+    res = _ctx(P).run(ws)
+    table = {}
+    for o in res.orders:
+        for t, e in zip(o.tuples, o.eps):
+            table[tuple(int(x) for x in t)] = float(e)
+    ref = ombe.run(P, energy=lambda S: table[tuple(S)])
+    for o, ro in zip(res.orders, ref.orders):
+        assert [tuple(int(x) for x in t) for t in o.tuples] == list(ro.tuples)
+        assert np.array_equal(o.dinc, np.array(ro.dinc))
+
+
+def test_edge_cases(ws):
+    # single-determinant CAS: RHF reference space, order 0
+    P = synth.small_problem(6, 2, 2, [0, 1], nvec=4, seed=2)
+    ctx = _ctx(P)
+    assert ctx.tuple_shape(0, ())["dim"] == 1
+    e, st = ctx.solve_tuples(0, [()], ws)
+    assert st[0] == 0 and abs(e[0] - fci.casci_energy(P, ())) <= 1e-12
+    # empty tuple list
+    e, st = ctx.solve_tuples(1, np.zeros((0, 1), np.int16), ws)
+    assert e.shape == (0,)
+    # a one-tuple workspace that is too small
+    with pytest.raises(M.MBEFCIError) as ex:
+        ctx.solve_tuples(1, [(3,)], ws[:1024])
+    assert ex.value.code == -2
+    # out-of-space tuple
+    with pytest.raises(M.MBEFCIError):
+        ctx.solve_tuples(1, [(0,)], ws)
+    # one electron
+    P1 = synth.small_problem(5, 1, 0, [0], nvec=3, seed=1)
+    e, st = _ctx(P1).solve_tuples(4, [(1, 2, 3, 4)], ws)
+    assert abs(e[0] - fci.casci_energy(P1, (1, 2, 3, 4))) <= 1e-10

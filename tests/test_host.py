@@ -1,0 +1,173 @@
+"""Host-side checks of libmbefci.so that need no GPU: every declared symbol is
+exported, the string/link tables equal explicit fermionic operator action, the
+planner (tuple generation, screening, Eq. 3 assembly) reproduces the oracle's
+bit for bit when both are fed the same tuple energies, and bad input is
+rejected."""
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mbe as ombe
+import paper_1905_02786_amd as M
+from paper_1905_02786_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    with open(os.path.join(ROOT, "include", "mbefci.h")) as f:
+        hdr = f.read()
+    names = set(re.findall(r"\b(mbefci_[a-z_0-9]+)\s*\(", hdr))
+    names.discard("mbefci_energy_fn")
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert {n for n, _, _ in _lib.SIGNATURES} == names
+
+
+def _apply(m, p, q):
+    """E_pq on one-spin bit string m: (sign, result) by a_q then a+_p."""
+    if not (m >> q) & 1:
+        return 0, None
+    s = (-1) ** bin(m & ((1 << q) - 1)).count("1")
+    m2 = m & ~(1 << q)
+    if (m2 >> p) & 1:
+        return 0, None
+    s *= (-1) ** bin(m2 & ((1 << p) - 1)).count("1")
+    return s, m2 | (1 << p)
+
+
+@pytest.mark.parametrize("nA,nel", [(1, 0), (1, 1), (4, 2), (5, 2), (6, 3), (7, 4), (8, 1)])
+def test_string_tables_equal_operator_action(nA, nel):
+    strings, links = M.string_tables(nA, nel)
+    ref = sorted(sum(1 << p for p in c) for c in itertools.combinations(range(nA), nel))
+    assert list(strings) == ref
+    rank = {m: i for i, m in enumerate(ref)}
+    assert links.shape == (len(ref), nel * (nA - nel) + nel)
+    for I, m in enumerate(ref):
+        expect = []
+        for p in range(nA):
+            for q in range(nA):
+                s, J = _apply(m, p, q)
+                if s:
+                    P = max(p, q) * (max(p, q) + 1) // 2 + min(p, q)
+                    expect.append((rank[J], P, s))
+        got = [(int(L & 0xFFFFF), int((L >> 20) & 0x3FF), -1 if L >> 31 else 1) for L in links[I]]
+        assert sorted(got) == sorted(expect)
+
+
+def _table_energy(seed):
+    """Pseudo-random tuple energies whose increments straddle the screening
+    thresholds (fed identically to both planners)."""
+    rng = np.random.default_rng(seed)
+    cache = {}
+
+    def eps(S):
+        S = tuple(int(x) for x in S)
+        if S not in cache:
+            mag = 10.0 ** rng.uniform(-14.0, -8.5)
+            lin = sum(0.01 for x in S if x % 2)      # odd orbitals carry a large first-order term
+            cache[S] = -1.0 - lin + mag * rng.choice([-1.0, 1.0])
+        return cache[S]
+    return eps
+
+
+@pytest.mark.parametrize("a,seed", [(5.0, 0), (2.5, 1), (0.0, 2), (5.0, 3)])
+def test_planner_matches_oracle_bitwise(a, seed):
+    n = 12
+    P = synth.Problem("plan", np.eye(n), np.zeros((n,) * 4), 4, 4, 1, [3, 4], a=a, max_order=6)
+    eps = _table_energy(seed)
+    ref = ombe.run(P, energy=eps)
+    ctx = M.Context(device=None)
+    ctx.set_hamiltonian(P.h, P.eri)
+    ctx.set_spaces(P.nalpha, P.nbeta, P.nfrozen, P.ref)
+    ctx.set_options(a=a, max_order=6)
+    got = ctx.run_host(lambda k, tup: [eps(t) for t in tup] if k > 0 else [eps(())])
+    assert len(got.orders) == len(ref.orders)
+    screened = False
+    for go, ro in zip(got.orders, ref.orders):
+        assert [tuple(int(x) for x in t) for t in go.tuples] == list(ro.tuples)
+        assert np.array_equal(go.eps, np.array(ro.eps))
+        assert np.array_equal(go.dinc, np.array(ro.dinc))     # bitwise
+        assert go.order_sum == ro.order_sum
+        if ro.k >= 2 and len(ro.tuples) < math.comb(len(P.expansion_space()), ro.k):
+            screened = True
+    assert got.total == ref.total
+    if a > 0:
+        assert screened
+
+
+def test_planner_counts_without_screening():
+    n = 10
+    P = synth.Problem("c", np.eye(n), np.zeros((n,) * 4), 4, 4, 1, [1, 2, 3])
+    ctx = M.Context(device=None)
+    ctx.set_hamiltonian(P.h, P.eri)
+    ctx.set_spaces(4, 4, 1, [1, 2, 3])
+    ctx.set_options(a=0.0, max_order=0)
+    got = ctx.run_host(lambda k, tup: np.full(len(tup), -float(k)))
+    assert [len(o.tuples) for o in got.orders] == [1] + [math.comb(6, k) for k in range(1, 7)]
+
+
+def test_invalid_inputs_rejected():
+    ctx = M.Context(device=None)
+    h = np.eye(4)
+    h[0, 1] = 0.1
+    with pytest.raises(M.MBEFCIError) as e:
+        ctx.set_hamiltonian(h, np.zeros((4,) * 4))
+    assert e.value.code == -1
+    h[1, 0] = 0.1
+    ctx.set_hamiltonian(h, np.zeros((4,) * 4))
+    bad = np.zeros((4,) * 4)
+    bad[0, 0, 0, 0] = np.nan
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_hamiltonian(h, bad)
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_spaces(3, 1, 0, [0])          # singly occupied orbital 2 outside [Pi]
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_spaces(2, 2, 1, [0, 1])       # reference orbital frozen
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_spaces(2, 2, 3, [3])          # frozen orbital not doubly occupied
+    ctx.set_spaces(2, 2, 0, [1, 2])
+    with pytest.raises(M.MBEFCIError):
+        ctx.tuple_shape(2, (3, 0))            # not ascending
+    with pytest.raises(M.MBEFCIError):
+        ctx.tuple_shape(1, (1,))              # reference orbital, not expansion
+    sh = ctx.tuple_shape(1, (3,))
+    assert sh["n_active"] == 3 and sh["dim"] == 9
+    with pytest.raises(M.MBEFCIError) as e:
+        ctx.solve_tuples(1, [(0,)], _FakeTensor())
+    assert e.value.code == -5                  # host-only context
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_options(max_space=1)
+
+
+class _FakeTensor:
+    is_cuda = True
+
+    def data_ptr(self):
+        return 0
+
+    def numel(self):
+        return 0
+
+
+def test_tuple_shapes_match_partition():
+    P = synth.config_sweep()
+    ctx = M.Context(device=None)
+    ctx.set_hamiltonian(P.h, P.eri)
+    ctx.set_spaces(P.nalpha, P.nbeta, P.nfrozen, P.ref)
+    from oracle import fci
+    for S in [(), (1,), (9,), (1, 2), (1, 9, 10), (1, 2, 9, 10, 11), (9, 10, 11, 12, 13)]:
+        sh = ctx.tuple_shape(len(S), S)
+        sp = fci.cas_space(P, S)
+        assert sh["n_active"] == len(sp.active)
+        assert (sh["n_alpha_active"], sh["n_beta_active"]) == (sp.na, sp.nb)
+        assert sh["dim"] == sp.dim
+    sh = ctx.tuple_shape(5, (1, 2, 9, 10, 11))
+    assert sh["dim"] == 213444 and sh["n_active"] == 11
