@@ -90,7 +90,11 @@ typedef struct {
                                0: one tuple per launch sequence (the per-solve path) */
     int32_t keep_vectors;   /* reserved for the backward pass; 0 */
     int32_t profile;        /* 1: time every sigma launch with HIP events (mbefci_get_stats) */
-    int32_t reserved[7];
+    int32_t sigma_variant;  /* 0: automatic; 1: column strip (W kept in LDS, beta-beta part as a
+                               GEMM with the dense beta-string Hamiltonian); 2: W materialised
+                               in the workspace and gathered back.  1 falls back to 2 when the
+                               strip does not fit in LDS (more than ~1100 alpha strings). */
+    int32_t reserved[6];
 } mbefci_options;
 
 typedef struct {

@@ -18,7 +18,8 @@ c_int32, c_int64, c_double, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64
 class Options(ctypes.Structure):
     _fields_ = [("a", c_double), ("max_order", c_int32), ("e_tol", c_double), ("r_tol", c_double),
                 ("max_iter", c_int32), ("max_space", c_int32), ("batched", c_int32),
-                ("keep_vectors", c_int32), ("profile", c_int32), ("reserved", c_int32 * 7)]
+                ("keep_vectors", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
+                ("reserved", c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):

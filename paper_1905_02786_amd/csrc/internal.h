@@ -9,7 +9,15 @@ namespace mbefci {
 
 constexpr int kMaxActive = 13;     // n_A limit: the sigma kernel stages (P x P) in LDS
 constexpr int kMaxSpace = 32;      // Davidson subspace limit
-constexpr int kTile = 64;          // determinants per sigma tile
+constexpr int kTile = 64;          // determinants per sigma tile (materialised-W variant)
+constexpr int kStrip = 16;         // beta columns per workgroup (column-strip variant)
+constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
+constexpr int kMaxKS = 24;         // K steps of 4 covering the padded pair count (<= 92)
+
+// sigma variants: the column strip (W stays in LDS, beta-beta part as a GEMM
+// with the dense beta-string Hamiltonian) and the materialised W (W in HBM,
+// gathered back).  0 picks the strip whenever its LDS footprint fits.
+enum : int32_t { SIGMA_AUTO = 0, SIGMA_STRIP = 1, SIGMA_WMAT = 2 };
 
 // Davidson per-tuple status codes (device side); the public codes are derived.
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_STALLED = 4 };
@@ -65,7 +73,9 @@ struct Batch {
     double e_tol, r_tol;
     double *V, *S;          // [B][max_space][dim]
     double *Hd, *T;         // [B][dim]
-    double *W;              // [B][P][dim] sigma intermediate
+    int sigma_variant;      // SIGMA_STRIP or SIGMA_WMAT
+    double *W;              // [B][P][dim] sigma intermediate (SIGMA_WMAT)
+    double *Hb;             // [B][Nb][Nb] beta-string Hamiltonian (SIGMA_STRIP)
     int nblk;               // blocks per tuple for vector kernels
     double *part;           // [B][nblk][kMaxSpace + 1] block partial sums
     double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix
@@ -88,5 +98,8 @@ hipError_t launch_iter_head(const Batch &b, hipStream_t s);
 hipError_t launch_orthonormalize(const Batch &b, hipStream_t s);
 hipError_t launch_finalize(const Batch &b, hipStream_t s);
 size_t sigma_lds_bytes(const ParamLayout &pl);
+size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na);
+bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB);
+hipError_t launch_build_hb(const Batch &b, hipStream_t s);
 
 }  // namespace mbefci

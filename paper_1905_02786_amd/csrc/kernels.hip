@@ -294,12 +294,387 @@ __global__ __launch_bounds__(256) void k_sigma_g(Batch b, VecRef cref, VecRef sr
     }
 }
 
+// ------------------------------------------------- column-strip variant --
+// sigma = G^a( 1/2 (pq|rs) (D^a + 2 D^b) + k c ) + C H_b^T, where D^a / D^b are
+// the alpha / beta parts of D+, G^a the alpha-link gather, and H_b the
+// beta-string Hamiltonian sum_P k_P E+_P + 1/2 sum_PQ (P|Q) E+_P E+_Q (the
+// alpha-beta coupling E^a E^b appears twice in the pair sum and is carried by
+// the factor 2 on D^b).  A workgroup owns 16 beta columns: for every alpha
+// string K_a it gathers D for the 16 determinants (K_a, B0..B0+15) into LDS,
+// contracts with 1/2 (pq|rs) held as MFMA A fragments in registers (one
+// 16-row M tile per wave), and scatters W through the alpha links of K_a
+// into an LDS strip sigma[:, B0..B0+15].  Each alpha link of one string moves
+// to a different string and the diagonal links all return to K_a itself, so
+// the scatter of one step has no write conflicts.
+
+// MFMA waves of the strip kernel: one 16-row M tile each, at most 4 so the
+// waves of a workgroup sit on distinct SIMDs; rows beyond 64 use vector FMA.
+static inline int strip_waves(const ParamLayout &pl) { return pl.Ppad / 16 < 4 ? pl.Ppad / 16 : 4; }
+
+// M tiles past the 4 wave-owned ones (rows >= 64): each wave contracts a
+// quarter of K into a partial 16x16 tile; readers sum the 4 partials.
+static inline int strip_extra_tiles(const ParamLayout &pl) {
+    const int x = pl.Ppad / 16 - strip_waves(pl);
+    return x > 0 ? x : 0;
+}
+
+size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na) {
+    return sizeof(double) * ((size_t)Na * kStrip + 2 * (size_t)pl.Kpad * kStrip + (size_t)64 * kStrip +
+                             (size_t)strip_extra_tiles(pl) * (4 * 256 + 16));
+}
+
+constexpr int kMaxR = 4;   // gather items per thread: ceil(n_links * 16 / threads) <= 3 for n_A <= 13
+
+bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB) {
+    const int nth = 64 * strip_waves(pl);
+    return strip_lds_bytes(pl, Na) <= 150 * 1024 && pl.Kpad / 4 <= kMaxKS && strip_extra_tiles(pl) <= 2 &&
+           (nentA * kStrip + nth - 1) / nth <= kMaxR && (nentB * kStrip + nth - 1) / nth <= kMaxR;
+}
+
+// Software-pipelined: the alpha links and c values of step K_a + 1 are loaded
+// into registers while step K_a runs its MFMA and scatter.  Thread items:
+// alpha item (e, col) = (item >> 4, item & 15) over the alpha links of K_a
+// (the same item later scatters W through that link), beta item
+// (col, e) = (item / n_links_b, item % n_links_b) over the fixed beta links
+// of the strip's columns.  D is split into D^a and 2 D^b so each entry has a
+// single writer per step; D^b entries are rewritten at the same places every
+// step, D^a entries are reset by their writer after the MFMA.
+// Workgroups are handed to the 8 XCDs round-robin by linear id; map id L to
+// (tuple, strip) so that every strip of tuple t runs on XCD t % 8 and the
+// strips of one tuple are dispatched back to back: its vector stays in that
+// XCD's L2 while they run.
+__device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, int &strip) {
+    const int64_t xcd = L % kXcds, j = L / kXcds;
+    t = (int)((j / nstrips) * kXcds + xcd);
+    strip = (int)(j % nstrips);
+    return t < B;
+}
+
+template <int MT, int NX>
+__global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, VecRef sref, double shift,
+                                                         int skip_done) {
+    const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
+    int t, strip_id;
+    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    constexpr int NTH = 64 * MT;
+    const ParamLayout &pl = b.pl;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t Na = b.Na, Nb = b.Nb;
+    const int B0 = strip_id * kStrip;
+    const int ncol = (int)min((int64_t)kStrip, Nb - B0);
+    const int nentA = b.nentA, nentB = b.nentB, ndiag = b.na;
+    extern __shared__ double lds[];
+    double *strip = lds;                               // [Na][16]
+    double *Da = strip + Na * kStrip;                  // [Kpad][16]
+    double *Db = Da + pl.Kpad * kStrip;                // [Kpad][16]  (holds 2 D^b)
+    double *Wt = Db + pl.Kpad * kStrip;                // [64][16]   rows of the wave-owned tiles
+    double *Wp = Wt + 64 * kStrip;                     // [NX][4][16][16] partial tiles, rows >= 64
+    double *kx = Wp + NX * 4 * 256;                    // [32] k of rows >= 64
+    const double *prm = b.params + (int64_t)t * pl.stride;
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const int KS = pl.Kpad / 4;
+    const int ar = lane & 15, kr = lane >> 4;
+    double af[kMaxKS];
+#pragma unroll
+    for (int ks = 0; ks < kMaxKS; ++ks)
+        af[ks] = (ks < KS) ? prm[pl.off_eri + (wave * 16 + ar) * pl.Kpad + ks * 4 + kr] : 0.0;
+    double kv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = wave * 16 + kr + 4 * v;
+        kv[v] = row < pl.P ? prm[pl.off_k + row] : 0.0;
+    }
+    for (int i = tid; i < Na * kStrip; i += NTH) strip[i] = 0.0;
+    for (int i = tid; i < 2 * pl.Kpad * kStrip; i += NTH) Da[i] = 0.0;
+    // extra tiles: this wave's quarter of the K steps
+    const int KQ = (KS + 3) / 4, ks0 = wave * KQ;
+    double afx[NX > 0 ? NX : 1][6];
+#pragma unroll
+    for (int x = 0; x < NX; ++x) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const int ks = ks0 + j;
+            afx[x][j] = (j < KQ && ks < KS) ? prm[pl.off_eri + (64 + 16 * x + ar) * pl.Kpad + ks * 4 + kr] : 0.0;
+        }
+    }
+    for (int i = tid; i < 16 * NX; i += NTH) kx[i] = 64 + i < pl.P ? prm[pl.off_k + 64 + i] : 0.0;
+    // fixed beta items: D^b offset | sign bit 31, and the source column in a c row
+    int bq[kMaxR], bj[kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+        const int item = tid + r * NTH;
+        bq[r] = -1;
+        bj[r] = 0;
+        if (item < nentB * kStrip) {
+            const int col = item / nentB, e = item % nentB;
+            if (col < ncol) {
+                const uint32_t L = b.linkB[(int64_t)(B0 + col) * nentB + e];
+                bq[r] = (int)((((L >> 20) & 0x3FFu) * kStrip + col) | (L & 0x80000000u));
+                bj[r] = (int)(L & 0xFFFFFu);
+            }
+        }
+    }
+    // alpha items: link e = (tid >> 4) + r * NTH / 16 of the current string, column ar (= tid & 15)
+    const int ae0 = tid >> 4;
+    constexpr int ESTEP = NTH / 16;
+    const bool colok = ar < ncol;
+    // prefetch step 0
+    uint32_t lw[kMaxR];
+    double ca[kMaxR], cb[kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+        const bool av = colok && ae0 + r * ESTEP < nentA;
+        lw[r] = av ? b.linkA[ae0 + r * ESTEP] : 0u;
+        ca[r] = av ? c[(int64_t)(lw[r] & 0xFFFFFu) * Nb + B0 + ar] : 0.0;
+        cb[r] = bq[r] != -1 ? c[bj[r]] : 0.0;
+    }
+    uint32_t sa = b.strA[0];
+    double cc = ar < ncol ? c[B0 + ar] : 0.0;
+    __syncthreads();
+    for (int64_t Ka = 0; Ka < Na; ++Ka) {
+        // P1: write D for step Ka
+        uint32_t cur[kMaxR];
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            cur[r] = lw[r];
+            if (colok && ae0 + r * ESTEP < nentA) {
+                const double s = (lw[r] >> 31) ? -1.0 : 1.0;
+                Da[((lw[r] >> 20) & 0x3FFu) * kStrip + ar] = s * ca[r];
+            }
+            if (bq[r] != -1) Db[bq[r] & 0x7FFFFFFF] = (bq[r] < 0 ? -2.0 : 2.0) * cb[r];
+        }
+        const uint32_t cur_sa = sa;
+        const double cur_cc = cc;
+        __syncthreads();
+        // P2: links of step Ka+1, MFMA of step Ka, c values of step Ka+1
+        const bool more = Ka + 1 < Na;
+        if (more) {
+#pragma unroll
+            for (int r = 0; r < kMaxR; ++r)
+                if (colok && ae0 + r * ESTEP < nentA) lw[r] = b.linkA[(Ka + 1) * nentA + ae0 + r * ESTEP];
+            sa = b.strA[Ka + 1];
+        }
+        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < kMaxKS; ks += 2) {
+            if (ks < KS) {
+                const int o = (ks * 4 + kr) * kStrip + ar;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], Da[o] + Db[o], acc0, 0, 0, 0);
+            }
+            if (ks + 1 < KS) {
+                const int o = ((ks + 1) * 4 + kr) * kStrip + ar;
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks + 1], Da[o] + Db[o], acc1, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = wave * 16 + kr + 4 * v;   // f64 16x16x4 output: lane>>4 + 4*item
+            Wt[row * kStrip + ar] = acc0[v] + acc1[v] + kv[v] * cur_cc;
+        }
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+            {
+                dbl4 ax = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < 6; ++j) {
+                    const int ks = ks0 + j;
+                    if (j < KQ && ks < KS) {
+                        const int o = (ks * 4 + kr) * kStrip + ar;
+                        ax = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], Da[o] + Db[o], ax, 0, 0, 0);
+                    }
+                }
+                double *wp = Wp + (x * 4 + wave) * 256;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) wp[(kr + 4 * v) * kStrip + ar] = ax[v];
+            }
+        }
+        if (more) {
+            const double *crow = c + (Ka + 1) * Nb;
+#pragma unroll
+            for (int r = 0; r < kMaxR; ++r) {
+                if (colok && ae0 + r * ESTEP < nentA) ca[r] = c[(int64_t)(lw[r] & 0xFFFFFu) * Nb + B0 + ar];
+                if (bq[r] != -1) cb[r] = crow[bj[r]];
+            }
+            cc = ar < ncol ? crow[B0 + ar] : 0.0;
+        }
+        __syncthreads();
+        // P3: reset D^a, scatter W through the alpha links of Ka
+        // col is always tid & 15 here, whose c value is cur_cc
+        auto wval = [&](int Q, int col) -> double {
+            if (NX == 0 || Q < 64) return Wt[Q * kStrip + col];
+            const double *wp = Wp + ((Q - 64) >> 4) * 4 * 256 + ((Q - 64) & 15) * kStrip + col;
+            return wp[0] + wp[256] + wp[512] + wp[768] + kx[Q - 64] * cur_cc;
+        };
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            const int e = ae0 + r * ESTEP;
+            if (colok && e < nentA) {
+                const int Q = (int)((cur[r] >> 20) & 0x3FFu);
+                Da[Q * kStrip + ar] = 0.0;
+                if (e >= ndiag) {
+                    const double s = (cur[r] >> 31) ? -1.0 : 1.0;
+                    strip[(int64_t)(cur[r] & 0xFFFFFu) * kStrip + ar] += s * wval(Q, ar);
+                }
+            }
+        }
+        if (tid < kStrip) {
+            double acc = 0.0;
+            for (uint32_t x = cur_sa; x; x &= x - 1) {
+                const int p = __ffs(x) - 1;
+                acc += wval(p * (p + 3) / 2, tid);
+            }
+            strip[Ka * kStrip + tid] += acc;
+        }
+        __syncthreads();
+    }
+    for (int64_t i = tid; i < Na * kStrip; i += NTH) {
+        const int64_t row = i / kStrip;
+        const int col = (int)(i % kStrip);
+        if (col < ncol) {
+            const int64_t d = row * Nb + B0 + col;
+            sg[d] = strip[i] + shift * c[d];
+        }
+    }
+}
+
+// H_b (symmetric, Nb x Nb) per tuple; thread J writes row J:
+// H_b e_J = sum_{links (Q,K,s) of J} s [ k_Q e_K + 1/2 sum_{links (P,I,s') of K} s' (P|Q) e_I ].
+__global__ __launch_bounds__(64) void k_build_hb(Batch b) {
+    const int t = blockIdx.y;
+    const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= b.Nb) return;
+    const ParamLayout &pl = b.pl;
+    const double *prm = b.params + (int64_t)t * pl.stride;
+    double *row = b.Hb + ((int64_t)t * b.Nb + J) * b.Nb;
+    for (int64_t i = 0; i < b.Nb; ++i) row[i] = 0.0;
+    const uint32_t *lj = b.linkB + J * b.nentB;
+    for (int e = 0; e < b.nentB; ++e) {
+        int K, Q;
+        double s;
+        link_decode(lj[e], K, Q, s);
+        row[K] += s * prm[pl.off_k + Q];
+        const uint32_t *lk = b.linkB + (int64_t)K * b.nentB;
+        for (int f = 0; f < b.nentB; ++f) {
+            int I, P;
+            double s2;
+            link_decode(lk[f], I, P, s2);
+            row[I] += s * s2 * prm[pl.off_eri + P * pl.Kpad + Q];   // stored as 1/2 (P|Q)
+        }
+    }
+}
+
+hipError_t launch_build_hb(const Batch &b, hipStream_t s) {
+    if (b.sigma_variant != SIGMA_STRIP) return hipSuccess;
+    dim3 grid((unsigned)((b.Nb + 63) / 64), b.B);
+    hipLaunchKernelGGL(k_build_hb, grid, dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+// sigma += C H_b per tuple (C = c as Na x Nb row-major, H_b symmetric):
+// 64 x 64 output tile per block of 4 waves, each wave 32 x 32 = 2 x 2 FP64
+// MFMA tiles; K in chunks of 16 staged through LDS.
+__global__ __launch_bounds__(256) void k_gemm_hb(Batch b, VecRef cref, VecRef sref, int skip_done) {
+    const int t = blockIdx.z;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const int64_t Na = b.Na, Nb = b.Nb;
+    const double *C = vref(cref, t, b.dim);
+    double *S = const_cast<double *>(vref(sref, t, b.dim));
+    const double *Hb = b.Hb + (int64_t)t * Nb * Nb;
+    __shared__ double As[64][17];
+    __shared__ double Bs[16][65];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wy = wave >> 1, wx = wave & 1;
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = 0; k0 < Nb; k0 += 16) {
+        __syncthreads();
+        for (int i = tid; i < 64 * 16; i += 256) {
+            const int r = i >> 4, kk = i & 15;
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            As[r][kk] = (gr < Na && gk < Nb) ? C[gr * Nb + gk] : 0.0;
+            const int kb = i >> 6, cj = i & 63;
+            const int64_t gk2 = k0 + kb, gc = c0 + cj;
+            Bs[kb][cj] = (gk2 < Nb && gc < Nb) ? Hb[gk2 * Nb + gc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            double a[2], bb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[wy * 32 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bb[j] = Bs[ks * 4 + (lane >> 4)][wx * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gr = r0 + wy * 32 + i * 16 + (lane >> 4) + 4 * v;
+                const int64_t gc = c0 + wx * 32 + j * 16 + (lane & 15);
+                if (gr < Na && gc < Nb) S[gr * Nb + gc] += acc[i][j][v];
+            }
+}
+
+template <int MT, int NX>
+static hipError_t launch_strip_mt(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+    const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
+    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
+    hipLaunchKernelGGL((k_sigma_strip<MT, NX>), grid, dim3(64 * MT), strip_lds_bytes(b.pl, b.Na), s, b, c, sig, shift,
+                       skip);
+    return hipGetLastError();
+}
+
+static hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+    switch (strip_waves(b.pl) * 4 + strip_extra_tiles(b.pl)) {
+        case 4: return launch_strip_mt<1, 0>(b, c, sig, shift, skip, s);
+        case 8: return launch_strip_mt<2, 0>(b, c, sig, shift, skip, s);
+        case 12: return launch_strip_mt<3, 0>(b, c, sig, shift, skip, s);
+        case 16: return launch_strip_mt<4, 0>(b, c, sig, shift, skip, s);
+        case 17: return launch_strip_mt<4, 1>(b, c, sig, shift, skip, s);
+        case 18: return launch_strip_mt<4, 2>(b, c, sig, shift, skip, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t init_kernels() {
-    return hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    const void *strips[] = {(const void *)k_sigma_strip<1, 0>, (const void *)k_sigma_strip<2, 0>,
+                            (const void *)k_sigma_strip<3, 0>, (const void *)k_sigma_strip<4, 0>,
+                            (const void *)k_sigma_strip<4, 1>, (const void *)k_sigma_strip<4, 2>};
+    for (const void *f : strips) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
+    if (b.sigma_variant == SIGMA_STRIP) {
+        if (ev0) (void)hipEventRecord(ev0, s);
+        hipError_t e = launch_strip(b, c, sig, shift, skip_done ? 1 : 0, s);
+        if (e != hipSuccess) return e;
+        if (ev1) (void)hipEventRecord(ev1, s);
+        const dim3 grid((unsigned)((b.Nb + 63) / 64), (unsigned)((b.Na + 63) / 64), b.B);
+        hipLaunchKernelGGL(k_gemm_hb, grid, dim3(256), 0, s, b, c, sig, skip_done ? 1 : 0);
+        e = hipGetLastError();
+        if (ev2) (void)hipEventRecord(ev2, s);
+        return e;
+    }
     const int64_t ntiles = (b.dim + kTile - 1) / kTile;
     // aim for >= ~2048 blocks over the batch, at most 32 tiles per block
     int64_t want_blocks = (2048 + b.B - 1) / b.B;

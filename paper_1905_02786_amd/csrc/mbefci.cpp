@@ -191,6 +191,7 @@ struct ClassPlan {
     int64_t dim;
     ParamLayout pl;
     int nblk;
+    int variant;
     size_t fixed_bytes, per_tuple;
 };
 
@@ -202,6 +203,9 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.dim = cp.ta->nstr * cp.tb->nstr;
     cp.pl.init(key.nA);
     cp.nblk = nblk_for(cp.dim);
+    const int want = ctx->opt.sigma_variant;
+    const bool fits = strip_fits(cp.pl, cp.ta->nstr, cp.ta->nent, cp.tb->nent);
+    cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) + 64 * 256;
@@ -210,7 +214,8 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     pt += 8 * (size_t)cp.pl.stride;                          // params
     pt += 4 * (size_t)(key.nA + nC + 2);                      // act, core
     pt += 8 * (size_t)cp.dim * (2 * ms + (davidson ? 2 : 0)); // V, S, Hd, T
-    pt += 8 * (size_t)cp.pl.P * cp.dim;                      // W
+    if (cp.variant == SIGMA_WMAT) pt += 8 * (size_t)cp.pl.P * cp.dim;            // W
+    else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr;                            // H_b
     pt += 8 * (size_t)cp.nblk * (kMaxSpace + 1);             // partials
     pt += 8 * (size_t)(kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 6;
     cp.per_tuple = pt + 256;
@@ -268,7 +273,14 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.Hd = cv.take<double>((size_t)B * b.dim);
         b.T = cv.take<double>((size_t)B * b.dim);
     }
-    b.W = cv.take<double>((size_t)B * cp.pl.P * b.dim + 1);
+    b.sigma_variant = cp.variant;
+    if (cp.variant == SIGMA_WMAT) {
+        b.W = cv.take<double>((size_t)B * cp.pl.P * b.dim + 1);
+        b.Hb = nullptr;
+    } else {
+        b.W = nullptr;
+        b.Hb = cv.take<double>((size_t)B * b.Nb * b.Nb);
+    }
     b.nblk = cp.nblk;
     b.part = cv.take<double>((size_t)B * b.nblk * (kMaxSpace + 1));
     b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
@@ -348,6 +360,7 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     hipStream_t s = ctx->stream;
     hipError_t e;
     if ((e = launch_gather(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    if ((e = launch_build_hb(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if ((e = launch_hdiag(b, b.Hd, b.dim, 0, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if ((e = launch_init_state(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if ((e = launch_guess(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
@@ -717,6 +730,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->max_space < 2 || o->max_space > kMaxSpace) return ctx->fail(MBEFCI_EINVAL, "max_space must be in 2..32");
     if (o->max_iter < 1) return ctx->fail(MBEFCI_EINVAL, "max_iter must be >= 1");
     if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
+    if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
     ctx->opt = *o;
     return MBEFCI_OK;
 }
@@ -826,6 +840,8 @@ static mbefci_status single_tuple_batch(mbefci_ctx *ctx, int32_t order, const in
     std::vector<const TupleShape *> sh{&ts};
     if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) return rc;
     hipError_t e = launch_gather(b, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    e = launch_build_hb(b, ctx->stream);
     if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     return MBEFCI_OK;
 }

@@ -77,10 +77,11 @@ SIGMA_CASES = [
 ]
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("name,S", SIGMA_CASES)
-def test_hdiag_and_sigma_match_oracle(ws, name, S):
+def test_hdiag_and_sigma_match_oracle(ws, name, S, variant):
     P = PROBLEMS[name]()
-    ctx = _ctx(P)
+    ctx = _ctx(P, sigma_variant=variant)
     sp = fci.cas_space(P, S)
     print(f"case {name} {S} dim {sp.dim}", flush=True)
     rng = np.random.default_rng(sum(S) + 7)
@@ -134,13 +135,25 @@ def test_energies_orders_0_to_3_match_oracle(ws):
         assert np.abs(e - ref).max() <= 1e-10
 
 
-def test_batched_and_per_solve_agree_bitwise(ws):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_batched_and_per_solve_agree_bitwise(ws, variant):
     P = synth.config_plain(0)
     tuples = _tuples_with_dims(P, 2, 10 ** 9)
-    e1, s1 = _ctx(P, batched=1).solve_tuples(2, tuples, ws)
-    e0, s0 = _ctx(P, batched=0).solve_tuples(2, tuples, ws)
+    e1, s1 = _ctx(P, batched=1, sigma_variant=variant).solve_tuples(2, tuples, ws)
+    e0, s0 = _ctx(P, batched=0, sigma_variant=variant).solve_tuples(2, tuples, ws)
     assert (s1 == 0).all() and (s0 == 0).all()
     assert np.array_equal(e1, e0)
+
+
+def test_sigma_variants_agree(ws):
+    """The column-strip and materialised-W sigma give the same energies."""
+    P = synth.config_sweep(0)
+    import itertools
+    tuples = list(itertools.combinations(P.expansion_space(), 3))[::7]
+    e1, s1 = _ctx(P, sigma_variant=1).solve_tuples(3, tuples, ws)
+    e2, s2 = _ctx(P, sigma_variant=2).solve_tuples(3, tuples, ws)
+    assert (s1 == 0).all() and (s2 == 0).all()
+    assert np.abs(e1 - e2).max() <= 1e-10
 
 
 def test_repeat_runs_are_bitwise_identical(ws):
