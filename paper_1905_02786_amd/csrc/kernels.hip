@@ -318,10 +318,27 @@ static inline int strip_extra_tiles(const ParamLayout &pl) {
     return x > 0 ? x : 0;
 }
 
-size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na) {
-    return sizeof(double) * ((size_t)Na * kStrip + 2 * (size_t)pl.Kpad * kStrip + (size_t)64 * kStrip +
-                             (size_t)strip_extra_tiles(pl) * (4 * 256 + 16));
+// LDS of the strip kernel; `split` keeps D^a and 2 D^b in separate tiles
+// (plain stores), otherwise one tile takes both through LDS atomic adds.
+static size_t strip_lds(const ParamLayout &pl, int64_t Na, bool split) {
+    const int xr = pl.P > 64 ? pl.P - 64 : 0;   // rows of the extra tiles that hold pairs
+    return sizeof(double) * ((size_t)Na * kStrip + (split ? 2 : 1) * (size_t)pl.Kpad * kStrip +
+                             (size_t)64 * kStrip + (size_t)4 * xr * kStrip + 32);
 }
+
+// Workgroups per CU of the strip kernel (160 KiB LDS; register file: 3 waves
+// per SIMD without extra tiles, 2 with).
+static int strip_blocks_per_cu(const ParamLayout &pl, int64_t Na, bool split) {
+    const int by_lds = (int)((160 * 1024) / strip_lds(pl, Na, split));
+    const int by_regs = strip_extra_tiles(pl) ? 2 : 3;
+    return by_lds < by_regs ? by_lds : by_regs;
+}
+
+static bool strip_split(const ParamLayout &pl, int64_t Na) {
+    return strip_blocks_per_cu(pl, Na, true) >= strip_blocks_per_cu(pl, Na, false);
+}
+
+size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na) { return strip_lds(pl, Na, strip_split(pl, Na)); }
 
 constexpr int kMaxR = 4;   // gather items per thread: ceil(n_links * 16 / threads) <= 3 for n_A <= 13
 
@@ -336,9 +353,10 @@ bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB) {
 // alpha item (e, col) = (item >> 4, item & 15) over the alpha links of K_a
 // (the same item later scatters W through that link), beta item
 // (col, e) = (item / n_links_b, item % n_links_b) over the fixed beta links
-// of the strip's columns.  D is split into D^a and 2 D^b so each entry has a
-// single writer per step; D^b entries are rewritten at the same places every
-// step, D^a entries are reset by their writer after the MFMA.
+// of the strip's columns.  D = D^a + 2 D^b: an entry receives at most one
+// alpha and one beta term, added atomically in LDS (two-term sums commute, so
+// the value does not depend on their order); writers reset their entries
+// after the MFMA.
 // Workgroups are handed to the 8 XCDs round-robin by linear id; map id L to
 // (tuple, strip) so that every strip of tuple t runs on XCD t % 8 and the
 // strips of one tuple are dispatched back to back: its vector stays in that
@@ -350,7 +368,7 @@ __device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, i
     return t < B;
 }
 
-template <int MT, int NX>
+template <int MT, int NX, bool SPLIT>
 __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, VecRef sref, double shift,
                                                          int skip_done) {
     const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
@@ -366,11 +384,12 @@ __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, V
     const int nentA = b.nentA, nentB = b.nentB, ndiag = b.na;
     extern __shared__ double lds[];
     double *strip = lds;                               // [Na][16]
-    double *Da = strip + Na * kStrip;                  // [Kpad][16]
-    double *Db = Da + pl.Kpad * kStrip;                // [Kpad][16]  (holds 2 D^b)
-    double *Wt = Db + pl.Kpad * kStrip;                // [64][16]   rows of the wave-owned tiles
-    double *Wp = Wt + 64 * kStrip;                     // [NX][4][16][16] partial tiles, rows >= 64
-    double *kx = Wp + NX * 4 * 256;                    // [32] k of rows >= 64
+    double *D = strip + Na * kStrip;                   // [Kpad][16]  D^a (+ 2 D^b unless SPLIT)
+    double *Db = SPLIT ? D + pl.Kpad * kStrip : D;     // [Kpad][16]  2 D^b when SPLIT
+    double *Wt = D + (SPLIT ? 2 : 1) * pl.Kpad * kStrip;   // [64][16] rows of the wave-owned tiles
+    const int XR = pl.P > 64 ? pl.P - 64 : 0;          // pair rows past 64
+    double *Wp = Wt + 64 * kStrip;                     // [4][XR][16] partial rows >= 64, per wave
+    double *kx = Wp + 4 * XR * kStrip;                 // [32] k of rows >= 64
     const double *prm = b.params + (int64_t)t * pl.stride;
     const double *c = vref(cref, t, b.dim);
     double *sg = const_cast<double *>(vref(sref, t, b.dim));
@@ -387,7 +406,7 @@ __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, V
         kv[v] = row < pl.P ? prm[pl.off_k + row] : 0.0;
     }
     for (int i = tid; i < Na * kStrip; i += NTH) strip[i] = 0.0;
-    for (int i = tid; i < 2 * pl.Kpad * kStrip; i += NTH) Da[i] = 0.0;
+    for (int i = tid; i < (SPLIT ? 2 : 1) * pl.Kpad * kStrip; i += NTH) D[i] = 0.0;
     // extra tiles: this wave's quarter of the K steps
     const int KQ = (KS + 3) / 4, ks0 = wave * KQ;
     double afx[NX > 0 ? NX : 1][6];
@@ -441,9 +460,14 @@ __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, V
             cur[r] = lw[r];
             if (colok && ae0 + r * ESTEP < nentA) {
                 const double s = (lw[r] >> 31) ? -1.0 : 1.0;
-                Da[((lw[r] >> 20) & 0x3FFu) * kStrip + ar] = s * ca[r];
+                if (SPLIT) D[((lw[r] >> 20) & 0x3FFu) * kStrip + ar] = s * ca[r];
+                else atomicAdd(&D[((lw[r] >> 20) & 0x3FFu) * kStrip + ar], s * ca[r]);
             }
-            if (bq[r] != -1) Db[bq[r] & 0x7FFFFFFF] = (bq[r] < 0 ? -2.0 : 2.0) * cb[r];
+            if (bq[r] != -1) {
+                const double v = (bq[r] < 0 ? -2.0 : 2.0) * cb[r];
+                if (SPLIT) Db[bq[r] & 0x7FFFFFFF] = v;
+                else atomicAdd(&D[bq[r] & 0x7FFFFFFF], v);
+            }
         }
         const uint32_t cur_sa = sa;
         const double cur_cc = cc;
@@ -461,11 +485,11 @@ __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, V
         for (int ks = 0; ks < kMaxKS; ks += 2) {
             if (ks < KS) {
                 const int o = (ks * 4 + kr) * kStrip + ar;
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], Da[o] + Db[o], acc0, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], SPLIT ? D[o] + Db[o] : D[o], acc0, 0, 0, 0);
             }
             if (ks + 1 < KS) {
                 const int o = ((ks + 1) * 4 + kr) * kStrip + ar;
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks + 1], Da[o] + Db[o], acc1, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks + 1], SPLIT ? D[o] + Db[o] : D[o], acc1, 0, 0, 0);
             }
         }
 #pragma unroll
@@ -482,12 +506,15 @@ __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, V
                     const int ks = ks0 + j;
                     if (j < KQ && ks < KS) {
                         const int o = (ks * 4 + kr) * kStrip + ar;
-                        ax = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], Da[o] + Db[o], ax, 0, 0, 0);
+                        ax = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], SPLIT ? D[o] + Db[o] : D[o], ax, 0, 0, 0);
                     }
                 }
-                double *wp = Wp + (x * 4 + wave) * 256;
+                double *wp = Wp + wave * XR * kStrip;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) wp[(kr + 4 * v) * kStrip + ar] = ax[v];
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = 16 * x + kr + 4 * v;
+                    if (rr < XR) wp[rr * kStrip + ar] = ax[v];
+                }
             }
         }
         if (more) {
@@ -504,15 +531,17 @@ __global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, V
         // col is always tid & 15 here, whose c value is cur_cc
         auto wval = [&](int Q, int col) -> double {
             if (NX == 0 || Q < 64) return Wt[Q * kStrip + col];
-            const double *wp = Wp + ((Q - 64) >> 4) * 4 * 256 + ((Q - 64) & 15) * kStrip + col;
-            return wp[0] + wp[256] + wp[512] + wp[768] + kx[Q - 64] * cur_cc;
+            const double *wp = Wp + (Q - 64) * kStrip + col;
+            const int ws = XR * kStrip;
+            return wp[0] + wp[ws] + wp[2 * ws] + wp[3 * ws] + kx[Q - 64] * cur_cc;
         };
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             const int e = ae0 + r * ESTEP;
+            if (!SPLIT && bq[r] != -1) D[bq[r] & 0x7FFFFFFF] = 0.0;
             if (colok && e < nentA) {
                 const int Q = (int)((cur[r] >> 20) & 0x3FFu);
-                Da[Q * kStrip + ar] = 0.0;
+                D[Q * kStrip + ar] = 0.0;
                 if (e >= ndiag) {
                     const double s = (cur[r] >> 31) ? -1.0 : 1.0;
                     strip[(int64_t)(cur[r] & 0xFFFFFu) * kStrip + ar] += s * wval(Q, ar);
@@ -628,23 +657,30 @@ __global__ __launch_bounds__(256) void k_gemm_hb(Batch b, VecRef cref, VecRef sr
             }
 }
 
-template <int MT, int NX>
+template <int MT, int NX, bool SPLIT>
 static hipError_t launch_strip_mt(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    hipLaunchKernelGGL((k_sigma_strip<MT, NX>), grid, dim3(64 * MT), strip_lds_bytes(b.pl, b.Na), s, b, c, sig, shift,
+    hipLaunchKernelGGL((k_sigma_strip<MT, NX, SPLIT>), grid, dim3(64 * MT), strip_lds(b.pl, b.Na, SPLIT), s, b, c, sig, shift,
                        skip);
     return hipGetLastError();
 }
 
 static hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
-    switch (strip_waves(b.pl) * 4 + strip_extra_tiles(b.pl)) {
-        case 4: return launch_strip_mt<1, 0>(b, c, sig, shift, skip, s);
-        case 8: return launch_strip_mt<2, 0>(b, c, sig, shift, skip, s);
-        case 12: return launch_strip_mt<3, 0>(b, c, sig, shift, skip, s);
-        case 16: return launch_strip_mt<4, 0>(b, c, sig, shift, skip, s);
-        case 17: return launch_strip_mt<4, 1>(b, c, sig, shift, skip, s);
-        case 18: return launch_strip_mt<4, 2>(b, c, sig, shift, skip, s);
+    const bool split = strip_split(b.pl, b.Na);
+    switch ((strip_waves(b.pl) * 4 + strip_extra_tiles(b.pl)) * 2 + (split ? 1 : 0)) {
+        case 8: return launch_strip_mt<1, 0, false>(b, c, sig, shift, skip, s);
+        case 9: return launch_strip_mt<1, 0, true>(b, c, sig, shift, skip, s);
+        case 16: return launch_strip_mt<2, 0, false>(b, c, sig, shift, skip, s);
+        case 17: return launch_strip_mt<2, 0, true>(b, c, sig, shift, skip, s);
+        case 24: return launch_strip_mt<3, 0, false>(b, c, sig, shift, skip, s);
+        case 25: return launch_strip_mt<3, 0, true>(b, c, sig, shift, skip, s);
+        case 32: return launch_strip_mt<4, 0, false>(b, c, sig, shift, skip, s);
+        case 33: return launch_strip_mt<4, 0, true>(b, c, sig, shift, skip, s);
+        case 34: return launch_strip_mt<4, 1, false>(b, c, sig, shift, skip, s);
+        case 35: return launch_strip_mt<4, 1, true>(b, c, sig, shift, skip, s);
+        case 36: return launch_strip_mt<4, 2, false>(b, c, sig, shift, skip, s);
+        case 37: return launch_strip_mt<4, 2, true>(b, c, sig, shift, skip, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -652,9 +688,13 @@ static hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shif
 hipError_t init_kernels() {
     hipError_t e = hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    const void *strips[] = {(const void *)k_sigma_strip<1, 0>, (const void *)k_sigma_strip<2, 0>,
-                            (const void *)k_sigma_strip<3, 0>, (const void *)k_sigma_strip<4, 0>,
-                            (const void *)k_sigma_strip<4, 1>, (const void *)k_sigma_strip<4, 2>};
+    const void *strips[] = {
+        (const void *)k_sigma_strip<1, 0, false>, (const void *)k_sigma_strip<1, 0, true>,
+        (const void *)k_sigma_strip<2, 0, false>, (const void *)k_sigma_strip<2, 0, true>,
+        (const void *)k_sigma_strip<3, 0, false>, (const void *)k_sigma_strip<3, 0, true>,
+        (const void *)k_sigma_strip<4, 0, false>, (const void *)k_sigma_strip<4, 0, true>,
+        (const void *)k_sigma_strip<4, 1, false>, (const void *)k_sigma_strip<4, 1, true>,
+        (const void *)k_sigma_strip<4, 2, false>, (const void *)k_sigma_strip<4, 2, true>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
