@@ -216,6 +216,28 @@ mbefci_status mbefci_tuple_shape(mbefci_ctx *ctx, int32_t order, const int16_t *
 mbefci_status mbefci_string_tables(int32_t norb_active, int32_t nel, int64_t *n_strings,
                                    int32_t *n_entries, uint32_t *strings, uint32_t *links);
 
+/* Gradient of the summed MBE energy of `res` (Eq. 1-3, tuple set held fixed)
+ * with respect to every entry of h1 and of the full n^4 (pq|rs) array, each
+ * treated as an independent variable, times gE:
+ *   grad_h1[p*n+q]            = gE * sum_S w_S gamma_pq(S)
+ *   grad_eri[((p*n+q)*n+r)*n+s] = gE * 1/2 sum_S w_S Gamma_pqrs(S)
+ * where w = (I + L^T)^-1 1 are the integer adjoint weights of the increment
+ * recursion (L_ST = 1 iff T is a proper subtuple of S), and gamma(S), Gamma(S)
+ * are the full-space one- and two-particle density matrices of tuple S's
+ * CASCI ground state (gamma_pq = <E_pq>, Gamma_pqrs = <E_pq E_rs> - d_qr
+ * gamma_ps, frozen core included).  Tuples with w_S != 0 are solved again
+ * (same Davidson), and their density matrices come from a device Gram
+ * contraction of <I|E_pq|c>.  Host outputs: n*n and n^4 doubles.  ETOOLARGE
+ * for a CAS of more than 12 active orbitals.  The ground states must be
+ * non-degenerate for the derivative to exist. */
+mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double gE, void *d_workspace,
+                              size_t ws_bytes, double *grad_h1, double *grad_eri);
+
+/* CASCI energy and full-space density matrices of one tuple (host outputs:
+ * *energy, gamma [n*n], Gamma [n^4], conventions as at mbefci_backward). */
+mbefci_status mbefci_tuple_rdm(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, void *d_workspace,
+                               size_t ws_bytes, double *energy, double *gamma, double *Gamma);
+
 /* Counters of the last solve/run call. */
 mbefci_status mbefci_get_stats(const mbefci_ctx *ctx, mbefci_stats *stats);
 

@@ -64,6 +64,9 @@ SIGNATURES = [
     ("mbefci_string_tables", c_int32, [c_int32, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32),
                                        c_void_p, c_void_p]),
     ("mbefci_get_stats", c_int32, [c_void_p, ctypes.POINTER(Stats)]),
+    ("mbefci_backward", c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, c_void_p, c_void_p]),
+    ("mbefci_tuple_rdm", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,
+                                   c_void_p]),
 ]
 
 _lib = None

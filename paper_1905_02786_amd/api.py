@@ -175,17 +175,43 @@ class Context:
         self._check(rc, allow=(-4,) if allow_noconv else ())
         return e, st
 
-    def run(self, workspace, allow_noconv=False) -> Result:
+    def run(self, workspace, allow_noconv=False, keep=False):
+        """The whole expansion.  keep=True returns (Result, ResultHandle) so
+        that backward() can use the library's copy of the tuple set."""
         if not getattr(workspace, "is_cuda", False):
             raise ValueError("workspace must be a CUDA tensor")
         res = ctypes.c_void_p()
         rc = self.L.mbefci_run(self.ptr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                ctypes.byref(res))
         self._check(rc, allow=(-4,) if allow_noconv else ())
-        try:
-            return _read_result(self.L, res)
-        finally:
-            self.L.mbefci_result_free(res)
+        out = _read_result(self.L, res)
+        if keep:
+            return out, ResultHandle(self.L, res)
+        self.L.mbefci_result_free(res)
+        return out
+
+    def backward(self, handle, workspace, gE=1.0):
+        """(dE/dh1 [n, n], dE/d(pq|rs) [n, n, n, n]) of the summed MBE energy,
+        times gE, with the tuple set of `handle` held fixed."""
+        n = self.norb
+        gh = np.zeros((n, n))
+        ge = np.zeros((n, n, n, n))
+        self._check(self.L.mbefci_backward(self.ptr, handle.ptr, float(gE), ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel(), _p(gh), _p(ge)))
+        return gh, ge
+
+    def tuple_rdm(self, order, tuple_, workspace):
+        """(energy, gamma [n, n], Gamma [n, n, n, n]) of one tuple's CASCI
+        ground state, frozen core included."""
+        n = self.norb
+        t = self._tuples(order, [tuple_] if order > 0 else [()])
+        e = ctypes.c_double()
+        g1 = np.zeros((n, n))
+        g2 = np.zeros((n, n, n, n))
+        self._check(self.L.mbefci_tuple_rdm(self.ptr, order, _p(t) if t.size else None,
+                                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                            ctypes.byref(e), _p(g1), _p(g2)))
+        return e.value, g1, g2
 
     def run_host(self, energy) -> Result:
         """The planner with tuple energies from the Python callable
@@ -261,6 +287,21 @@ class Context:
         s = _lib.Stats()
         self._check(self.L.mbefci_get_stats(self.ptr, ctypes.byref(s)))
         return {name: getattr(s, name) for name, _ in _lib.Stats._fields_}
+
+
+class ResultHandle:
+    """Owns a library-side result (freed with the handle)."""
+
+    def __init__(self, L, ptr):
+        self.L, self.ptr = L, ptr
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                self.L.mbefci_result_free(self.ptr)
+                self.ptr = None
+        except Exception:
+            pass
 
 
 def string_tables(n_active, nel):

@@ -13,6 +13,8 @@ constexpr int kTile = 64;          // determinants per sigma tile (materialised-
 constexpr int kStrip = 16;         // beta columns per workgroup (column-strip variant)
 constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
 constexpr int kMaxKS = 24;         // K steps of 4 covering the padded pair count (<= 92)
+constexpr int kRdmMaxPairs = 16;   // upper 16x16 tile pairs of the RDM Gram per wave (n_A <= 12)
+constexpr int kRdmMaxActive = 12;
 
 // sigma variants: the column strip (W stays in LDS, beta-beta part as a GEMM
 // with the dense beta-string Hamiltonian) and the materialised W (W in HBM,
@@ -20,7 +22,8 @@ constexpr int kMaxKS = 24;         // K steps of 4 covering the padded pair coun
 enum : int32_t { SIGMA_AUTO = 0, SIGMA_STRIP = 1, SIGMA_WMAT = 2 };
 
 // Davidson per-tuple status codes (device side); the public codes are derived.
-enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_STALLED = 4 };
+enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_STALLED = 4,
+                 ST_RESTART = 5 /* running; skips this expansion, restarts from its Ritz vector next */ };
 
 inline int pair_count(int n) { return n * (n + 1) / 2; }
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -83,6 +86,10 @@ struct Batch {
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
     int32_t *status, *m, *iter, *restart, *out_status; // [B]
     int32_t *counter;       // [1] running tuples
+    // RDM pass (backward): Gram partials and sums
+    int nblk_r;
+    double *rdm_part;       // [B][nblk_r][NP*NP]
+    double *rdm_G;          // [B][NP*NP]
 };
 
 // kernels.hip
@@ -101,5 +108,9 @@ size_t sigma_lds_bytes(const ParamLayout &pl);
 size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na);
 bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB);
 hipError_t launch_build_hb(const Batch &b, hipStream_t s);
+hipError_t launch_form_x(const Batch &b, hipStream_t s);
+int rdm_np(int nA);
+size_t rdm_lds_bytes(int NP);
+hipError_t launch_rdm(const Batch &b, VecRef x, double *part, double *G, int nblk_r, hipStream_t s);
 
 }  // namespace mbefci

@@ -919,7 +919,10 @@ hipError_t launch_dots(const Batch &b, VecRef y, int nx_extra, hipStream_t s) {
 // parallel (round-robin) rotation order; one block of 64 threads per tuple.
 __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     const int t = blockIdx.x;
-    if (b.status[t] != ST_RUNNING) return;
+    const int32_t st0 = b.status[t];
+    if (st0 != ST_RUNNING && st0 != ST_RESTART) return;
+    __syncthreads();
+    if (threadIdx.x == 0 && st0 == ST_RESTART) b.status[t] = ST_RUNNING;
     const int m = b.m[t];
     const int mm = m + (m & 1);                  // even number of players
     __shared__ double A[kMaxSpace + 1][kMaxSpace + 2];
@@ -1008,7 +1011,7 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
         b.theta[t] = A[k][k];
         double *y = b.y + (int64_t)t * kMaxSpace;
         for (int i = 0; i < m; ++i) y[i] = Vv[i][k];
-        b.restart[t] = (m >= b.max_space) ? 1 : 0;
+        b.restart[t] = (m >= b.max_space || st0 == ST_RESTART) ? 1 : 0;
     }
 }
 
@@ -1068,9 +1071,10 @@ __global__ void k_converge(Batch b) {
     b.iter[t] = it;
     if (st == ST_RUNNING && it >= b.max_iter) st = ST_MAXITER;
     b.theta_prev[t] = th;
-    if (st == ST_RUNNING && b.restart[t]) {
+    if (b.restart[t]) {   // V_0 = x, S_0 = A x already: the subspace is {x} whatever the outcome
         b.m[t] = 1;
         b.G[(int64_t)t * kMaxSpace * kMaxSpace] = th;
+        b.y[(int64_t)t * kMaxSpace] = 1.0;
     }
     b.status[t] = st;
     if (st == ST_RUNNING) atomicAdd(b.counter, 1);
@@ -1116,14 +1120,17 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int want_norm) {
 }
 
 // 1/|T| into coef[0].  A correction that lies inside the subspace (its
-// projection kept less than 1e-8 of its norm) ends the iteration: converged if
-// the residual is within 1000 r_tol, stalled otherwise.
+// projection kept less than 1e-8 of its norm) adds nothing: the Ritz pair is
+// converged if the residual is below r_tol (an invariant subspace, e.g. a
+// one-determinant space); otherwise the tuple skips this expansion and
+// restarts from its Ritz vector at the next iteration, or has stalled when the
+// subspace already is that one vector.
 __global__ void k_tnorm(Batch b) {
     const int t = blockIdx.x;
     if (threadIdx.x != 0 || b.status[t] != ST_RUNNING) return;
     const double tn = sqrt(sum_parts(b, t, 0));
     if (!(tn > 1e-8 * b.tnorm0[t]) || !(tn > 1e-300) || b.m[t] >= b.max_space) {
-        b.status[t] = (b.rnorm[t] < 1e3 * b.r_tol) ? ST_DONE : ST_STALLED;
+        b.status[t] = b.rnorm[t] < b.r_tol ? ST_DONE : (b.m[t] > 1 ? ST_RESTART : ST_STALLED);
         return;
     }
     b.coef[(int64_t)t * kMaxSpace] = 1.0 / tn;
@@ -1151,6 +1158,141 @@ hipError_t launch_orthonormalize(const Batch &b, hipStream_t s) {
     }
     hipLaunchKernelGGL(k_tnorm, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_store_t, grid, dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- RDMs ------
+// Ritz vector x = sum_i y_i V_i (normalised) into T, for every tuple.
+__global__ __launch_bounds__(256) void k_form_x(Batch b) {
+    const int t = blockIdx.y;
+    const int m = b.m[t];
+    const double *yv = b.y + (int64_t)t * kMaxSpace;
+    double yy[kMaxSpace];
+#pragma unroll
+    for (int i = 0; i < kMaxSpace; ++i) yy[i] = (i < m) ? yv[i] : 0.0;
+    const double *V = b.V + (int64_t)t * b.max_space * b.dim;
+    double *T = b.T + (int64_t)t * b.dim;
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
+        double x = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxSpace; ++i)
+            if (i < m) x += yy[i] * V[(int64_t)i * b.dim + d];
+        T[d] = x;
+    }
+}
+
+hipError_t launch_form_x(const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_form_x, dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// Gram matrix of the transition vectors: column i = p * nA + q holds
+// D_pq(I) = <I|E_pq|x> (a link E_ab|I'> = s|I> of string I' adds s x_{I'} to
+// D_ba(I') ... written here from the ket side: the link (a created, b
+// annihilated) of string I moving I to J gives <I|E_ba|J> = s, so
+// D_ba(I) += s x_J), column nA^2 holds x itself.  G = D^T D over the
+// determinants, accumulated with FP64 MFMA on 32-determinant tiles staged in
+// LDS; every block writes its upper tile pairs to part[t][blk][NP*NP].
+constexpr int kRdmTile = 32;
+
+__global__ __launch_bounds__(256) void k_rdm_gram(Batch b, VecRef xref, double *part, int NP, int nblk_r) {
+    const int t = blockIdx.y;
+    const int nA = b.nA, nn = nA * nA;
+    const int ld = NP + 1;
+    extern __shared__ double Dt[];                       // [32][NP+1]
+    __shared__ int pp[kMaxActive * (kMaxActive + 1) / 2], qq[kMaxActive * (kMaxActive + 1) / 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, ar = lane & 15, kr = lane >> 4;
+    if (tid < b.pl.P) {
+        int p, q;
+        pair_of(tid, p, q);
+        pp[tid] = p;
+        qq[tid] = q;
+    }
+    const double *x = vref(xref, t, b.dim);
+    const int NT = NP / 16, npairs = NT * (NT + 1) / 2;
+    dbl4 acc[kRdmMaxPairs];
+#pragma unroll
+    for (int u = 0; u < kRdmMaxPairs; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = (b.dim + kRdmTile - 1) / kRdmTile;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += nblk_r) {
+        __syncthreads();
+        for (int i = tid; i < kRdmTile * ld; i += 256) Dt[i] = 0.0;
+        __syncthreads();
+        const int j = tid & 31, part8 = tid >> 5;
+        const int64_t d = tile * kRdmTile + j;
+        if (d < b.dim) {
+            const int64_t Ka = d / b.Nb, Kb = d % b.Nb;
+            const uint32_t ma = b.strA[Ka], mb = b.strB[Kb];
+            for (int e = part8; e < b.nentA + b.nentB; e += 8) {
+                const bool alpha = e < b.nentA;
+                const uint32_t L = alpha ? b.linkA[Ka * b.nentA + e] : b.linkB[Kb * b.nentB + (e - b.nentA)];
+                int J, Q;
+                double s;
+                link_decode(L, J, Q, s);
+                const int p = pp[Q], q = qq[Q];
+                const uint32_t m = alpha ? ma : mb;
+                // the annihilated orbital of the link is the one occupied in the string
+                const int an = (m >> p & 1u) ? p : q;
+                const int cr = (an == p) ? q : p;
+                const double xv = alpha ? x[(int64_t)J * b.Nb + Kb] : x[Ka * b.Nb + J];
+                atomicAdd(&Dt[j * ld + an * nA + cr], s * xv);
+            }
+            if (part8 == 0) Dt[j * ld + nn] = x[d];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kRdmMaxPairs; ++u) {
+            const int uu = wave + 4 * u;
+            if (uu < npairs) {
+                int ti = 0, rem = uu;
+                while (rem >= NT - ti) { rem -= NT - ti; ++ti; }
+                const int tj = ti + rem;
+#pragma unroll
+                for (int ks = 0; ks < kRdmTile / 4; ++ks) {
+                    const double a = Dt[(ks * 4 + kr) * ld + ti * 16 + ar];
+                    const double bb = Dt[(ks * 4 + kr) * ld + tj * 16 + ar];
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[u], 0, 0, 0);
+                }
+            }
+        }
+    }
+    double *out = part + ((int64_t)t * nblk_r + blockIdx.x) * NP * NP;
+#pragma unroll
+    for (int u = 0; u < kRdmMaxPairs; ++u) {
+        const int uu = wave + 4 * u;
+        if (uu < npairs) {
+            int ti = 0, rem = uu;
+            while (rem >= NT - ti) { rem -= NT - ti; ++ti; }
+            const int tj = ti + rem;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(int64_t)(ti * 16 + kr + 4 * v) * NP + tj * 16 + ar] = acc[u][v];
+        }
+    }
+}
+
+// G[t] (NP x NP, symmetric) = sum over blocks of the upper tile pairs
+__global__ __launch_bounds__(256) void k_rdm_reduce(const double *part, double *G, int NP, int nblk_r) {
+    const int t = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)NP * NP) return;
+    int i = (int)(idx / NP), j = (int)(idx % NP);
+    if (i / 16 > j / 16) { const int x = i; i = j; j = x; }
+    double s = 0.0;
+    for (int blk = 0; blk < nblk_r; ++blk) s += part[((int64_t)t * nblk_r + blk) * NP * NP + (int64_t)i * NP + j];
+    G[(int64_t)t * NP * NP + idx] = s;
+}
+
+int rdm_np(int nA) { return round_up(nA * nA + 1, 16); }
+
+size_t rdm_lds_bytes(int NP) { return sizeof(double) * (size_t)kRdmTile * (NP + 1); }
+
+hipError_t launch_rdm(const Batch &b, VecRef x, double *part, double *G, int nblk_r, hipStream_t s) {
+    const int NP = rdm_np(b.nA);
+    hipLaunchKernelGGL(k_rdm_gram, dim3(nblk_r, b.B), dim3(256), rdm_lds_bytes(NP), s, b, x, part, NP, nblk_r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rdm_reduce, dim3((unsigned)(((int64_t)NP * NP + 255) / 256), b.B), dim3(256), 0, s, part, G,
+                       NP, nblk_r);
     return hipGetLastError();
 }
 

@@ -192,10 +192,17 @@ struct ClassPlan {
     ParamLayout pl;
     int nblk;
     int variant;
+    bool rdm;
+    int nblk_r, NP;
     size_t fixed_bytes, per_tuple;
 };
 
-void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, bool davidson) {
+int nblk_rdm(int64_t dim) {
+    const int64_t tiles = (dim + 31) / 32;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(32, (tiles + 7) / 8));
+}
+
+void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, bool davidson, bool rdm = false) {
     cp.key = key;
     cp.nC = nC;
     cp.ta = &ctx->table(key.nA, key.na);
@@ -217,6 +224,10 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     if (cp.variant == SIGMA_WMAT) pt += 8 * (size_t)cp.pl.P * cp.dim;            // W
     else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr;                            // H_b
     pt += 8 * (size_t)cp.nblk * (kMaxSpace + 1);             // partials
+    cp.rdm = rdm;
+    cp.NP = rdm_np(key.nA);
+    cp.nblk_r = nblk_rdm(cp.dim);
+    if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP;  // RDM Gram partials and sum
     pt += 8 * (size_t)(kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 6;
     cp.per_tuple = pt + 256;
 }
@@ -297,6 +308,13 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.restart = cv.take<int32_t>(B);
     b.out_status = cv.take<int32_t>(B);
     b.counter = cv.take<int32_t>(1);
+    b.nblk_r = cp.nblk_r;
+    if (cp.rdm) {
+        b.rdm_part = cv.take<double>((size_t)B * cp.nblk_r * cp.NP * cp.NP);
+        b.rdm_G = cv.take<double>((size_t)B * cp.NP * cp.NP);
+    } else {
+        b.rdm_part = b.rdm_G = nullptr;
+    }
     return cv.ok;
 }
 
@@ -356,7 +374,10 @@ mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, dou
 }
 
 // Davidson for one batch; energies/status (public codes) written at out[t].
-mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out) {
+// With `gram` the RDM Gram matrices of the converged vectors (NP*NP each) are
+// copied to the host too.
+mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out,
+                             std::vector<double> *gram = nullptr) {
     hipStream_t s = ctx->stream;
     hipError_t e;
     if ((e = launch_gather(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
@@ -385,6 +406,15 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
         if ((e = launch_dots(b, sm, 1, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     }
     if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    if (gram) {
+        const int NP = rdm_np(b.nA);
+        if ((e = launch_form_x(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        VecRef xr{b.T, b.dim, nullptr, 0};
+        if ((e = launch_rdm(b, xr, b.rdm_part, b.rdm_G, b.nblk_r, s)) != hipSuccess)
+            return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        gram->resize((size_t)b.B * NP * NP);
+        HIPCHK(hipMemcpyAsync(gram->data(), b.rdm_G, 8 * gram->size(), hipMemcpyDeviceToHost, s));
+    }
     std::vector<int32_t> dst(b.B), dit(b.B);
     HIPCHK(hipMemcpyAsync(e_out, b.out_e, 8 * (size_t)b.B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(dst.data(), b.out_status, 4 * (size_t)b.B, hipMemcpyDeviceToHost, s));
@@ -413,10 +443,16 @@ mbefci_status check_device(mbefci_ctx *ctx) {
     return MBEFCI_OK;
 }
 
+// Receives the RDM Gram matrix of one solved tuple (input index, its shape).
+struct RdmSink {
+    virtual void take(int64_t index, const TupleShape &ts, const double *G, int NP) = 0;
+    virtual ~RdmSink() = default;
+};
+
 // Solve a list of tuples (device).  Groups by shape class, batches within
 // the workspace, writes energies/status in input order.
 mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16_t *tuples, void *ws, size_t wsb,
-                           double *energies, int32_t *status) {
+                           double *energies, int32_t *status, RdmSink *sink = nullptr) {
     mbefci_status rc = check_device(ctx);
     if (rc != MBEFCI_OK) return rc;
     if (ntup < 0 || (ntup > 0 && order > 0 && !tuples)) return ctx->fail(MBEFCI_EINVAL, "bad tuple list");
@@ -431,7 +467,9 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
     bool failed = false;
     for (auto &g : groups) {
         ClassPlan cp;
-        plan_class(ctx, g.first.first, g.first.second, cp, true);
+        if (sink && g.first.first.nA > kRdmMaxActive)
+            return ctx->fail(MBEFCI_ETOOLARGE, "RDMs need at most 12 active orbitals");
+        plan_class(ctx, g.first.first, g.first.second, cp, true, sink != nullptr);
         if (cp.fixed_bytes + cp.per_tuple > wsb)
             return ctx->fail(MBEFCI_ENOMEM, "workspace of " + std::to_string(wsb) + " bytes cannot hold one tuple (" +
                                                 std::to_string(cp.fixed_bytes + cp.per_tuple) + " needed)");
@@ -447,13 +485,15 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
             std::vector<const TupleShape *> sh(B);
             for (int t = 0; t < B; ++t) sh[t] = &shapes[idx[start + t]];
             if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) return rc;
-            std::vector<double> e(B);
+            std::vector<double> e(B), gram;
             std::vector<int32_t> st(B);
-            if ((rc = davidson_batch(ctx, b, e.data(), st.data())) != MBEFCI_OK) return rc;
+            if ((rc = davidson_batch(ctx, b, e.data(), st.data(), sink ? &gram : nullptr)) != MBEFCI_OK) return rc;
             for (int t = 0; t < B; ++t) {
                 energies[idx[start + t]] = e[t];
                 status[idx[start + t]] = st[t];
                 failed |= st[t] != MBEFCI_TUPLE_OK;
+                if (sink) sink->take(idx[start + t], shapes[idx[start + t]], gram.data() + (size_t)t * cp.NP * cp.NP,
+                                     cp.NP);
             }
         }
     }
@@ -580,6 +620,95 @@ mbefci_status run_planner(mbefci_ctx *ctx, EnergyFn energy, Result &R) {
     R.total = tot;
     return failed ? ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge") : MBEFCI_OK;
 }
+
+// Full-space density matrices of one CASCI vector from its Gram matrix G
+// (columns p*nA+q: D_pq = <I|E_pq|x>, column nA^2: x), accumulated with
+// weight w into gh (n*n, receives w gamma) and ge (n^4, receives w Gamma / 2):
+//   gamma_pq = G[pq, x],  Gamma_pqrs = G[qp, rs] - delta_qr gamma_ps  (active);
+//   core c (doubly occupied): gamma_cc = 2, Gamma_ccdd = 4, Gamma_cddc = -2
+//   (c != d), Gamma_cccc = 2, and with active p, q: Gamma_pqcc = Gamma_ccpq =
+//   2 gamma_pq, Gamma_pccq = Gamma_cqpc = -gamma_pq.
+void accumulate_rdm(int n, const TupleShape &ts, const double *G, int NP, double w, double *gh, double *ge) {
+    const int nA = (int)ts.act.size(), nn = nA * nA;
+    const std::vector<int32_t> &o = ts.act, &C = ts.core;
+    std::vector<double> gam(nn);
+    for (int p = 0; p < nA; ++p)
+        for (int q = 0; q < nA; ++q) gam[p * nA + q] = G[(size_t)(p * nA + q) * NP + nn];
+    auto E = [&](int p, int q, int r, int s) -> double & { return ge[(((size_t)p * n + q) * n + r) * n + s]; };
+    const double hw = 0.5 * w;
+    for (int p = 0; p < nA; ++p)
+        for (int q = 0; q < nA; ++q) gh[(size_t)o[p] * n + o[q]] += w * gam[p * nA + q];
+    for (int cc : C) gh[(size_t)cc * n + cc] += 2.0 * w;
+    for (int p = 0; p < nA; ++p)
+        for (int q = 0; q < nA; ++q)
+            for (int r = 0; r < nA; ++r)
+                for (int s = 0; s < nA; ++s) {
+                    double v = G[(size_t)(q * nA + p) * NP + (r * nA + s)];
+                    if (q == r) v -= gam[p * nA + s];
+                    E(o[p], o[q], o[r], o[s]) += hw * v;
+                }
+    for (int cc : C)
+        for (int d : C) {
+            if (cc == d) {
+                E(cc, cc, cc, cc) += hw * 2.0;
+            } else {
+                E(cc, cc, d, d) += hw * 4.0;
+                E(cc, d, d, cc) += hw * -2.0;
+            }
+        }
+    for (int cc : C)
+        for (int p = 0; p < nA; ++p)
+            for (int q = 0; q < nA; ++q) {
+                const double g = gam[p * nA + q];
+                E(o[p], o[q], cc, cc) += hw * 2.0 * g;
+                E(cc, cc, o[p], o[q]) += hw * 2.0 * g;
+                E(o[p], cc, cc, o[q]) -= hw * g;
+                E(cc, o[q], o[p], cc) -= hw * g;
+            }
+}
+
+// dE_total / d eps(S) = w_S for the summed increments of Eq. 3 with the tuple
+// set fixed: w_S = 1 - sum_{U computed, U proper superset of S} w_U (integers),
+// evaluated from the highest order down.
+std::vector<std::vector<int64_t>> adjoint_weights(const Result &R) {
+    std::unordered_map<uint64_t, int64_t> acc;
+    for (auto &o : R.orders) {
+        const size_t nt = o.eps.size();
+        for (size_t i = 0; i < nt; ++i) acc[tuple_mask(o.tuples.data() + i * o.k, o.k)] = 0;
+    }
+    std::vector<std::vector<int64_t>> w(R.orders.size());
+    std::vector<int> ix;
+    for (int oi = (int)R.orders.size() - 1; oi >= 0; --oi) {
+        const auto &o = R.orders[oi];
+        const int k = o.k;
+        const size_t nt = o.eps.size();
+        w[oi].resize(nt);
+        for (size_t i = 0; i < nt; ++i) {
+            const int16_t *U = o.tuples.data() + i * k;
+            const int64_t wu = 1 - acc[tuple_mask(U, k)];
+            w[oi][i] = wu;
+            if (wu == 0) continue;
+            for (uint32_t sub = 0; sub + 1 < (1u << k); ++sub) {   // proper subsets, by bit pattern
+                uint64_t m = 0;
+                for (int j = 0; j < k; ++j)
+                    if (sub >> j & 1u) m |= (uint64_t)1 << U[j];
+                auto it = acc.find(m);
+                if (it != acc.end()) it->second += wu;
+            }
+        }
+    }
+    return w;
+}
+
+struct GradSink : RdmSink {
+    int n;
+    const std::vector<int64_t> *w;
+    double *gh, *ge;
+    void take(int64_t index, const TupleShape &ts, const double *G, int NP) override {
+        const double wi = (double)(*w)[index];
+        if (wi != 0.0) accumulate_rdm(n, ts, G, NP, wi, gh, ge);
+    }
+};
 
 }  // namespace
 
@@ -906,6 +1035,64 @@ mbefci_status mbefci_string_tables(int32_t nA, int32_t nel, int64_t *n_strings, 
     if (n_entries) *n_entries = T.nent;
     if (strings) std::memcpy(strings, T.strings.data(), 4 * T.strings.size());
     if (links) std::memcpy(links, T.links.data(), 4 * T.links.size());
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double gE, void *ws, size_t wsb,
+                              double *grad_h1, double *grad_eri) {
+    if (!ctx || !res || !grad_h1 || !grad_eri) return MBEFCI_EINVAL;
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    const int n = ctx->norb;
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    std::vector<double> gh(n2, 0.0), ge(n4, 0.0);
+    const auto w = adjoint_weights(res->r);
+    const double t0 = now_ms();
+    ctx->stats = mbefci_stats{};
+    for (size_t oi = 0; oi < res->r.orders.size(); ++oi) {
+        const auto &o = res->r.orders[oi];
+        // tuples with a non-zero weight only
+        std::vector<int16_t> tl;
+        std::vector<int64_t> wl;
+        for (size_t i = 0; i < o.eps.size(); ++i)
+            if (w[oi][i] != 0) {
+                tl.insert(tl.end(), o.tuples.begin() + i * o.k, o.tuples.begin() + (i + 1) * o.k);
+                wl.push_back(w[oi][i]);
+            }
+        if (wl.empty()) continue;
+        std::vector<double> e(wl.size());
+        std::vector<int32_t> st(wl.size());
+        GradSink sink;
+        sink.n = n;
+        sink.w = &wl;
+        sink.gh = gh.data();
+        sink.ge = ge.data();
+        rc = solve_device(ctx, o.k, (int64_t)wl.size(), tl.data(), ws, wsb, e.data(), st.data(), &sink);
+        if (rc != MBEFCI_OK) return rc;
+    }
+    for (size_t i = 0; i < n2; ++i) grad_h1[i] = gE * gh[i];
+    for (size_t i = 0; i < n4; ++i) grad_eri[i] = gE * ge[i];
+    ctx->stats.solve_ms = now_ms() - t0;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_tuple_rdm(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, void *ws, size_t wsb,
+                               double *energy, double *gamma, double *Gamma) {
+    if (!ctx || !energy || !gamma || !Gamma) return MBEFCI_EINVAL;
+    const int n = ctx->norb;
+    const size_t n2 = (size_t)n * n;
+    std::memset(gamma, 0, 8 * n2);
+    std::memset(Gamma, 0, 8 * n2 * n2);
+    std::vector<int64_t> w1{1};
+    GradSink sink;
+    sink.n = n;
+    sink.w = &w1;
+    sink.gh = gamma;
+    sink.ge = Gamma;
+    int32_t st = 0;
+    mbefci_status rc = solve_device(ctx, order, 1, tuple, ws, wsb, energy, &st, &sink);
+    if (rc != MBEFCI_OK) return rc;
+    for (size_t i = 0; i < n2 * n2; ++i) Gamma[i] *= 2.0;   // the sink stores Gamma / 2
     return MBEFCI_OK;
 }
 

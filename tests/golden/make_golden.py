@@ -10,6 +10,7 @@ Outputs (JSON, one file per workload) next to this script:
   hubbard_U{2,4,8}.json  full-order MBE of the 10-site chain, a = 0 and a = 5.0
   sweep_sample.json    sampled CASCI energies of the 24-orbital order sweep
   large_sample.json    sampled CASCI energies of the 60-orbital problem
+  gradients.npz        MBE gradients (h, (pq|rs)) at orders 2, 4 and full
 """
 from __future__ import annotations
 
@@ -119,7 +120,26 @@ def large():
     sample(P, picks, "large_sample.json")
 
 
+def gradients():
+    """Oracle MBE gradients (h and full (pq|rs)) of the plain problem and the
+    U/t = 4 chain at truncation orders 2, 4 and full order, no screening."""
+    from oracle import rdm
+    out = {}
+    for name, P in (("plain", synth.config_plain(0)), ("hubbard4", synth.config_hubbard(4.0))):
+        for K in (2, 4, 0):
+            t = time.time()
+            res = mbe.run(P, max_order=K if K else None)
+            gh, ge = rdm.mbe_gradient(P, res)
+            key = f"{name}_K{K if K else 'full'}"
+            out[key + "_h"] = gh
+            out[key + "_eri"] = ge
+            out[key + "_E"] = np.array([res.total])
+            print(key, f"{time.time() - t:.1f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "gradients.npz"), **out)
+    print("wrote gradients.npz", flush=True)
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["plain", "hubbard", "sweep", "large"]
+    which = sys.argv[1:] or ["plain", "hubbard", "sweep", "large", "gradients"]
     for w in which:
         globals()[w]()
