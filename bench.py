@@ -21,6 +21,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |ΔE|≤1e-9 Eh"
+# HBM bytes per k_sigma_strip dispatch from the calibrated FETCH_SIZE / WRITE_SIZE
+# passes in profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md, valid only for
+# the kernel source they were taken on.
+TRAFFIC = {"kernels_sha1": "fdcb7558b17b6312d8f0785f93ef8add4cb8c765", "bytes_per_launch": 798330178.9}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -36,11 +40,19 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--per-solve-stride", type=int, default=4)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="bytes of a plain device-to-device copy run 3 times first (HBM counter calibration)")
     return ap.parse_args()
 
 
 def count_tuples(res):
     return sum(len(o.tuples) for o in res.orders)
+
+
+def kernels_sha1():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1905_02786_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
 
 
 def log(msg):
@@ -149,6 +161,14 @@ def main():
     import paper_1905_02786_amd as M
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {args.copy_probe} bytes")
+        del src, dst
     P = synth.config_sweep(0, max_order=args.max_order)
     ws = M.workspace(int(args.ws_gib * (1 << 30)))
     ctx = M.Context.from_problem(P, device=0, profile=1, batched=1)
@@ -176,8 +196,11 @@ def main():
         "davidson": {"iterations_total": st["iterations_total"], "iterations_max": st["iterations_max"]},
         "per_order_ms": [o.wall_ms for o in res.orders],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_sigma_w (D gather + FP64 MFMA W = 1/2 (pq|rs) D)",
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": TRAFFIC["bytes_per_launch"] if kernels_sha1() == TRAFFIC["kernels_sha1"] else None,
+                     "algorithmic_bytes_per_launch": st["sigma_bytes"] / max(1, st["sigma_launches"]),
+                     "kernel": "k_sigma_strip (column-strip sigma: D gather, FP64 MFMA with 1/2 (pq|rs), "
+                               "W scattered through alpha links in LDS)",
                      "per_launch_flops": st["sigma_flops"] / max(1, st["sigma_launches"]),
                      "avg_launch_ms": st["sigma_ms"] / max(1, st["sigma_launches"])},
     }
