@@ -68,6 +68,7 @@ struct Batch {
     double e_const;
     const double *h, *eri;  // resident integrals (n^2, n^4)
     const uint32_t *strA, *strB, *linkA, *linkB;
+    const uint32_t *scatA, *pairB;   // column-strip sigma: alpha scatter table, beta pair links
     const int32_t *act;     // [B * nA] active orbitals (ascending)
     const int32_t *core;    // [B * nC] core orbitals
     double *params;         // [B * pl.stride]
@@ -78,7 +79,7 @@ struct Batch {
     double *Hd, *T;         // [B][dim]
     int sigma_variant;      // SIGMA_STRIP or SIGMA_WMAT
     double *W;              // [B][P][dim] sigma intermediate (SIGMA_WMAT)
-    double *Hb;             // [B][Nb][Nb] beta-string Hamiltonian (SIGMA_STRIP)
+    double *Ha, *Hb;        // [B][Na][Na], [B][Nb][Nb] string Hamiltonians (SIGMA_STRIP; Ha == Hb when na == nb)
     int nblk;               // blocks per tuple for vector kernels
     double *part;           // [B][nblk][kMaxSpace + 1] block partial sums
     double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix

@@ -295,68 +295,72 @@ __global__ __launch_bounds__(256) void k_sigma_g(Batch b, VecRef cref, VecRef sr
 }
 
 // ------------------------------------------------- column-strip variant --
-// sigma = G^a( 1/2 (pq|rs) (D^a + 2 D^b) + k c ) + C H_b^T, where D^a / D^b are
-// the alpha / beta parts of D+, G^a the alpha-link gather, and H_b the
-// beta-string Hamiltonian sum_P k_P E+_P + 1/2 sum_PQ (P|Q) E+_P E+_Q (the
-// alpha-beta coupling E^a E^b appears twice in the pair sum and is carried by
-// the factor 2 on D^b).  A workgroup owns 16 beta columns: for every alpha
-// string K_a it gathers D for the 16 determinants (K_a, B0..B0+15) into LDS,
-// contracts with 1/2 (pq|rs) held as MFMA A fragments in registers (one
-// 16-row M tile per wave), and scatters W through the alpha links of K_a
-// into an LDS strip sigma[:, B0..B0+15].  Each alpha link of one string moves
-// to a different string and the diagonal links all return to K_a itself, so
-// the scatter of one step has no write conflicts.
+// With C the coefficient matrix (alpha strings x beta strings) and E^a_P,
+// E^b_P the spin parts of E+_P, the Hamiltonian splits as
+//   sigma = H_a C + C H_b^T + sum_PQ (P|Q) E^a_P C (E^b_Q)^T,
+// where H_s = sum_P k_P E^s_P + 1/2 sum_PQ (P|Q) E^s_P E^s_Q is the dense
+// string Hamiltonian of one spin (an N_s x N_s matrix per tuple, applied as
+// FP64 MFMA GEMMs).  The strip kernel computes the alpha-beta term: for each
+// alpha string K the beta part D^b_Q(K, I_b) = <I_b|E^b_Q|C(K, .)> uses row K
+// of C only; W = 1/2 (pq|rs) (2 D^b) (FP64 MFMA) is scattered through the
+// alpha links of K.  A workgroup owns 16 beta columns and keeps the sigma
+// strip sigma[:, B0..B0+15] in LDS.
+//
+// On this GPU an FP64 MFMA keeps the SIMD's vector ALU busy for its whole
+// duration, so every vector instruction of the loop costs MFMA time; the
+// loop is written to need few of them: per-item addresses and multipliers are
+// precomputed, the per-string parts of the load addresses are scalar, and the
+// host tables already hold strip byte offsets.
 
-// MFMA waves of the strip kernel: one 16-row M tile each, at most 4 so the
-// waves of a workgroup sit on distinct SIMDs; rows beyond 64 use vector FMA.
-static inline int strip_waves(const ParamLayout &pl) { return pl.Ppad / 16 < 4 ? pl.Ppad / 16 : 4; }
-
-// M tiles past the 4 wave-owned ones (rows >= 64): each wave contracts a
-// quarter of K into a partial 16x16 tile; readers sum the 4 partials.
-static inline int strip_extra_tiles(const ParamLayout &pl) {
-    const int x = pl.Ppad / 16 - strip_waves(pl);
-    return x > 0 ? x : 0;
+// Pair order inside the strip kernel: the n_A diagonal pairs (p,p) first, then
+// the pairs p > q in packed order.  Returns the packed index p(p+1)/2 + q.
+__host__ __device__ inline int strip_pair_packed(int qs, int nA) {
+    if (qs < nA) return qs * (qs + 3) / 2;
+    const int m = qs - nA;
+    int p = 1;
+    while ((p + 1) * p / 2 <= m) ++p;
+    return p * (p + 1) / 2 + (m - p * (p - 1) / 2);
 }
 
-// LDS of the strip kernel; `split` keeps D^a and 2 D^b in separate tiles
-// (plain stores), otherwise one tile takes both through LDS atomic adds.
-static size_t strip_lds(const ParamLayout &pl, int64_t Na, bool split) {
-    const int xr = pl.P > 64 ? pl.P - 64 : 0;   // rows of the extra tiles that hold pairs
-    return sizeof(double) * ((size_t)Na * kStrip + (split ? 2 : 1) * (size_t)pl.Kpad * kStrip +
-                             (size_t)64 * kStrip + (size_t)4 * xr * kStrip + 32);
+// Host tables of the strip kernel (columns in the strip pair order):
+//  * link form [N_s][P]: J in bits 0-19, bit 30 set when the string has a link
+//    through E+_Q, bit 31 its sign (a string has at most one link per pair);
+//  * scatter form [N_s + 1][P + 1]: byte offset J * 128 of the target row of
+//    the sigma strip for off-diagonal links, else the discard row (N_s * 128);
+//    bit 31 the sign; column P and row N_s are all discard.
+constexpr uint32_t kPairJ = 0xFFFFFu, kPairValid = 1u << 30, kPairSign = 1u << 31;
+
+// Compile-time shape of the strip kernel for n_A active orbitals.
+template <int NA>
+struct StripShape {
+    static constexpr int P = NA * (NA + 1) / 2;
+    static constexpr int Ppad = (P + 15) / 16 * 16;
+    static constexpr int Kpad = (P + 3) / 4 * 4;
+    static constexpr int KS = Kpad / 4;                        // MFMA K steps
+    static constexpr int MT = Ppad / 16 < 4 ? Ppad / 16 : 4;   // waves, one 16-row tile each (distinct SIMDs)
+    static constexpr int NX = Ppad / 16 - MT;                  // tiles past row 64, K split over the waves
+    static constexpr int XR = P > 64 ? P - 64 : 0;             // pair rows past 64
+    static constexpr int NTH = 64 * MT;
+    static constexpr int NXI = (XR * 16 + NTH - 1) / NTH;      // items per thread on rows past 64
+    static constexpr int KQ = (KS + 3) / 4;                    // K steps per wave in a tile past row 64
+    static constexpr int NI = 4 + NXI;                         // D / scatter items per thread
+};
+
+// LDS of the strip kernel (doubles): sigma strip [Na + 1][16] (row Na is a
+// discard row for masked-off stores), D [2][Ppad][16] (rows past Kpad are
+// written with zeros and never read), per-wave partial W of rows past 64
+// [2][4][XR][16].
+static size_t strip_lds(const ParamLayout &pl, int64_t Na) {
+    const int xr = pl.P > 64 ? pl.P - 64 : 0;
+    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 2 * (size_t)pl.Ppad * kStrip + 8 * (size_t)xr * kStrip);
 }
 
-// Workgroups per CU of the strip kernel (160 KiB LDS; register file: 3 waves
-// per SIMD without extra tiles, 2 with).
-static int strip_blocks_per_cu(const ParamLayout &pl, int64_t Na, bool split) {
-    const int by_lds = (int)((160 * 1024) / strip_lds(pl, Na, split));
-    const int by_regs = strip_extra_tiles(pl) ? 2 : 3;
-    return by_lds < by_regs ? by_lds : by_regs;
+size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na) { return strip_lds(pl, Na); }
+
+bool strip_fits(const ParamLayout &pl, int64_t Na, int, int) {
+    return pl.nA >= 1 && pl.nA <= kMaxActive && strip_lds(pl, Na) <= 160 * 1024 && Na < (1 << 24);
 }
 
-static bool strip_split(const ParamLayout &pl, int64_t Na) {
-    return strip_blocks_per_cu(pl, Na, true) >= strip_blocks_per_cu(pl, Na, false);
-}
-
-size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na) { return strip_lds(pl, Na, strip_split(pl, Na)); }
-
-constexpr int kMaxR = 4;   // gather items per thread: ceil(n_links * 16 / threads) <= 3 for n_A <= 13
-
-bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB) {
-    const int nth = 64 * strip_waves(pl);
-    return strip_lds_bytes(pl, Na) <= 150 * 1024 && pl.Kpad / 4 <= kMaxKS && strip_extra_tiles(pl) <= 2 &&
-           (nentA * kStrip + nth - 1) / nth <= kMaxR && (nentB * kStrip + nth - 1) / nth <= kMaxR;
-}
-
-// Software-pipelined: the alpha links and c values of step K_a + 1 are loaded
-// into registers while step K_a runs its MFMA and scatter.  Thread items:
-// alpha item (e, col) = (item >> 4, item & 15) over the alpha links of K_a
-// (the same item later scatters W through that link), beta item
-// (col, e) = (item / n_links_b, item % n_links_b) over the fixed beta links
-// of the strip's columns.  D = D^a + 2 D^b: an entry receives at most one
-// alpha and one beta term, added atomically in LDS (two-term sums commute, so
-// the value does not depend on their order); writers reset their entries
-// after the MFMA.
 // Workgroups are handed to the 8 XCDs round-robin by linear id; map id L to
 // (tuple, strip) so that every strip of tuple t runs on XCD t % 8 and the
 // strips of one tuple are dispatched back to back: its vector stays in that
@@ -368,224 +372,270 @@ __device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, i
     return t < B;
 }
 
-template <int MT, int NX, bool SPLIT>
-__global__ __launch_bounds__(64 * MT) void k_sigma_strip(Batch b, VecRef cref, VecRef sref, double shift,
-                                                         int skip_done) {
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+    const int src = ((int)(threadIdx.x & 63) ^ mask) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(src, (int)__double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, (int)__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// One workgroup per (tuple, 16-column strip), MT waves.  Thread items: the
+// pair rows Q = 16 w + (lane >> 4) + 4 v (v < 4) of its wave's MFMA output
+// tile, column lane & 15, plus rows past 64 spread over the block.  The same
+// thread writes D for its items and scatters W of those items (rows < 64
+// straight from the MFMA registers).  The diagonal pairs are rows 0..n_A-1,
+// all in wave 0, which sums them for the string with a lane mask and two
+// cross-lane steps.  Software pipeline over the alpha strings, one barrier
+// per step: in the step of string K the block
+//   - runs the MFMA of string K on D[K & 1] (results read one step later),
+//   - stores the partial rows past 64 of W(K-1) and sums its diagonal pairs,
+//   - scatters W of string K-2 into the LDS strip and adds its diagonal sum,
+//   - writes D of string K+1 into D[(K+1) & 1] from C row K+1,
+//   - loads row K+2 of C at the beta-link columns of its items and the
+//     scatter-table row of string K+2.
+// Each phase touches a buffer no other phase of the same step touches, and
+// the scatter of one string has no write conflicts: each link of a string
+// reaches a different string, and its diagonal sum goes to the string itself.
+// Masked-off stores go to the discard row, so the step has no branches
+// besides wave 0's diagonal sum.
+template <int NA>
+__global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b, VecRef cref, VecRef sref,
+                                                                          double shift, int skip_done) {
+    using S = StripShape<NA>;
+    constexpr int P = S::P, KP = S::Kpad, DR = S::Ppad, KS = S::KS, NX = S::NX, XR = S::XR, NTH = S::NTH,
+                  NI = S::NI, KQ = S::KQ, NXA = NX > 0 ? NX : 1;
+    constexpr uint32_t DB = DR * kStrip * sizeof(double);   // byte stride of the D buffers
     const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
     int t, strip_id;
     if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
     if (skip_done && b.status[t] != ST_RUNNING) return;
-    constexpr int NTH = 64 * MT;
-    const ParamLayout &pl = b.pl;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t Na = b.Na, Nb = b.Nb;
-    const int B0 = strip_id * kStrip;
-    const int ncol = (int)min((int64_t)kStrip, Nb - B0);
-    const int nentA = b.nentA, nentB = b.nentB, ndiag = b.na;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ar = lane & 15, kr = lane >> 4;
+    // determinant indices fit 32 bits (dim <= C(13,6)^2)
+    const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
+    const uint32_t B0 = (uint32_t)strip_id * kStrip;
+    const bool colok = B0 + ar < Nb;
     extern __shared__ double lds[];
-    double *strip = lds;                               // [Na][16]
-    double *D = strip + Na * kStrip;                   // [Kpad][16]  D^a (+ 2 D^b unless SPLIT)
-    double *Db = SPLIT ? D + pl.Kpad * kStrip : D;     // [Kpad][16]  2 D^b when SPLIT
-    double *Wt = D + (SPLIT ? 2 : 1) * pl.Kpad * kStrip;   // [64][16] rows of the wave-owned tiles
-    const int XR = pl.P > 64 ? pl.P - 64 : 0;          // pair rows past 64
-    double *Wp = Wt + 64 * kStrip;                     // [4][XR][16] partial rows >= 64, per wave
-    double *kx = Wp + 4 * XR * kStrip;                 // [32] k of rows >= 64
+    double *strip = lds;                   // [Na + 1][16]
+    double *D = strip + (Na + 1) * kStrip; // [2][DR][16]
+    double *Wx = D + 2 * DR * kStrip;      // [2][4][XR][16]
+    char *const sbase = reinterpret_cast<char *>(strip) + ar * sizeof(double);
+    double *const dump = strip + Na * kStrip + ar;
+    const ParamLayout &pl = b.pl;
     const double *prm = b.params + (int64_t)t * pl.stride;
     const double *c = vref(cref, t, b.dim);
     double *sg = const_cast<double *>(vref(sref, t, b.dim));
-    const int KS = pl.Kpad / 4;
-    const int ar = lane & 15, kr = lane >> 4;
-    double af[kMaxKS];
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
+                                                                        (int)(b.dim * sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(b.scatA), (short)0, (int)((Na + 1) * (P + 1) * sizeof(uint32_t)), 0x00020000);
+
+    // A fragments of 1/2 (pq|rs) in the strip pair order: this wave's rows,
+    // and its K quarter of the rows past 64
+    auto eri_at = [&](int r, int k) -> double {
+        return (r < P && k < P) ? prm[pl.off_eri + strip_pair_packed(r, NA) * KP + strip_pair_packed(k, NA)] : 0.0;
+    };
+    double af[KS];
 #pragma unroll
-    for (int ks = 0; ks < kMaxKS; ++ks)
-        af[ks] = (ks < KS) ? prm[pl.off_eri + (wave * 16 + ar) * pl.Kpad + ks * 4 + kr] : 0.0;
-    double kv[4];
+    for (int ks = 0; ks < KS; ++ks) af[ks] = eri_at(w * 16 + ar, ks * 4 + kr);
+    double afx[NXA][KQ];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int row = wave * 16 + kr + 4 * v;
-        kv[v] = row < pl.P ? prm[pl.off_k + row] : 0.0;
-    }
-    for (int i = tid; i < Na * kStrip; i += NTH) strip[i] = 0.0;
-    for (int i = tid; i < (SPLIT ? 2 : 1) * pl.Kpad * kStrip; i += NTH) D[i] = 0.0;
-    // extra tiles: this wave's quarter of the K steps
-    const int KQ = (KS + 3) / 4, ks0 = wave * KQ;
-    double afx[NX > 0 ? NX : 1][6];
+    for (int x = 0; x < NXA; ++x)
 #pragma unroll
-    for (int x = 0; x < NX; ++x) {
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const int ks = ks0 + j;
-            afx[x][j] = (j < KQ && ks < KS) ? prm[pl.off_eri + (64 + 16 * x + ar) * pl.Kpad + ks * 4 + kr] : 0.0;
+        for (int j = 0; j < KQ; ++j) {
+            const int ks = w * KQ + j;
+            afx[x][j] = (x < NX && ks < KS) ? eri_at(64 + 16 * x + ar, ks * 4 + kr) : 0.0;
         }
-    }
-    for (int i = tid; i < 16 * NX; i += NTH) kx[i] = 64 + i < pl.P ? prm[pl.off_k + 64 + i] : 0.0;
-    // fixed beta items: D^b offset | sign bit 31, and the source column in a c row
-    int bq[kMaxR], bj[kMaxR];
+    // items: pair row, D slot (LDS byte address in buffer 0), beta link
+    // (byte offset in a row of C, 2 * sign), scatter-table byte offset
+    int qi[NI];
+    uint32_t dsl[NI], boff[NI], qa[NI];
+    double bmul[NI];
 #pragma unroll
-    for (int r = 0; r < kMaxR; ++r) {
-        const int item = tid + r * NTH;
-        bq[r] = -1;
-        bj[r] = 0;
-        if (item < nentB * kStrip) {
-            const int col = item / nentB, e = item % nentB;
-            if (col < ncol) {
-                const uint32_t L = b.linkB[(int64_t)(B0 + col) * nentB + e];
-                bq[r] = (int)((((L >> 20) & 0x3FFu) * kStrip + col) | (L & 0x80000000u));
-                bj[r] = (int)(L & 0xFFFFFu);
-            }
-        }
-    }
-    // alpha items: link e = (tid >> 4) + r * NTH / 16 of the current string, column ar (= tid & 15)
-    const int ae0 = tid >> 4;
-    constexpr int ESTEP = NTH / 16;
-    const bool colok = ar < ncol;
-    // prefetch step 0
-    uint32_t lw[kMaxR];
-    double ca[kMaxR], cb[kMaxR];
+    for (int v = 0; v < 4; ++v) qi[v] = w * 16 + kr + 4 * v;
 #pragma unroll
-    for (int r = 0; r < kMaxR; ++r) {
-        const bool av = colok && ae0 + r * ESTEP < nentA;
-        lw[r] = av ? b.linkA[ae0 + r * ESTEP] : 0u;
-        ca[r] = av ? c[(int64_t)(lw[r] & 0xFFFFFu) * Nb + B0 + ar] : 0.0;
-        cb[r] = bq[r] != -1 ? c[bj[r]] : 0.0;
+    for (int r = 0; r < NI - 4; ++r) {
+        const int j = tid + NTH * r;
+        qi[4 + r] = j < XR * 16 ? 64 + (j >> 4) : P;
     }
-    uint32_t sa = b.strA[0];
-    double cc = ar < ncol ? c[B0 + ar] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const bool ok = colok && qi[i] < P;
+        const uint32_t eb = ok ? b.pairB[(B0 + ar) * (uint32_t)P + qi[i]] : 0u;
+        const bool vb = (eb & kPairValid) != 0;
+        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0u;
+        bmul[i] = vb ? ((eb & kPairSign) ? -2.0 : 2.0) : 0.0;
+        qa[i] = (uint32_t)(qi[i] < P ? qi[i] : P) * (uint32_t)sizeof(uint32_t);
+        dsl[i] = (uint32_t)(D + qi[i] * kStrip + ar - lds) * (uint32_t)sizeof(double);
+    }
+    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += NTH) strip[i] = 0.0;
+    for (int i = tid; i < 2 * DR * kStrip; i += NTH) D[i] = 0.0;
+
+    const uint32_t rowC = Nb * (uint32_t)sizeof(double), rowS = (P + 1) * (uint32_t)sizeof(uint32_t);
+    auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    auto load_c = [&](uint32_t s, int i) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[i], s * rowC, 0));
+    };
+    auto load_s = [&](uint32_t s, int i) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, qa[i], s * rowS, 0);
+    };
+
+    double cb[NI];
+    uint32_t en1[NI], en0[NI], em1[NI], em2[NI];   // scatter entries of strings K+1, K, K-1, K-2
+    double w2[4];                                  // W of string K-2 on this thread's wave rows
+    double dg1 = 0.0;                              // diagonal sum of the previous string (wave 0)
+    // prologue: D of string 0; C row 1 and the entries of strings 0 and 1
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        cb[i] = load_c(0, i);
+        en0[i] = load_s(0, i);
+        em1[i] = em2[i] = load_s(Na, i);   // discard row
+    }
     __syncthreads();
-    for (int64_t Ka = 0; Ka < Na; ++Ka) {
-        // P1: write D for step Ka
-        uint32_t cur[kMaxR];
 #pragma unroll
-        for (int r = 0; r < kMaxR; ++r) {
-            cur[r] = lw[r];
-            if (colok && ae0 + r * ESTEP < nentA) {
-                const double s = (lw[r] >> 31) ? -1.0 : 1.0;
-                if (SPLIT) D[((lw[r] >> 20) & 0x3FFu) * kStrip + ar] = s * ca[r];
-                else atomicAdd(&D[((lw[r] >> 20) & 0x3FFu) * kStrip + ar], s * ca[r]);
+    for (int i = 0; i < NI; ++i) *lds_at(dsl[i]) = bmul[i] * cb[i];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        cb[i] = load_c(Na > 1 ? 1u : 0u, i);
+        en1[i] = load_s(Na > 1 ? 1u : Na, i);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w2[v] = 0.0;
+    uint32_t sa1 = 0u;   // alpha string K-1
+    dbl4 accA[1 + NXA], accB[1 + NXA];   // the wave tile, then the tiles past row 64
+#pragma unroll
+    for (int j = 0; j < 1 + NXA; ++j) accA[j] = accB[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+
+    // Pipeline step of string K: MFMA of K into `an` (read back one step
+    // later, so no wave waits for its own MFMA results), epilogue of K-1
+    // from `ao`, scatter of K-2, D of K+1, loads of K+2.  Steps past the last
+    // string run on stale data whose results are discarded: their scatter
+    // entries come from the discard row and their diagonal sums are dropped.
+    auto step = [&](uint32_t K, dbl4 (&an)[1 + NXA], dbl4 (&ao)[1 + NXA]) {
+        const double *Dk = D + (K & 1) * DR * kStrip;
+        {
+            double bv[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bv[ks] = Dk[(ks * 4 + kr) * kStrip + ar];
+            dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
+            an[0] = a;
+        }
+        if (NX > 0) {
+            // tiles past row 64: this wave's K quarter (its own B operands)
+            double bx[KQ];
+#pragma unroll
+            for (int j = 0; j < KQ; ++j) {
+                const int ks = w * KQ + j;
+                bx[j] = Dk[((ks < KS ? ks : 0) * 4 + kr) * kStrip + ar];
             }
-            if (bq[r] != -1) {
-                const double v = (bq[r] < 0 ? -2.0 : 2.0) * cb[r];
-                if (SPLIT) Db[bq[r] & 0x7FFFFFFF] = v;
-                else atomicAdd(&D[bq[r] & 0x7FFFFFFF], v);
+#pragma unroll
+            for (int x = 0; x < NXA; ++x) {
+                dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < KQ; ++j) a = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], bx[j], a, 0, 0, 0);
+                an[1 + x] = a;
             }
         }
-        const uint32_t cur_sa = sa;
-        const double cur_cc = cc;
-        __syncthreads();
-        // P2: links of step Ka+1, MFMA of step Ka, c values of step Ka+1
-        const bool more = Ka + 1 < Na;
-        if (more) {
+        // epilogue of string K-1: partial rows past 64 to LDS
+        if (NX > 0) {
+            double *wx = Wx + (((K + 1) & 1) * 4 + w) * XR * kStrip;
 #pragma unroll
-            for (int r = 0; r < kMaxR; ++r)
-                if (colok && ae0 + r * ESTEP < nentA) lw[r] = b.linkA[(Ka + 1) * nentA + ae0 + r * ESTEP];
-            sa = b.strA[Ka + 1];
-        }
-        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < kMaxKS; ks += 2) {
-            if (ks < KS) {
-                const int o = (ks * 4 + kr) * kStrip + ar;
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], SPLIT ? D[o] + Db[o] : D[o], acc0, 0, 0, 0);
-            }
-            if (ks + 1 < KS) {
-                const int o = ((ks + 1) * 4 + kr) * kStrip + ar;
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks + 1], SPLIT ? D[o] + Db[o] : D[o], acc1, 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = wave * 16 + kr + 4 * v;   // f64 16x16x4 output: lane>>4 + 4*item
-            Wt[row * kStrip + ar] = acc0[v] + acc1[v] + kv[v] * cur_cc;
-        }
-#pragma unroll
-        for (int x = 0; x < NX; ++x) {
-            {
-                dbl4 ax = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int j = 0; j < 6; ++j) {
-                    const int ks = ks0 + j;
-                    if (j < KQ && ks < KS) {
-                        const int o = (ks * 4 + kr) * kStrip + ar;
-                        ax = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], SPLIT ? D[o] + Db[o] : D[o], ax, 0, 0, 0);
-                    }
-                }
-                double *wp = Wp + wave * XR * kStrip;
+            for (int x = 0; x < NXA; ++x)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int rr = 16 * x + kr + 4 * v;
-                    if (rr < XR) wp[rr * kStrip + ar] = ax[v];
+                    const int r = 16 * x + kr + 4 * v;
+                    *(r < XR ? wx + r * kStrip + ar : dump) = ao[1 + x][v];
                 }
-            }
         }
-        if (more) {
-            const double *crow = c + (Ka + 1) * Nb;
+        // scatter of string K-2 through its off-diagonal alpha links
+        const double *wx2 = Wx + (K & 1) * 4 * XR * kStrip;
 #pragma unroll
-            for (int r = 0; r < kMaxR; ++r) {
-                if (colok && ae0 + r * ESTEP < nentA) ca[r] = c[(int64_t)(lw[r] & 0xFFFFFu) * Nb + B0 + ar];
-                if (bq[r] != -1) cb[r] = crow[bj[r]];
+        for (int i = 0; i < NI; ++i) {
+            const uint32_t e = em2[i];
+            double wv;
+            if (i < 4) {
+                wv = w2[i < 4 ? i : 0];
+            } else {
+                const int r = qi[i] < P ? qi[i] - 64 : 0;
+                wv = wx2[r * kStrip + ar] + wx2[(XR + r) * kStrip + ar] + wx2[(2 * XR + r) * kStrip + ar] +
+                     wx2[(3 * XR + r) * kStrip + ar];
             }
-            cc = ar < ncol ? crow[B0 + ar] : 0.0;
+            double *d = reinterpret_cast<double *>(sbase + (e & 0x7FFFFFFFu));
+            *d += (e & kPairSign) ? -wv : wv;
         }
-        __syncthreads();
-        // P3: reset D^a, scatter W through the alpha links of Ka
-        // col is always tid & 15 here, whose c value is cur_cc
-        auto wval = [&](int Q, int col) -> double {
-            if (NX == 0 || Q < 64) return Wt[Q * kStrip + col];
-            const double *wp = Wp + (Q - 64) * kStrip + col;
-            const int ws = XR * kStrip;
-            return wp[0] + wp[ws] + wp[2 * ws] + wp[3 * ws] + kx[Q - 64] * cur_cc;
-        };
+        // D of string K+1 (C row K+1 was loaded one step ago)
 #pragma unroll
-        for (int r = 0; r < kMaxR; ++r) {
-            const int e = ae0 + r * ESTEP;
-            if (!SPLIT && bq[r] != -1) D[bq[r] & 0x7FFFFFFF] = 0.0;
-            if (colok && e < nentA) {
-                const int Q = (int)((cur[r] >> 20) & 0x3FFu);
-                D[Q * kStrip + ar] = 0.0;
-                if (e >= ndiag) {
-                    const double s = (cur[r] >> 31) ? -1.0 : 1.0;
-                    strip[(int64_t)(cur[r] & 0xFFFFFu) * kStrip + ar] += s * wval(Q, ar);
-                }
-            }
+        for (int i = 0; i < NI; ++i) *lds_at(dsl[i] + ((K + 1) & 1) * DB) = bmul[i] * cb[i];
+        // loads of string K+2
+        const uint32_t K2c = K + 2 < Na ? K + 2 : Na - 1, K2s = K + 2 < Na ? K + 2 : Na;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            em2[i] = em1[i];
+            em1[i] = en0[i];
+            en0[i] = en1[i];
+            cb[i] = load_c(K2c, i);
+            en1[i] = load_s(K2s, i);
         }
-        if (tid < kStrip) {
-            double acc = 0.0;
-            for (uint32_t x = cur_sa; x; x &= x - 1) {
-                const int p = __ffs(x) - 1;
-                acc += wval(p * (p + 3) / 2, tid);
-            }
-            strip[Ka * kStrip + tid] += acc;
+        double w1[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w1[v] = ao[0][v];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w2[v] = w1[v];
+        // diagonal pairs: rows 0..NA-1 of wave 0.  Add the sum of string K-2,
+        // then form the sum of string K-1 (lane mask of its occupied orbitals,
+        // fixed order: v within the lane, then lanes (kr, kr^1), then (kr, kr^2)).
+        if (w == 0) {
+            if (kr == 0 && K >= 2 && K - 2 < Na) strip[(K - 2) * kStrip + ar] += dg1;
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (4 * v < NA) s += ((sa1 >> (kr + 4 * v)) & 1u) ? ao[0][v] : 0.0;
+            s += shfl_xor_d(s, 16);
+            s += shfl_xor_d(s, 32);
+            dg1 = s;
         }
+        const uint32_t sk = b.strA[K < Na ? K : Na - 1];
+        sa1 = K < Na ? sk : 0u;
         __syncthreads();
+    };
+    for (uint32_t K = 0; K < Na + 2; K += 2) {
+        step(K, accA, accB);
+        step(K + 1, accB, accA);
     }
-    for (int64_t i = tid; i < Na * kStrip; i += NTH) {
-        const int64_t row = i / kStrip;
-        const int col = (int)(i % kStrip);
-        if (col < ncol) {
-            const int64_t d = row * Nb + B0 + col;
+    for (uint32_t i = tid; i < Na * kStrip; i += NTH) {
+        const uint32_t row = i / kStrip, col = i % kStrip;
+        if (B0 + col < Nb) {
+            const uint32_t d = row * Nb + B0 + col;
             sg[d] = strip[i] + shift * c[d];
         }
     }
 }
 
-// H_b (symmetric, Nb x Nb) per tuple; thread J writes row J:
-// H_b e_J = sum_{links (Q,K,s) of J} s [ k_Q e_K + 1/2 sum_{links (P,I,s') of K} s' (P|Q) e_I ].
-__global__ __launch_bounds__(64) void k_build_hb(Batch b) {
+// Dense string Hamiltonian of one spin (symmetric, N x N per tuple); thread J
+// writes row J:
+//   H e_J = sum_{links (Q,K,s) of J} s [ k_Q e_K + 1/2 sum_{links (P,I,s') of K} s' (P|Q) e_I ].
+__global__ __launch_bounds__(64) void k_build_h(Batch b, int beta) {
     const int t = blockIdx.y;
+    const int64_t N = beta ? b.Nb : b.Na;
+    const int nent = beta ? b.nentB : b.nentA;
+    const uint32_t *links = beta ? b.linkB : b.linkA;
     const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (J >= b.Nb) return;
+    if (J >= N) return;
     const ParamLayout &pl = b.pl;
     const double *prm = b.params + (int64_t)t * pl.stride;
-    double *row = b.Hb + ((int64_t)t * b.Nb + J) * b.Nb;
-    for (int64_t i = 0; i < b.Nb; ++i) row[i] = 0.0;
-    const uint32_t *lj = b.linkB + J * b.nentB;
-    for (int e = 0; e < b.nentB; ++e) {
+    double *row = (beta ? b.Hb : b.Ha) + ((int64_t)t * N + J) * N;
+    for (int64_t i = 0; i < N; ++i) row[i] = 0.0;
+    const uint32_t *lj = links + J * nent;
+    for (int e = 0; e < nent; ++e) {
         int K, Q;
         double s;
         link_decode(lj[e], K, Q, s);
         row[K] += s * prm[pl.off_k + Q];
-        const uint32_t *lk = b.linkB + (int64_t)K * b.nentB;
-        for (int f = 0; f < b.nentB; ++f) {
+        const uint32_t *lk = links + (int64_t)K * nent;
+        for (int f = 0; f < nent; ++f) {
             int I, P;
             double s2;
             link_decode(lk[f], I, P, s2);
@@ -596,20 +646,22 @@ __global__ __launch_bounds__(64) void k_build_hb(Batch b) {
 
 hipError_t launch_build_hb(const Batch &b, hipStream_t s) {
     if (b.sigma_variant != SIGMA_STRIP) return hipSuccess;
-    dim3 grid((unsigned)((b.Nb + 63) / 64), b.B);
-    hipLaunchKernelGGL(k_build_hb, grid, dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Nb + 63) / 64), b.B), dim3(64), 0, s, b, 1);
+    if (b.Ha != b.Hb)
+        hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Na + 63) / 64), b.B), dim3(64), 0, s, b, 0);
     return hipGetLastError();
 }
 
-// sigma += C H_b per tuple (C = c as Na x Nb row-major, H_b symmetric):
-// 64 x 64 output tile per block of 4 waves, each wave 32 x 32 = 2 x 2 FP64
-// MFMA tiles; K in chunks of 16 staged through LDS.
-__global__ __launch_bounds__(256) void k_gemm_hb(Batch b, VecRef cref, VecRef sref, int skip_done) {
+// sigma += H_a C + C H_b per tuple (C = c as Na x Nb row-major; H_a, H_b
+// symmetric): 64 x 64 output tile per block of 4 waves, each wave 32 x 32 =
+// 2 x 2 FP64 MFMA tiles; K in chunks of 16 staged through LDS.
+__global__ __launch_bounds__(256) void k_gemm_h(Batch b, VecRef cref, VecRef sref, int skip_done) {
     const int t = blockIdx.z;
     if (skip_done && b.status[t] != ST_RUNNING) return;
     const int64_t Na = b.Na, Nb = b.Nb;
     const double *C = vref(cref, t, b.dim);
     double *S = const_cast<double *>(vref(sref, t, b.dim));
+    const double *Ha = b.Ha + (int64_t)t * Na * Na;
     const double *Hb = b.Hb + (int64_t)t * Nb * Nb;
     __shared__ double As[64][17];
     __shared__ double Bs[16][65];
@@ -621,17 +673,7 @@ __global__ __launch_bounds__(256) void k_gemm_hb(Batch b, VecRef cref, VecRef sr
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int64_t k0 = 0; k0 < Nb; k0 += 16) {
-        __syncthreads();
-        for (int i = tid; i < 64 * 16; i += 256) {
-            const int r = i >> 4, kk = i & 15;
-            const int64_t gr = r0 + r, gk = k0 + kk;
-            As[r][kk] = (gr < Na && gk < Nb) ? C[gr * Nb + gk] : 0.0;
-            const int kb = i >> 6, cj = i & 63;
-            const int64_t gk2 = k0 + kb, gc = c0 + cj;
-            Bs[kb][cj] = (gk2 < Nb && gc < Nb) ? Hb[gk2 * Nb + gc] : 0.0;
-        }
-        __syncthreads();
+    auto tile = [&]() {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             double a[2], bb[2];
@@ -644,6 +686,34 @@ __global__ __launch_bounds__(256) void k_gemm_hb(Batch b, VecRef cref, VecRef sr
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
         }
+    };
+    // H_a C: A = H_a rows r0.., B = C rows k
+    for (int64_t k0 = 0; k0 < Na; k0 += 16) {
+        __syncthreads();
+        for (int i = tid; i < 64 * 16; i += 256) {
+            const int r = i >> 4, kk = i & 15;
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            As[r][kk] = (gr < Na && gk < Na) ? Ha[gr * Na + gk] : 0.0;
+            const int kb = i >> 6, cj = i & 63;
+            const int64_t gk2 = k0 + kb, gc = c0 + cj;
+            Bs[kb][cj] = (gk2 < Na && gc < Nb) ? C[gk2 * Nb + gc] : 0.0;
+        }
+        __syncthreads();
+        tile();
+    }
+    // C H_b: A = C rows r0.., B = H_b rows k
+    for (int64_t k0 = 0; k0 < Nb; k0 += 16) {
+        __syncthreads();
+        for (int i = tid; i < 64 * 16; i += 256) {
+            const int r = i >> 4, kk = i & 15;
+            const int64_t gr = r0 + r, gk = k0 + kk;
+            As[r][kk] = (gr < Na && gk < Nb) ? C[gr * Nb + gk] : 0.0;
+            const int kb = i >> 6, cj = i & 63;
+            const int64_t gk2 = k0 + kb, gc = c0 + cj;
+            Bs[kb][cj] = (gk2 < Nb && gc < Nb) ? Hb[gk2 * Nb + gc] : 0.0;
+        }
+        __syncthreads();
+        tile();
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -657,30 +727,30 @@ __global__ __launch_bounds__(256) void k_gemm_hb(Batch b, VecRef cref, VecRef sr
             }
 }
 
-template <int MT, int NX, bool SPLIT>
-static hipError_t launch_strip_mt(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+template <int NA>
+static hipError_t launch_strip_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    hipLaunchKernelGGL((k_sigma_strip<MT, NX, SPLIT>), grid, dim3(64 * MT), strip_lds(b.pl, b.Na, SPLIT), s, b, c, sig, shift,
-                       skip);
+    hipLaunchKernelGGL(k_sigma_strip<NA>, grid, dim3(StripShape<NA>::NTH), strip_lds(b.pl, b.Na), s, b, c, sig,
+                       shift, skip);
     return hipGetLastError();
 }
 
 static hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
-    const bool split = strip_split(b.pl, b.Na);
-    switch ((strip_waves(b.pl) * 4 + strip_extra_tiles(b.pl)) * 2 + (split ? 1 : 0)) {
-        case 8: return launch_strip_mt<1, 0, false>(b, c, sig, shift, skip, s);
-        case 9: return launch_strip_mt<1, 0, true>(b, c, sig, shift, skip, s);
-        case 16: return launch_strip_mt<2, 0, false>(b, c, sig, shift, skip, s);
-        case 17: return launch_strip_mt<2, 0, true>(b, c, sig, shift, skip, s);
-        case 24: return launch_strip_mt<3, 0, false>(b, c, sig, shift, skip, s);
-        case 25: return launch_strip_mt<3, 0, true>(b, c, sig, shift, skip, s);
-        case 32: return launch_strip_mt<4, 0, false>(b, c, sig, shift, skip, s);
-        case 33: return launch_strip_mt<4, 0, true>(b, c, sig, shift, skip, s);
-        case 34: return launch_strip_mt<4, 1, false>(b, c, sig, shift, skip, s);
-        case 35: return launch_strip_mt<4, 1, true>(b, c, sig, shift, skip, s);
-        case 36: return launch_strip_mt<4, 2, false>(b, c, sig, shift, skip, s);
-        case 37: return launch_strip_mt<4, 2, true>(b, c, sig, shift, skip, s);
+    switch (b.nA) {
+        case 1: return launch_strip_na<1>(b, c, sig, shift, skip, s);
+        case 2: return launch_strip_na<2>(b, c, sig, shift, skip, s);
+        case 3: return launch_strip_na<3>(b, c, sig, shift, skip, s);
+        case 4: return launch_strip_na<4>(b, c, sig, shift, skip, s);
+        case 5: return launch_strip_na<5>(b, c, sig, shift, skip, s);
+        case 6: return launch_strip_na<6>(b, c, sig, shift, skip, s);
+        case 7: return launch_strip_na<7>(b, c, sig, shift, skip, s);
+        case 8: return launch_strip_na<8>(b, c, sig, shift, skip, s);
+        case 9: return launch_strip_na<9>(b, c, sig, shift, skip, s);
+        case 10: return launch_strip_na<10>(b, c, sig, shift, skip, s);
+        case 11: return launch_strip_na<11>(b, c, sig, shift, skip, s);
+        case 12: return launch_strip_na<12>(b, c, sig, shift, skip, s);
+        case 13: return launch_strip_na<13>(b, c, sig, shift, skip, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -688,13 +758,13 @@ static hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shif
 hipError_t init_kernels() {
     hipError_t e = hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    const void *strips[] = {
-        (const void *)k_sigma_strip<1, 0, false>, (const void *)k_sigma_strip<1, 0, true>,
-        (const void *)k_sigma_strip<2, 0, false>, (const void *)k_sigma_strip<2, 0, true>,
-        (const void *)k_sigma_strip<3, 0, false>, (const void *)k_sigma_strip<3, 0, true>,
-        (const void *)k_sigma_strip<4, 0, false>, (const void *)k_sigma_strip<4, 0, true>,
-        (const void *)k_sigma_strip<4, 1, false>, (const void *)k_sigma_strip<4, 1, true>,
-        (const void *)k_sigma_strip<4, 2, false>, (const void *)k_sigma_strip<4, 2, true>};
+    const void *strips[] = {(const void *)k_sigma_strip<1>,  (const void *)k_sigma_strip<2>,
+                            (const void *)k_sigma_strip<3>,  (const void *)k_sigma_strip<4>,
+                            (const void *)k_sigma_strip<5>,  (const void *)k_sigma_strip<6>,
+                            (const void *)k_sigma_strip<7>,  (const void *)k_sigma_strip<8>,
+                            (const void *)k_sigma_strip<9>,  (const void *)k_sigma_strip<10>,
+                            (const void *)k_sigma_strip<11>, (const void *)k_sigma_strip<12>,
+                            (const void *)k_sigma_strip<13>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -710,7 +780,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
         if (e != hipSuccess) return e;
         if (ev1) (void)hipEventRecord(ev1, s);
         const dim3 grid((unsigned)((b.Nb + 63) / 64), (unsigned)((b.Na + 63) / 64), b.B);
-        hipLaunchKernelGGL(k_gemm_hb, grid, dim3(256), 0, s, b, c, sig, skip_done ? 1 : 0);
+        hipLaunchKernelGGL(k_gemm_h, grid, dim3(256), 0, s, b, c, sig, skip_done ? 1 : 0);
         e = hipGetLastError();
         if (ev2) (void)hipEventRecord(ev2, s);
         return e;

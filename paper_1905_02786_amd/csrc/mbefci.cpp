@@ -24,6 +24,8 @@ struct Tables {
     int64_t nstr = 0;
     std::vector<uint32_t> strings;   // ascending bit masks
     std::vector<uint32_t> links;     // [nstr][nent]
+    std::vector<uint32_t> pairs;     // [nstr][P]: link of each string per pair, strip pair order
+    std::vector<uint32_t> scat;      // [nstr + 1][P + 1]: scatter form for the strip kernel
 };
 
 // Strings with `nel` of `nA` bits set, ascending; for each string I the
@@ -60,6 +62,30 @@ void build_tables(int nA, int nel, Tables &T) {
                 const int P = hi * (hi + 1) / 2 + lo;
                 out[e++] = (uint32_t)rank[J] | ((uint32_t)P << 20) | (neg << 31);
             }
+        }
+    }
+    // Dense forms for the column-strip sigma kernel, columns in its pair order
+    // (diagonal pairs (p,p) first as column p, then p > q in packed order; a
+    // string has at most one link per pair):
+    //   pairs[I][Q] = J | bit 30 (link exists) | bit 31 (sign);
+    //   scat[I][Q]  = J * 128 (byte offset of the sigma-strip row) | bit 31
+    //                 for off-diagonal links, else nstr * 128 (discard row);
+    //                 column np and row nstr are all discard.
+    const int np = nA * (nA + 1) / 2;
+    const uint32_t discard = (uint32_t)T.nstr * 128u;
+    T.pairs.assign((size_t)T.nstr * np, 0u);
+    T.scat.assign((size_t)(T.nstr + 1) * (np + 1), discard);
+    for (int64_t I = 0; I < T.nstr; ++I) {
+        for (int e = 0; e < T.nent; ++e) {
+            const uint32_t L = T.links[(size_t)I * T.nent + e];
+            const int P = (int)((L >> 20) & 0x3FFu);
+            int p = 0;
+            while ((p + 1) * (p + 2) / 2 <= P) ++p;
+            const int q = P - p * (p + 1) / 2;
+            const int col = p == q ? p : nA + P - p;
+            const uint32_t J = L & 0xFFFFFu, sign = L & 0x80000000u;
+            T.pairs[(size_t)I * np + col] = J | sign | (1u << 30);
+            if (p != q) T.scat[(size_t)I * (np + 1) + col] = J * 128u | sign;
         }
     }
 }
@@ -215,14 +241,18 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
-                     align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) + 64 * 256;
+                     align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
+                     align256(4 * (size_t)(cp.ta->nstr + 1) * (cp.pl.P + 1)) +
+                     align256(4 * (size_t)cp.tb->nstr * cp.pl.P) +
+                     64 * 256;
     const int ms = davidson ? ctx->opt.max_space : 0;
     size_t pt = 0;
     pt += 8 * (size_t)cp.pl.stride;                          // params
     pt += 4 * (size_t)(key.nA + nC + 2);                      // act, core
     pt += 8 * (size_t)cp.dim * (2 * ms + (davidson ? 2 : 0)); // V, S, Hd, T
     if (cp.variant == SIGMA_WMAT) pt += 8 * (size_t)cp.pl.P * cp.dim;            // W
-    else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr;                            // H_b
+    else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr +                             // H_b, H_a
+               (key.na != key.nb ? 8 * (size_t)cp.ta->nstr * cp.ta->nstr : 0);
     pt += 8 * (size_t)cp.nblk * (kMaxSpace + 1);             // partials
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
@@ -271,6 +301,8 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.strB = cv.take<uint32_t>(b.Nb);
     b.linkA = cv.take<uint32_t>((size_t)b.Na * b.nentA);
     b.linkB = cv.take<uint32_t>((size_t)b.Nb * b.nentB);
+    b.scatA = cv.take<uint32_t>((size_t)(b.Na + 1) * (cp.pl.P + 1));
+    b.pairB = cv.take<uint32_t>((size_t)b.Nb * cp.pl.P);
     b.act = cv.take<int32_t>((size_t)B * b.nA + 1);
     b.core = cv.take<int32_t>((size_t)B * b.nC + 1);
     b.params = cv.take<double>((size_t)B * cp.pl.stride);
@@ -287,10 +319,12 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.sigma_variant = cp.variant;
     if (cp.variant == SIGMA_WMAT) {
         b.W = cv.take<double>((size_t)B * cp.pl.P * b.dim + 1);
-        b.Hb = nullptr;
+        b.Ha = b.Hb = nullptr;
     } else {
         b.W = nullptr;
         b.Hb = cv.take<double>((size_t)B * b.Nb * b.Nb);
+        // equal electron counts share tables and integrals, hence the string Hamiltonian
+        b.Ha = b.na == b.nb ? b.Hb : cv.take<double>((size_t)B * b.Na * b.Na);
     }
     b.nblk = cp.nblk;
     b.part = cv.take<double>((size_t)B * b.nblk * (kMaxSpace + 1));
@@ -324,6 +358,10 @@ mbefci_status upload_tables(mbefci_ctx *ctx, const ClassPlan &cp, const Batch &b
     HIPCHK(hipMemcpyAsync((void *)b.linkA, cp.ta->links.data(), 4 * (size_t)b.Na * b.nentA, hipMemcpyHostToDevice,
                           ctx->stream));
     HIPCHK(hipMemcpyAsync((void *)b.linkB, cp.tb->links.data(), 4 * (size_t)b.Nb * b.nentB, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync((void *)b.scatA, cp.ta->scat.data(), 4 * (size_t)(b.Na + 1) * (b.pl.P + 1),
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync((void *)b.pairB, cp.tb->pairs.data(), 4 * (size_t)b.Nb * b.pl.P, hipMemcpyHostToDevice,
                           ctx->stream));
     return MBEFCI_OK;
 }
