@@ -480,39 +480,50 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
         return __builtin_amdgcn_raw_buffer_load_b32(rs, qa[i], s * rowS, 0);
     };
 
+    // rows past 64: few of them (n_A = 11) go through vector FMAs on this
+    // wave's K quarter instead of a mostly empty MFMA tile
+    constexpr bool XV = NX == 1 && XR <= 4;
+    constexpr int XVR = XV ? XR : 1;
+    double axv[XVR][KQ];
+#pragma unroll
+    for (int r = 0; r < XVR; ++r)
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            const int ks = w * KQ + j;
+            axv[r][j] = (XV && ks < KS) ? eri_at(64 + r, ks * 4 + kr) : 0.0;
+        }
+    const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
     double cb[NI];
-    uint32_t en1[NI], en0[NI], em1[NI], em2[NI];   // scatter entries of strings K+1, K, K-1, K-2
-    double w2[4];                                  // W of string K-2 on this thread's wave rows
-    double dg1 = 0.0;                              // diagonal sum of the previous string (wave 0)
-    // prologue: D of string 0; C row 1 and the entries of strings 0 and 1
+    uint32_t eA[NI], eB[NI];   // scatter entries (string K-2 is scattered, string K-1 loaded, alternately)
+    double w2[4];              // W of string K-2 on this thread's wave rows
+    double dg1 = 0.0;          // diagonal sum of the previous string (wave 0)
+    // prologue: D of string 0 and C row 1
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
         cb[i] = load_c(0, i);
-        en0[i] = load_s(0, i);
-        em1[i] = em2[i] = load_s(Na, i);   // discard row
+        eA[i] = load_s(Na, i);   // discard row
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NI; ++i) *lds_at(dsl[i]) = bmul[i] * cb[i];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        cb[i] = load_c(Na > 1 ? 1u : 0u, i);
-        en1[i] = load_s(Na > 1 ? 1u : Na, i);
-    }
+    for (int i = 0; i < NI; ++i) cb[i] = load_c(Na > 1 ? 1u : 0u, i);
 #pragma unroll
     for (int v = 0; v < 4; ++v) w2[v] = 0.0;
     uint32_t sa1 = 0u;   // alpha string K-1
-    dbl4 accA[1 + NXA], accB[1 + NXA];   // the wave tile, then the tiles past row 64
+    dbl4 accA[1 + NXA], accB[1 + NXA];   // the wave tile, then the rows past 64
 #pragma unroll
     for (int j = 0; j < 1 + NXA; ++j) accA[j] = accB[j] = dbl4{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
 
     // Pipeline step of string K: MFMA of K into `an` (read back one step
     // later, so no wave waits for its own MFMA results), epilogue of K-1
-    // from `ao`, scatter of K-2, D of K+1, loads of K+2.  Steps past the last
-    // string run on stale data whose results are discarded: their scatter
-    // entries come from the discard row and their diagonal sums are dropped.
-    auto step = [&](uint32_t K, dbl4 (&an)[1 + NXA], dbl4 (&ao)[1 + NXA]) {
+    // from `ao`, scatter of K-2 with entries `ep` while the entries of K-1
+    // load into `en`, D of K+1, C row K+2.  Steps past the last string run on
+    // stale data whose results are discarded: their scatter entries come from
+    // the discard row and their diagonal sums are dropped.
+    auto step = [&](uint32_t K, dbl4 (&an)[1 + NXA], dbl4 (&ao)[1 + NXA], uint32_t (&ep)[NI],
+                    uint32_t (&en)[NI]) {
         const double *Dk = D + (K & 1) * DR * kStrip;
         {
             double bv[KS];
@@ -524,37 +535,55 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
             an[0] = a;
         }
         if (NX > 0) {
-            // tiles past row 64: this wave's K quarter (its own B operands)
+            // rows past 64: this wave's K quarter (its own B operands)
             double bx[KQ];
 #pragma unroll
             for (int j = 0; j < KQ; ++j) {
                 const int ks = w * KQ + j;
                 bx[j] = Dk[((ks < KS ? ks : 0) * 4 + kr) * kStrip + ar];
             }
+            if (XV) {
+                // lane (kr, ar): partial over k = kr (mod 4) of the quarter, then summed over kr
 #pragma unroll
-            for (int x = 0; x < NXA; ++x) {
-                dbl4 a = {0.0, 0.0, 0.0, 0.0};
+                for (int r = 0; r < XVR; ++r) {
+                    double pr = 0.0;
 #pragma unroll
-                for (int j = 0; j < KQ; ++j) a = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], bx[j], a, 0, 0, 0);
-                an[1 + x] = a;
+                    for (int j = 0; j < KQ; ++j) pr = __builtin_fma(axv[r][j], bx[j], pr);
+                    pr += shfl_xor_d(pr, 16);
+                    pr += shfl_xor_d(pr, 32);
+                    an[1][r] = pr;
+                }
+            } else {
+#pragma unroll
+                for (int x = 0; x < NXA; ++x) {
+                    dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = 0; j < KQ; ++j) a = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], bx[j], a, 0, 0, 0);
+                    an[1 + x] = a;
+                }
             }
         }
-        // epilogue of string K-1: partial rows past 64 to LDS
+        // epilogue of string K-1: this wave's partial rows past 64 to LDS
         if (NX > 0) {
             double *wx = Wx + (((K + 1) & 1) * 4 + w) * XR * kStrip;
+            if (XV) {
 #pragma unroll
-            for (int x = 0; x < NXA; ++x)
+                for (int r = 0; r < XVR; ++r) *(kr == 0 ? wx + r * kStrip + ar : dump) = ao[1][r];
+            } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * x + kr + 4 * v;
-                    *(r < XR ? wx + r * kStrip + ar : dump) = ao[1 + x][v];
-                }
+                for (int x = 0; x < NXA; ++x)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * x + kr + 4 * v;
+                        *(r < XR ? wx + r * kStrip + ar : dump) = ao[1 + x][v];
+                    }
+            }
         }
         // scatter of string K-2 through its off-diagonal alpha links
         const double *wx2 = Wx + (K & 1) * 4 * XR * kStrip;
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-            const uint32_t e = em2[i];
+            const uint32_t e = ep[i];
             double wv;
             if (i < 4) {
                 wv = w2[i < 4 ? i : 0];
@@ -563,27 +592,22 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
                 wv = wx2[r * kStrip + ar] + wx2[(XR + r) * kStrip + ar] + wx2[(2 * XR + r) * kStrip + ar] +
                      wx2[(3 * XR + r) * kStrip + ar];
             }
-            double *d = reinterpret_cast<double *>(sbase + (e & 0x7FFFFFFFu));
-            *d += (e & kPairSign) ? -wv : wv;
+            // strip row at byte offset e & 0x7FFFFFFF (a multiple of 128), column ar; sign in bit 31
+            double *d = lds_at((e & 0x7FFFFFFFu) | ar8);
+            *d += __hiloint2double(__double2hiint(wv) ^ (int)(e & kPairSign), __double2loint(wv));
         }
         // D of string K+1 (C row K+1 was loaded one step ago)
 #pragma unroll
         for (int i = 0; i < NI; ++i) *lds_at(dsl[i] + ((K + 1) & 1) * DB) = bmul[i] * cb[i];
-        // loads of string K+2
-        const uint32_t K2c = K + 2 < Na ? K + 2 : Na - 1, K2s = K + 2 < Na ? K + 2 : Na;
+        // loads: C row K+2, scatter entries of string K-1 (scattered next step)
+        const uint32_t K2c = K + 2 < Na ? K + 2 : Na - 1, K1s = (K >= 1 && K - 1 < Na) ? K - 1 : Na;
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-            em2[i] = em1[i];
-            em1[i] = en0[i];
-            en0[i] = en1[i];
             cb[i] = load_c(K2c, i);
-            en1[i] = load_s(K2s, i);
+            en[i] = load_s(K1s, i);
         }
-        double w1[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) w1[v] = ao[0][v];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) w2[v] = w1[v];
+        for (int v = 0; v < 4; ++v) w2[v] = ao[0][v];
         // diagonal pairs: rows 0..NA-1 of wave 0.  Add the sum of string K-2,
         // then form the sum of string K-1 (lane mask of its occupied orbitals,
         // fixed order: v within the lane, then lanes (kr, kr^1), then (kr, kr^2)).
@@ -602,8 +626,8 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
         __syncthreads();
     };
     for (uint32_t K = 0; K < Na + 2; K += 2) {
-        step(K, accA, accB);
-        step(K + 1, accB, accA);
+        step(K, accA, accB, eA, eB);
+        step(K + 1, accB, accA, eB, eA);
     }
     for (uint32_t i = tid; i < Na * kStrip; i += NTH) {
         const uint32_t row = i / kStrip, col = i % kStrip;
