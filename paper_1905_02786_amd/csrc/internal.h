@@ -9,6 +9,7 @@ namespace mbefci {
 
 constexpr int kMaxActive = 13;     // n_A limit: the sigma kernel stages (P x P) in LDS
 constexpr int kMaxSpace = 32;      // Davidson subspace limit
+constexpr int kParts = kMaxSpace + 2;   // block partial sums per tuple and block
 constexpr int kTile = 64;          // determinants per sigma tile (materialised-W variant)
 constexpr int kStrip = 16;         // beta columns per workgroup (column-strip variant)
 constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
@@ -81,11 +82,12 @@ struct Batch {
     double *W;              // [B][P][dim] sigma intermediate (SIGMA_WMAT)
     double *Ha, *Hb;        // [B][Na][Na], [B][Nb][Nb] string Hamiltonians (SIGMA_STRIP; Ha == Hb when na == nb)
     int nblk;               // blocks per tuple for vector kernels
-    double *part;           // [B][nblk][kMaxSpace + 1] block partial sums
+    double *part;           // [B][nblk][kParts] block partial sums
     double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix
     double *y, *coef;       // [B][kMaxSpace]
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
     int32_t *status, *m, *iter, *restart, *out_status; // [B]
+    int32_t *cgs2;          // [B] correction needs a second Gram-Schmidt pass
     int32_t *counter;       // [1] running tuples
     // RDM pass (backward): Gram partials and sums
     int nblk_r;

@@ -835,7 +835,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
 // (one block of 64 threads per tuple) sum them in block order.
 
 __device__ __forceinline__ double *parts(const Batch &b, int t, int blk) {
-    return b.part + ((int64_t)t * b.nblk + blk) * (kMaxSpace + 1);
+    return b.part + ((int64_t)t * b.nblk + blk) * kParts;
 }
 
 // column sums of the partials for i < nx (thread i), fixed block order
@@ -845,12 +845,12 @@ __device__ double sum_parts(const Batch &b, int t, int i) {
     return s;
 }
 
-// Block-reduce up to kMaxSpace+1 per-thread accumulators into partials.
+// Block-reduce up to kParts per-thread accumulators into partials.
 __device__ void store_block_partials(const Batch &b, int t, const double *acc, int nx) {
-    __shared__ double sh[4][kMaxSpace + 1];
+    __shared__ double sh[4][kParts];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < kMaxSpace + 1; ++i) {
+    for (int i = 0; i < kParts; ++i) {
         if (i < nx) {
             const double v = wave_sum(acc[i]);
             if (lane == 0) sh[w][i] = v;
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void k_guess_fill(Batch b) {
     const int t = blockIdx.y;
     const int64_t imin = (int64_t)b.coef[(int64_t)t * kMaxSpace];
     double *v0 = b.V + (int64_t)t * b.max_space * b.dim;
-    double acc[kMaxSpace + 1];
+    double acc[kParts];
     acc[0] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
         const double v = (d == imin ? 1.0 : 0.0) + 1e-3 * guess_noise(d);
@@ -969,20 +969,21 @@ hipError_t launch_init_state(const Batch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-// partial dots V_i . y for i < m[t] + nx_extra (running tuples only)
-__global__ __launch_bounds__(256) void k_dots(Batch b, VecRef yref, int nx_extra) {
+// partial dots V_i . y for i < m[t] + nx_extra (running tuples only; with
+// only2, only those whose correction needs a second Gram-Schmidt pass)
+__global__ __launch_bounds__(256) void k_dots(Batch b, VecRef yref, int nx_extra, int only2) {
     const int t = blockIdx.y;
-    if (b.status[t] != ST_RUNNING) return;
+    if (b.status[t] != ST_RUNNING || (only2 && !b.cgs2[t])) return;
     const int nx = b.m[t] + nx_extra;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     const double *y = vref(yref, t, b.dim);
-    double acc[kMaxSpace + 1];
+    double acc[kParts];
 #pragma unroll
-    for (int i = 0; i < kMaxSpace + 1; ++i) acc[i] = 0.0;
+    for (int i = 0; i < kParts; ++i) acc[i] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
         const double yv = y[d];
 #pragma unroll
-        for (int i = 0; i < kMaxSpace + 1; ++i)
+        for (int i = 0; i < kParts; ++i)
             if (i < nx) acc[i] += V[(int64_t)i * b.dim + d] * yv;
     }
     store_block_partials(b, t, acc, nx);
@@ -1004,7 +1005,7 @@ __global__ void k_update_G(Batch b) {
 }
 
 hipError_t launch_dots(const Batch &b, VecRef y, int nx_extra, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra);
+    hipLaunchKernelGGL(k_dots, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra, 0);
     if (nx_extra == 1) hipLaunchKernelGGL(k_update_G, dim3(b.B), dim3(64), 0, s, b);
     return hipGetLastError();
 }
@@ -1109,7 +1110,9 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     }
 }
 
-// x = V y, Ax = S y, r = Ax - theta x, T = r / (theta - Hd) (clamped), partial |r|^2.
+// x = V y, Ax = S y, r = Ax - theta x, T = r / (theta - Hd) (clamped);
+// partials |r|^2, |T|^2 and the first Gram-Schmidt projections V_i . T of the
+// subspace the correction is added to (V_i, i < m, or x alone on restart).
 // On restart, V_0 <- x and S_0 <- Ax in place (each thread owns its d).
 __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     const int t = blockIdx.y;
@@ -1124,17 +1127,20 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     double *S = b.S + (int64_t)t * b.max_space * b.dim;
     const double *hd = b.Hd + (int64_t)t * b.dim;
     double *T = b.T + (int64_t)t * b.dim;
-    double acc[kMaxSpace + 1];
-    acc[0] = 0.0;
-    acc[1] = 0.0;
-    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-        double x = 0.0, ax = 0.0;
+    double acc[kParts];
 #pragma unroll
-        for (int i = 0; i < kMaxSpace; ++i)
+    for (int i = 0; i < kParts; ++i) acc[i] = 0.0;
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
+        double x = 0.0, ax = 0.0, vd[kMaxSpace];
+#pragma unroll
+        for (int i = 0; i < kMaxSpace; ++i) {
+            vd[i] = 0.0;
             if (i < m) {
-                x += yy[i] * V[(int64_t)i * b.dim + d];
+                vd[i] = V[(int64_t)i * b.dim + d];
+                x += yy[i] * vd[i];
                 ax += yy[i] * S[(int64_t)i * b.dim + d];
             }
+        }
         const double r = ax - th * x;
         acc[0] += r * r;
         double den = th - hd[d];
@@ -1145,9 +1151,14 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
         if (rs) {
             V[d] = x;
             S[d] = ax;
+            acc[2] += x * tv;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kMaxSpace; ++i)
+                if (i < m) acc[2 + i] += vd[i] * tv;
         }
     }
-    store_block_partials(b, t, acc, 2);
+    store_block_partials(b, t, acc, 2 + (rs ? 1 : m));
 }
 
 // convergence test, restart bookkeeping, running count
@@ -1174,25 +1185,34 @@ __global__ void k_converge(Batch b) {
     if (st == ST_RUNNING) atomicAdd(b.counter, 1);
 }
 
+// projection coefficients of the first Gram-Schmidt pass (partials 2..m+1 of k_ritz)
+__global__ void k_coef1(Batch b) {
+    const int t = blockIdx.x;
+    if (b.status[t] != ST_RUNNING) return;
+    const int m = b.m[t];
+    if ((int)threadIdx.x < m) b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = sum_parts(b, t, 2 + threadIdx.x);
+}
+
 hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_small_eig, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_ritz, dim3(b.nblk, b.B), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_converge, dim3(b.B), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_coef1, dim3(b.B), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 
-// coef[i] = sum of partials i (projection coefficients)
+// coef[i] = sum of partials i (projection coefficients of the second pass)
 __global__ void k_coef(Batch b) {
     const int t = blockIdx.x;
-    if (b.status[t] != ST_RUNNING) return;
+    if (b.status[t] != ST_RUNNING || !b.cgs2[t]) return;
     const int m = b.m[t];
     if ((int)threadIdx.x < m) b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = sum_parts(b, t, threadIdx.x);
 }
 
-// T -= sum_i coef_i V_i ; optional partial |T|^2
-__global__ __launch_bounds__(256) void k_axpy(Batch b, int want_norm) {
+// T -= sum_i coef_i V_i, partial |T|^2 (second pass: flagged tuples only)
+__global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
     const int t = blockIdx.y;
-    if (b.status[t] != ST_RUNNING) return;
+    if (b.status[t] != ST_RUNNING || (only2 && !b.cgs2[t])) return;
     const int m = b.m[t];
     double cf[kMaxSpace];
     const double *cp = b.coef + (int64_t)t * kMaxSpace;
@@ -1200,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int want_norm) {
     for (int i = 0; i < kMaxSpace; ++i) cf[i] = (i < m) ? cp[i] : 0.0;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     double *T = b.T + (int64_t)t * b.dim;
-    double acc[kMaxSpace + 1];
+    double acc[kParts];
     acc[0] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
         double v = T[d];
@@ -1210,7 +1230,16 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int want_norm) {
         T[d] = v;
         acc[0] += v * v;
     }
-    if (want_norm) store_block_partials(b, t, acc, 1);
+    store_block_partials(b, t, acc, 1);
+}
+
+// One classical Gram-Schmidt pass suffices when it kept at least 1/sqrt(2)
+// of the correction's norm (Kahan's criterion); otherwise project again.
+__global__ void k_cgs_check(Batch b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= b.B || b.status[t] != ST_RUNNING) return;
+    const double n1 = sqrt(sum_parts(b, t, 0));
+    b.cgs2[t] = (n1 >= 0.70710678118654752 * b.tnorm0[t]) ? 0 : 1;
 }
 
 // 1/|T| into coef[0].  A correction that lies inside the subspace (its
@@ -1241,15 +1270,17 @@ __global__ __launch_bounds__(256) void k_store_t(Batch b) {
         vm[d] = T[d] * s;
 }
 
-// Two rounds of classical Gram-Schmidt of T against V_0..V_{m-1}, then V_m = T/|T|.
+// Classical Gram-Schmidt of T against V_0..V_{m-1} (a second pass where the
+// first lost too much of the norm), then V_m = T/|T|.
 hipError_t launch_orthonormalize(const Batch &b, hipStream_t s) {
     const dim3 grid(b.nblk, b.B);
     VecRef tr{b.T, b.dim, nullptr, 0};
-    for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_dots, grid, dim3(256), 0, s, b, tr, 0);
-        hipLaunchKernelGGL(k_coef, dim3(b.B), dim3(64), 0, s, b);
-        hipLaunchKernelGGL(k_axpy, grid, dim3(256), 0, s, b, pass == 1 ? 1 : 0);
-    }
+    // first pass: projections from k_ritz, coefficients from k_coef1
+    hipLaunchKernelGGL(k_axpy, grid, dim3(256), 0, s, b, 0);
+    hipLaunchKernelGGL(k_cgs_check, dim3((b.B + 63) / 64), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_dots, grid, dim3(256), 0, s, b, tr, 0, 1);
+    hipLaunchKernelGGL(k_coef, dim3(b.B), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_axpy, grid, dim3(256), 0, s, b, 1);
     hipLaunchKernelGGL(k_tnorm, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_store_t, grid, dim3(256), 0, s, b);
     return hipGetLastError();

@@ -253,12 +253,12 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     if (cp.variant == SIGMA_WMAT) pt += 8 * (size_t)cp.pl.P * cp.dim;            // W
     else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr +                             // H_b, H_a
                (key.na != key.nb ? 8 * (size_t)cp.ta->nstr * cp.ta->nstr : 0);
-    pt += 8 * (size_t)cp.nblk * (kMaxSpace + 1);             // partials
+    pt += 8 * (size_t)cp.nblk * kParts;                      // partials
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
     if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP;  // RDM Gram partials and sum
-    pt += 8 * (size_t)(kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 6;
+    pt += 8 * (size_t)(kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 7;
     cp.per_tuple = pt + 256;
 }
 
@@ -327,7 +327,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.Ha = b.na == b.nb ? b.Hb : cv.take<double>((size_t)B * b.Na * b.Na);
     }
     b.nblk = cp.nblk;
-    b.part = cv.take<double>((size_t)B * b.nblk * (kMaxSpace + 1));
+    b.part = cv.take<double>((size_t)B * b.nblk * kParts);
     b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.y = cv.take<double>((size_t)B * kMaxSpace);
     b.coef = cv.take<double>((size_t)B * kMaxSpace);
@@ -341,6 +341,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.iter = cv.take<int32_t>(B);
     b.restart = cv.take<int32_t>(B);
     b.out_status = cv.take<int32_t>(B);
+    b.cgs2 = cv.take<int32_t>(B);
     b.counter = cv.take<int32_t>(1);
     b.nblk_r = cp.nblk_r;
     if (cp.rdm) {
