@@ -419,7 +419,6 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
     double *strip = lds;                   // [Na + 1][16]
     double *D = strip + (Na + 1) * kStrip; // [2][DR][16]
     double *Wx = D + 2 * DR * kStrip;      // [2][4][XR][16]
-    char *const sbase = reinterpret_cast<char *>(strip) + ar * sizeof(double);
     double *const dump = strip + Na * kStrip + ar;
     const ParamLayout &pl = b.pl;
     const double *prm = b.params + (int64_t)t * pl.stride;
@@ -677,77 +676,90 @@ hipError_t launch_build_hb(const Batch &b, hipStream_t s) {
 }
 
 // sigma += H_a C + C H_b per tuple (C = c as Na x Nb row-major; H_a, H_b
-// symmetric): 64 x 64 output tile per block of 4 waves, each wave 32 x 32 =
-// 2 x 2 FP64 MFMA tiles; K in chunks of 16 staged through LDS.
+// symmetric): 64 x 64 output tile per block of 4 waves (2 x 2), each wave
+// 32 x 32 = 2 x 2 FP64 MFMA tiles.  K runs over H_a C (K = Na) and then C H_b
+// (K = Nb) in chunks of 16 staged through a double-buffered LDS tile: the
+// next chunk's global loads are in flight while the current one is
+// multiplied, one barrier per chunk.  Rows and columns past the matrix are
+// read clamped (their results are not stored); K past the end reads as zero.
+constexpr int kGK = 16;
 __global__ __launch_bounds__(256) void k_gemm_h(Batch b, VecRef cref, VecRef sref, int skip_done) {
     const int t = blockIdx.z;
     if (skip_done && b.status[t] != ST_RUNNING) return;
-    const int64_t Na = b.Na, Nb = b.Nb;
+    const int Na = (int)b.Na, Nb = (int)b.Nb;
     const double *C = vref(cref, t, b.dim);
     double *S = const_cast<double *>(vref(sref, t, b.dim));
     const double *Ha = b.Ha + (int64_t)t * Na * Na;
     const double *Hb = b.Hb + (int64_t)t * Nb * Nb;
-    __shared__ double As[64][17];
-    __shared__ double Bs[16][65];
+    __shared__ double As[2][64][kGK + 1];
+    __shared__ double Bs[2][kGK][64 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wy = wave >> 1, wx = wave & 1;
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    // staging: A rows (tid >> 2), 4 consecutive k from (tid & 3) * 4; B row k = tid >> 4, 4 columns from (tid & 15) * 4
+    const int sa_r = tid >> 2, sa_k = (tid & 3) * 4, sb_k = tid >> 4, sb_c = (tid & 15) * 4;
+    const int arow = min(r0 + sa_r, Na - 1);
+    int bcol[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bcol[e] = min(c0 + sb_c + e, Nb - 1);
+    const int nc0 = (Na + kGK - 1) / kGK, nc = nc0 + (Nb + kGK - 1) / kGK;
+    double ra[4], rb[4];
+    auto load = [&](int j) {
+        const bool p1 = j >= nc0;
+        const int k0 = (p1 ? j - nc0 : j) * kGK, K = p1 ? Nb : Na;
+        const double *X = p1 ? C : Ha;
+        const int ldX = p1 ? Nb : Na;
+        const double *Y = p1 ? Hb : C;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ka = k0 + sa_k + e;
+            ra[e] = ka < K ? X[(int64_t)arow * ldX + ka] : 0.0;
+        }
+        const int kb = k0 + sb_k;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[e] = kb < K ? Y[(int64_t)kb * Nb + bcol[e]] : 0.0;
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[buf][sa_r][sa_k + e] = ra[e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bs[buf][sb_k][sb_c + e] = rb[e];
+    };
     dbl4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    auto tile = [&]() {
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int j = 0; j < nc; ++j) {
+        const int buf = j & 1;
+        if (j + 1 < nc) load(j + 1);
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            double a[2], bb[2];
+        for (int ks = 0; ks < kGK / 4; ++ks) {
+            double af[2], bf[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = As[wy * 32 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+            for (int i = 0; i < 2; ++i) af[i] = As[buf][wy * 32 + i * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bb[j] = Bs[ks * 4 + (lane >> 4)][wx * 32 + j * 16 + (lane & 15)];
+            for (int i = 0; i < 2; ++i) bf[i] = Bs[buf][ks * 4 + (lane >> 4)][wx * 32 + i * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+                for (int q = 0; q < 2; ++q) acc[i][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[q], acc[i][q], 0, 0, 0);
         }
-    };
-    // H_a C: A = H_a rows r0.., B = C rows k
-    for (int64_t k0 = 0; k0 < Na; k0 += 16) {
+        if (j + 1 < nc) store(buf ^ 1);
         __syncthreads();
-        for (int i = tid; i < 64 * 16; i += 256) {
-            const int r = i >> 4, kk = i & 15;
-            const int64_t gr = r0 + r, gk = k0 + kk;
-            As[r][kk] = (gr < Na && gk < Na) ? Ha[gr * Na + gk] : 0.0;
-            const int kb = i >> 6, cj = i & 63;
-            const int64_t gk2 = k0 + kb, gc = c0 + cj;
-            Bs[kb][cj] = (gk2 < Na && gc < Nb) ? C[gk2 * Nb + gc] : 0.0;
-        }
-        __syncthreads();
-        tile();
-    }
-    // C H_b: A = C rows r0.., B = H_b rows k
-    for (int64_t k0 = 0; k0 < Nb; k0 += 16) {
-        __syncthreads();
-        for (int i = tid; i < 64 * 16; i += 256) {
-            const int r = i >> 4, kk = i & 15;
-            const int64_t gr = r0 + r, gk = k0 + kk;
-            As[r][kk] = (gr < Na && gk < Nb) ? C[gr * Nb + gk] : 0.0;
-            const int kb = i >> 6, cj = i & 63;
-            const int64_t gk2 = k0 + kb, gc = c0 + cj;
-            Bs[kb][cj] = (gk2 < Nb && gc < Nb) ? Hb[gk2 * Nb + gc] : 0.0;
-        }
-        __syncthreads();
-        tile();
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t gr = r0 + wy * 32 + i * 16 + (lane >> 4) + 4 * v;
-                const int64_t gc = c0 + wx * 32 + j * 16 + (lane & 15);
-                if (gr < Na && gc < Nb) S[gr * Nb + gc] += acc[i][j][v];
+                const int gr = r0 + wy * 32 + i * 16 + (lane >> 4) + 4 * v;
+                const int gc = c0 + wx * 32 + q * 16 + (lane & 15);
+                if (gr < Na && gc < Nb) S[(int64_t)gr * Nb + gc] += acc[i][q][v];
             }
 }
 
