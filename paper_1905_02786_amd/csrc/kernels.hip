@@ -857,12 +857,13 @@ __device__ double sum_parts(const Batch &b, int t, int i) {
     return s;
 }
 
-// Block-reduce up to kParts per-thread accumulators into partials.
+// Block-reduce up to NP (<= kParts) per-thread accumulators into partials.
+template <int NP = kParts>
 __device__ void store_block_partials(const Batch &b, int t, const double *acc, int nx) {
-    __shared__ double sh[4][kParts];
+    __shared__ double sh[4][NP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < kParts; ++i) {
+    for (int i = 0; i < NP; ++i) {
         if (i < nx) {
             const double v = wave_sum(acc[i]);
             if (lane == 0) sh[w][i] = v;
@@ -983,22 +984,23 @@ hipError_t launch_init_state(const Batch &b, hipStream_t s) {
 
 // partial dots V_i . y for i < m[t] + nx_extra (running tuples only; with
 // only2, only those whose correction needs a second Gram-Schmidt pass)
+template <int MS>
 __global__ __launch_bounds__(256) void k_dots(Batch b, VecRef yref, int nx_extra, int only2) {
     const int t = blockIdx.y;
     if (b.status[t] != ST_RUNNING || (only2 && !b.cgs2[t])) return;
     const int nx = b.m[t] + nx_extra;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     const double *y = vref(yref, t, b.dim);
-    double acc[kParts];
+    double acc[MS + 1];
 #pragma unroll
-    for (int i = 0; i < kParts; ++i) acc[i] = 0.0;
+    for (int i = 0; i < MS + 1; ++i) acc[i] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
         const double yv = y[d];
 #pragma unroll
-        for (int i = 0; i < kParts; ++i)
+        for (int i = 0; i < MS + 1; ++i)
             if (i < nx) acc[i] += V[(int64_t)i * b.dim + d] * yv;
     }
-    store_block_partials(b, t, acc, nx);
+    store_block_partials<MS + 1>(b, t, acc, nx);
 }
 
 // G column m: G[i][m] = G[m][i] = V_i . S_m for i <= m; then m += 1
@@ -1017,7 +1019,8 @@ __global__ void k_update_G(Batch b) {
 }
 
 hipError_t launch_dots(const Batch &b, VecRef y, int nx_extra, hipStream_t s) {
-    hipLaunchKernelGGL(k_dots, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra, 0);
+    if (b.max_space <= 12) hipLaunchKernelGGL(k_dots<12>, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra, 0);
+    else hipLaunchKernelGGL(k_dots<kMaxSpace>, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra, 0);
     if (nx_extra == 1) hipLaunchKernelGGL(k_update_G, dim3(b.B), dim3(64), 0, s, b);
     return hipGetLastError();
 }
@@ -1126,26 +1129,27 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
 // partials |r|^2, |T|^2 and the first Gram-Schmidt projections V_i . T of the
 // subspace the correction is added to (V_i, i < m, or x alone on restart).
 // On restart, V_0 <- x and S_0 <- Ax in place (each thread owns its d).
+template <int MS>
 __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     const int t = blockIdx.y;
     if (b.status[t] != ST_RUNNING) return;
     const int m = b.m[t], rs = b.restart[t];
     const double th = b.theta[t];
     const double *yv = b.y + (int64_t)t * kMaxSpace;
-    double yy[kMaxSpace];
+    double yy[MS];
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i) yy[i] = (i < m) ? yv[i] : 0.0;
+    for (int i = 0; i < MS; ++i) yy[i] = (i < m) ? yv[i] : 0.0;
     double *V = b.V + (int64_t)t * b.max_space * b.dim;
     double *S = b.S + (int64_t)t * b.max_space * b.dim;
     const double *hd = b.Hd + (int64_t)t * b.dim;
     double *T = b.T + (int64_t)t * b.dim;
-    double acc[kParts];
+    double acc[MS + 2];
 #pragma unroll
-    for (int i = 0; i < kParts; ++i) acc[i] = 0.0;
+    for (int i = 0; i < MS + 2; ++i) acc[i] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-        double x = 0.0, ax = 0.0, vd[kMaxSpace];
+        double x = 0.0, ax = 0.0, vd[MS];
 #pragma unroll
-        for (int i = 0; i < kMaxSpace; ++i) {
+        for (int i = 0; i < MS; ++i) {
             vd[i] = 0.0;
             if (i < m) {
                 vd[i] = V[(int64_t)i * b.dim + d];
@@ -1166,11 +1170,11 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
             acc[2] += x * tv;
         } else {
 #pragma unroll
-            for (int i = 0; i < kMaxSpace; ++i)
+            for (int i = 0; i < MS; ++i)
                 if (i < m) acc[2 + i] += vd[i] * tv;
         }
     }
-    store_block_partials(b, t, acc, 2 + (rs ? 1 : m));
+    store_block_partials<MS + 2>(b, t, acc, 2 + (rs ? 1 : m));
 }
 
 // convergence test, restart bookkeeping, running count
@@ -1207,7 +1211,8 @@ __global__ void k_coef1(Batch b) {
 
 hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_small_eig, dim3(b.B), dim3(64), 0, s, b);
-    hipLaunchKernelGGL(k_ritz, dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    if (b.max_space <= 12) hipLaunchKernelGGL(k_ritz<12>, dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL(k_ritz<kMaxSpace>, dim3(b.nblk, b.B), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_converge, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_coef1, dim3(b.B), dim3(64), 0, s, b);
     return hipGetLastError();
@@ -1222,27 +1227,28 @@ __global__ void k_coef(Batch b) {
 }
 
 // T -= sum_i coef_i V_i, partial |T|^2 (second pass: flagged tuples only)
+template <int MS>
 __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
     const int t = blockIdx.y;
     if (b.status[t] != ST_RUNNING || (only2 && !b.cgs2[t])) return;
     const int m = b.m[t];
-    double cf[kMaxSpace];
+    double cf[MS];
     const double *cp = b.coef + (int64_t)t * kMaxSpace;
 #pragma unroll
-    for (int i = 0; i < kMaxSpace; ++i) cf[i] = (i < m) ? cp[i] : 0.0;
+    for (int i = 0; i < MS; ++i) cf[i] = (i < m) ? cp[i] : 0.0;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     double *T = b.T + (int64_t)t * b.dim;
-    double acc[kParts];
+    double acc[1];
     acc[0] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
         double v = T[d];
 #pragma unroll
-        for (int i = 0; i < kMaxSpace; ++i)
+        for (int i = 0; i < MS; ++i)
             if (i < m) v -= cf[i] * V[(int64_t)i * b.dim + d];
         T[d] = v;
         acc[0] += v * v;
     }
-    store_block_partials(b, t, acc, 1);
+    store_block_partials<1>(b, t, acc, 1);
 }
 
 // One classical Gram-Schmidt pass suffices when it kept at least 1/sqrt(2)
@@ -1288,11 +1294,15 @@ hipError_t launch_orthonormalize(const Batch &b, hipStream_t s) {
     const dim3 grid(b.nblk, b.B);
     VecRef tr{b.T, b.dim, nullptr, 0};
     // first pass: projections from k_ritz, coefficients from k_coef1
-    hipLaunchKernelGGL(k_axpy, grid, dim3(256), 0, s, b, 0);
+    const bool small = b.max_space <= 12;
+    if (small) hipLaunchKernelGGL(k_axpy<12>, grid, dim3(256), 0, s, b, 0);
+    else hipLaunchKernelGGL(k_axpy<kMaxSpace>, grid, dim3(256), 0, s, b, 0);
     hipLaunchKernelGGL(k_cgs_check, dim3((b.B + 63) / 64), dim3(64), 0, s, b);
-    hipLaunchKernelGGL(k_dots, grid, dim3(256), 0, s, b, tr, 0, 1);
+    if (small) hipLaunchKernelGGL(k_dots<12>, grid, dim3(256), 0, s, b, tr, 0, 1);
+    else hipLaunchKernelGGL(k_dots<kMaxSpace>, grid, dim3(256), 0, s, b, tr, 0, 1);
     hipLaunchKernelGGL(k_coef, dim3(b.B), dim3(64), 0, s, b);
-    hipLaunchKernelGGL(k_axpy, grid, dim3(256), 0, s, b, 1);
+    if (small) hipLaunchKernelGGL(k_axpy<12>, grid, dim3(256), 0, s, b, 1);
+    else hipLaunchKernelGGL(k_axpy<kMaxSpace>, grid, dim3(256), 0, s, b, 1);
     hipLaunchKernelGGL(k_tnorm, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_store_t, grid, dim3(256), 0, s, b);
     return hipGetLastError();
