@@ -372,11 +372,18 @@ __device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, i
     return t < B;
 }
 
-__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
-    const int src = ((int)(threadIdx.x & 63) ^ mask) << 2;
-    const int lo = __builtin_amdgcn_ds_bpermute(src, (int)__double2loint(v));
-    const int hi = __builtin_amdgcn_ds_bpermute(src, (int)__double2hiint(v));
-    return __hiloint2double(hi, lo);
+// Sum of x over the four lanes l, l^16, l^32, l^48 (the (lane >> 4) groups of
+// an MFMA output column), as ((x0 + x1) + (x2 + x3)) in every one of them:
+// row swaps of 16 and 32 lanes on the vector ALU, no LDS round trip.
+__device__ __forceinline__ double sum_over_kr(double x) {
+    const unsigned lo = __double2loint(x), hi = __double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double s = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+    const unsigned lo2 = __double2loint(s), hi2 = __double2hiint(s);
+    const auto c = __builtin_amdgcn_permlane32_swap(lo2, lo2, false, false);
+    const auto d = __builtin_amdgcn_permlane32_swap(hi2, hi2, false, false);
+    return __hiloint2double(d[0], c[0]) + __hiloint2double(d[1], c[1]);
 }
 
 // One workgroup per (tuple, 16-column strip), MT waves.  Thread items: the
@@ -385,7 +392,7 @@ __device__ __forceinline__ double shfl_xor_d(double v, int mask) {
 // thread writes D for its items and scatters W of those items (rows < 64
 // straight from the MFMA registers).  The diagonal pairs are rows 0..n_A-1,
 // all in wave 0, which sums them for the string with a lane mask and two
-// cross-lane steps.  Software pipeline over the alpha strings, one barrier
+// cross-lane row swaps.  Software pipeline over the alpha strings, one barrier
 // per step: in the step of string K the block
 //   - runs the MFMA of string K on D[K & 1] (results read one step later),
 //   - stores the partial rows past 64 of W(K-1) and sums its diagonal pairs,
@@ -548,9 +555,7 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
                     double pr = 0.0;
 #pragma unroll
                     for (int j = 0; j < KQ; ++j) pr = __builtin_fma(axv[r][j], bx[j], pr);
-                    pr += shfl_xor_d(pr, 16);
-                    pr += shfl_xor_d(pr, 32);
-                    an[1][r] = pr;
+                    an[1][r] = sum_over_kr(pr);
                 }
             } else {
 #pragma unroll
@@ -616,9 +621,7 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (4 * v < NA) s += ((sa1 >> (kr + 4 * v)) & 1u) ? ao[0][v] : 0.0;
-            s += shfl_xor_d(s, 16);
-            s += shfl_xor_d(s, 32);
-            dg1 = s;
+            dg1 = sum_over_kr(s);
         }
         const uint32_t sk = b.strA[K < Na ? K : Na - 1];
         sa1 = K < Na ? sk : 0u;
