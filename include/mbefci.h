@@ -94,7 +94,12 @@ typedef struct {
                                GEMM with the dense beta-string Hamiltonian); 2: W materialised
                                in the workspace and gathered back.  1 falls back to 2 when the
                                strip does not fit in LDS (more than ~1100 alpha strings). */
-    int32_t reserved[6];
+    int32_t pspace;         /* Davidson preconditioner: the exact inverse of (theta - H) on the
+                               pspace determinants of lowest diagonal energy, (theta - H_II)^-1
+                               elsewhere; 0..128, 0 = diagonal only (default 128).  Only for
+                               column-strip classes; the result does not depend on it beyond
+                               the convergence tolerances. */
+    int32_t reserved[5];
 } mbefci_options;
 
 typedef struct {

@@ -10,6 +10,7 @@ namespace mbefci {
 constexpr int kMaxActive = 13;     // n_A limit: the sigma kernel stages (P x P) in LDS
 constexpr int kMaxSpace = 32;      // Davidson subspace limit
 constexpr int kParts = kMaxSpace + 2;   // block partial sums per tuple and block
+constexpr int kPsp = 128;          // largest P space of the Davidson preconditioner
 constexpr int kTile = 64;          // determinants per sigma tile (materialised-W variant)
 constexpr int kStrip = 16;         // beta columns per workgroup (column-strip variant)
 constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
@@ -82,12 +83,18 @@ struct Batch {
     double *W;              // [B][P][dim] sigma intermediate (SIGMA_WMAT)
     double *Ha, *Hb;        // [B][Na][Na], [B][Nb][Nb] string Hamiltonians (SIGMA_STRIP; Ha == Hb when na == nb)
     int nblk;               // blocks per tuple for vector kernels
-    double *part;           // [B][nblk][kParts] block partial sums
+    double *part;           // [B][nblk + 1][kParts] block partial sums (the last block: P-space corrections)
     double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix
     double *y, *coef;       // [B][kMaxSpace]
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
     int32_t *status, *m, *iter, *restart, *out_status; // [B]
     int32_t *cgs2;          // [B] correction needs a second Gram-Schmidt pass
+    // P-space preconditioner: the psp determinants of lowest diagonal energy
+    // (0: diagonal preconditioner only); H_PP = Q T Q^T with T tridiagonal
+    int psp;
+    int32_t *pidx;          // [B][kPsp] determinant indices
+    double *pQ;             // [B][kPsp][kPsp] H_PP, then Q
+    double *pT;             // [B][3][kPsp] diagonal, subdiagonal of T, lowest eigenvector of H_PP
     int32_t *counter;       // [1] running tuples
     // RDM pass (backward): Gram partials and sums
     int nblk_r;
@@ -112,6 +119,7 @@ size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na);
 bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB);
 hipError_t launch_build_hb(const Batch &b, hipStream_t s);
 hipError_t launch_form_x(const Batch &b, hipStream_t s);
+hipError_t launch_pspace(const Batch &b, hipStream_t s);
 int rdm_np(int nA);
 size_t rdm_lds_bytes(int NP);
 hipError_t launch_rdm(const Batch &b, VecRef x, double *part, double *G, int nblk_r, hipStream_t s);

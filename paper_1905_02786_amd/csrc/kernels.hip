@@ -794,22 +794,6 @@ static hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shif
     }
 }
 
-hipError_t init_kernels() {
-    hipError_t e = hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    const void *strips[] = {(const void *)k_sigma_strip<1>,  (const void *)k_sigma_strip<2>,
-                            (const void *)k_sigma_strip<3>,  (const void *)k_sigma_strip<4>,
-                            (const void *)k_sigma_strip<5>,  (const void *)k_sigma_strip<6>,
-                            (const void *)k_sigma_strip<7>,  (const void *)k_sigma_strip<8>,
-                            (const void *)k_sigma_strip<9>,  (const void *)k_sigma_strip<10>,
-                            (const void *)k_sigma_strip<11>, (const void *)k_sigma_strip<12>,
-                            (const void *)k_sigma_strip<13>};
-    for (const void *f : strips) {
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
 
 hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
@@ -850,7 +834,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
 // (one block of 64 threads per tuple) sum them in block order.
 
 __device__ __forceinline__ double *parts(const Batch &b, int t, int blk) {
-    return b.part + ((int64_t)t * b.nblk + blk) * kParts;
+    return b.part + ((int64_t)t * (b.nblk + 1) + blk) * kParts;
 }
 
 // column sums of the partials for i < nx (thread i), fixed block order
@@ -858,6 +842,12 @@ __device__ double sum_parts(const Batch &b, int t, int i) {
     double s = 0.0;
     for (int blk = 0; blk < b.nblk; ++blk) s += parts(b, t, blk)[i];
     return s;
+}
+
+// the same plus the P-space correction block (guess norm, Ritz partials)
+__device__ double sum_parts_x(const Batch &b, int t, int i) {
+    const double s = sum_parts(b, t, i);
+    return b.psp > 0 ? s + parts(b, t, b.nblk)[i] : s;
 }
 
 // Block-reduce up to NP (<= kParts) per-thread accumulators into partials.
@@ -878,6 +868,414 @@ __device__ void store_block_partials(const Batch &b, int t, const double *acc, i
         for (int k = 0; k < 4; ++k) s += sh[k][threadIdx.x];
         parts(b, t, blockIdx.x)[threadIdx.x] = s;
     }
+}
+
+// ------------------------------------------------------- P-space ----------
+// Davidson preconditioner on the P space of the psp determinants with the
+// lowest diagonal energies: the correction there solves (theta - H_PP) t_P =
+// r_P exactly (H_PP = Q T Q^T, T tridiagonal, both computed once per tuple),
+// elsewhere t = r / (theta - H_II).  The initial guess is the lowest
+// eigenvector of H_PP plus the same 1e-3 admixture as the determinant guess
+// (none when P is the whole space, where that eigenvector is exact).
+
+// P selection, one block per tuple: histogram of H_II over [min, max] in 1024
+// bins, then the determinants of the bins below the one holding the psp-th
+// smallest value, and from that bin the lowest indices up to psp, in index
+// order (deterministic, ties broken by index).
+__global__ __launch_bounds__(256) void k_psp_select(Batch b) {
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = b.psp;
+    const double *hd = b.Hd + (int64_t)t * b.dim;
+    int32_t *out = b.pidx + (int64_t)t * kPsp;
+    __shared__ double rmin[4], rmax[4];
+    __shared__ int hist[1024];
+    __shared__ int sB, sC0, sNeed, wc1[4], wc2[4];
+    if (b.dim <= n) {
+        for (int i = tid; i < n; i += 256) out[i] = i;
+        return;
+    }
+    double mn = 1e300, mx = -1e300;
+    for (int64_t d = tid; d < b.dim; d += 256) {
+        mn = fmin(mn, hd[d]);
+        mx = fmax(mx, hd[d]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if (lane == 0) {
+        rmin[wv] = mn;
+        rmax[wv] = mx;
+    }
+    for (int i = tid; i < 1024; i += 256) hist[i] = 0;
+    __syncthreads();
+    mn = fmin(fmin(rmin[0], rmin[1]), fmin(rmin[2], rmin[3]));
+    mx = fmax(fmax(rmax[0], rmax[1]), fmax(rmax[2], rmax[3]));
+    const double scale = mx > mn ? 1024.0 / (mx - mn) : 0.0;
+    auto bin = [&](double v) -> int {
+        const int k = (int)((v - mn) * scale);
+        return k < 0 ? 0 : (k > 1023 ? 1023 : k);
+    };
+    for (int64_t d = tid; d < b.dim; d += 256) atomicAdd(&hist[bin(hd[d])], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int c = 0;
+        for (int k = 0; k < 1024; ++k) {
+            if (c + hist[k] >= n) {
+                sB = k;
+                sC0 = c;
+                sNeed = n - c;
+                break;
+            }
+            c += hist[k];
+        }
+    }
+    __syncthreads();
+    const int B = sB, C0 = sC0, need = sNeed;
+    int base1 = 0, base2 = 0;
+    for (int64_t d0 = 0; d0 < b.dim; d0 += 256) {
+        const int64_t d = d0 + tid;
+        const int k = d < b.dim ? bin(hd[d]) : 2048;
+        const bool f1 = k < B, f2 = k == B;
+        const uint64_t m1 = __ballot(f1), m2 = __ballot(f2);
+        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        const int p1 = __popcll(m1 & below), p2 = __popcll(m2 & below);
+        if (lane == 0) {
+            wc1[wv] = __popcll(m1);
+            wc2[wv] = __popcll(m2);
+        }
+        __syncthreads();
+        int o1 = base1, o2 = base2, t1 = 0, t2 = 0;
+        for (int q = 0; q < 4; ++q) {
+            if (q < wv) {
+                o1 += wc1[q];
+                o2 += wc2[q];
+            }
+            t1 += wc1[q];
+            t2 += wc2[q];
+        }
+        if (f1) out[o1 + p1] = (int32_t)d;
+        if (f2 && o2 + p2 < need) out[C0 + o2 + p2] = (int32_t)d;
+        base1 += t1;
+        base2 += t2;
+        __syncthreads();
+        if (base1 >= C0 && base2 >= need) break;
+    }
+}
+
+// One alpha (or beta) string pair <I|E+_P|J>: the pairs P with their
+// coefficients (diagonal: the occupied orbitals of I, coefficient 1; a single
+// excitation: its pair and sign; otherwise none).  Returns the count.
+__device__ __forceinline__ int string_transition(uint32_t mi, uint32_t mj, int *P, double *c) {
+    const uint32_t diff = mi ^ mj;
+    if (diff == 0u) {
+        int k = 0;
+        for (uint32_t x = mi; x; x &= x - 1) {
+            const int p = __ffs(x) - 1;
+            P[k] = p * (p + 3) / 2;
+            c[k++] = 1.0;
+        }
+        return k;
+    }
+    if (__popc(diff) != 2) return 0;
+    const int p = __ffs(mi & diff) - 1, q = __ffs(mj & diff) - 1;   // created in I, annihilated from J
+    const int lo = p < q ? p : q, hi = p < q ? q : p;
+    const uint32_t between = mj & (((1u << hi) - 1u) & ~((1u << (lo + 1)) - 1u));
+    P[0] = hi * (hi + 1) / 2 + lo;
+    c[0] = (__popc(between) & 1) ? -1.0 : 1.0;
+    return 1;
+}
+
+// H_PP[i][j] = H_a[Ia][Ja] d(Ib,Jb) + H_b[Ib][Jb] d(Ia,Ja)
+//            + sum_PQ (P|Q) <Ia|E+_P|Ja> <Ib|E+_Q|Jb>  (upper triangle, mirrored)
+__global__ __launch_bounds__(256) void k_psp_build(Batch b) {
+    const int t = blockIdx.x, n = b.psp;
+    const ParamLayout &pl = b.pl;
+    const double *prm = b.params + (int64_t)t * pl.stride;
+    const int32_t *pi = b.pidx + (int64_t)t * kPsp;
+    const double *Ha = b.Ha + (int64_t)t * b.Na * b.Na, *Hb = b.Hb + (int64_t)t * b.Nb * b.Nb;
+    double *H = b.pQ + (int64_t)t * kPsp * kPsp;
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+        const int i = idx / n, j = idx % n;
+        if (j < i) continue;
+        const int64_t I = pi[i], J = pi[j];
+        const int64_t ia = I / b.Nb, ib = I % b.Nb, ja = J / b.Nb, jb = J % b.Nb;
+        double v = 0.0;
+        if (ib == jb) v += Ha[ia * b.Na + ja];
+        if (ia == ja) v += Hb[ib * b.Nb + jb];
+        int Pa[kMaxActive], Pb[kMaxActive];
+        double ca[kMaxActive], cb2[kMaxActive];
+        const int na = string_transition(b.strA[ia], b.strA[ja], Pa, ca);
+        const int nb = na ? string_transition(b.strB[ib], b.strB[jb], Pb, cb2) : 0;
+        double x = 0.0;
+        for (int u = 0; u < na; ++u)
+            for (int w2 = 0; w2 < nb; ++w2) x += ca[u] * cb2[w2] * prm[pl.off_eri + Pa[u] * pl.Kpad + Pb[w2]];
+        v += 2.0 * x;   // stored as 1/2 (P|Q)
+        H[i * kPsp + j] = v;
+        H[j * kPsp + i] = v;
+    }
+}
+
+// Householder tridiagonalisation of H_PP in LDS (one block per tuple), Q
+// formed explicitly, and the lowest eigenvector of H_PP (bisection on T for
+// the lowest eigenvalue, inverse iteration, y = Q z).
+__device__ double block_sum256(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void k_psp_factor(Batch b) {
+    const int t = blockIdx.x, tid = threadIdx.x, n = b.psp;
+    constexpr int LD = kPsp + 1;
+    extern __shared__ double lds[];
+    double *A = lds;                 // [n][LD]
+    double *vec = A + kPsp * LD;     // [kPsp] p, then z
+    double *sh = vec + kPsp;         // [8]
+    double *cpv = sh + 8;            // [kPsp] Thomas multipliers
+    double *gQ = b.pQ + (int64_t)t * kPsp * kPsp;
+    double *dT = b.pT + (int64_t)t * 3 * kPsp, *eT = dT + kPsp, *yv = eT + kPsp;
+    for (int idx = tid; idx < n * n; idx += 256) A[(idx / n) * LD + idx % n] = gQ[(idx / n) * kPsp + idx % n];
+    __syncthreads();
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        double part = 0.0;
+        for (int i = tid; i < m; i += 256) part += A[(k + 1 + i) * LD + k] * A[(k + 1 + i) * LD + k];
+        const double s2 = block_sum256(part, sh);
+        const double x0 = A[(k + 1) * LD + k];
+        const double alpha = x0 > 0.0 ? -sqrt(s2) : sqrt(s2);
+        const double v0 = x0 - alpha;
+        const double vn2 = s2 - x0 * x0 + v0 * v0;
+        __syncthreads();
+        if (!(vn2 > 1e-300)) {   // column already reduced: no reflection
+            if (tid == 0) eT[k] = x0;
+            for (int i = tid; i < m; i += 256) A[(k + 1 + i) * LD + k] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        if (tid == 0) eT[k] = alpha;
+        const double inv = 1.0 / sqrt(vn2);
+        for (int i = tid; i < m; i += 256) A[(k + 1 + i) * LD + k] = (i == 0 ? v0 : A[(k + 1 + i) * LD + k]) * inv;
+        __syncthreads();
+        // p = B v over the trailing block B = A[k+1.., k+1..]
+        for (int i = tid; i < m; i += 256) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) s += A[(k + 1 + i) * LD + k + 1 + j] * A[(k + 1 + j) * LD + k];
+            vec[i] = s;
+        }
+        __syncthreads();
+        part = 0.0;
+        for (int i = tid; i < m; i += 256) part += A[(k + 1 + i) * LD + k] * vec[i];
+        const double K = block_sum256(part, sh);
+        // B -= v w^T + w v^T, w = 2 p - 2 K v
+        for (int idx = tid; idx < m * m; idx += 256) {
+            const int i = idx / m, j = idx % m;
+            const double vi = A[(k + 1 + i) * LD + k], vj = A[(k + 1 + j) * LD + k];
+            const double wi = 2.0 * vec[i] - 2.0 * K * vi, wj = 2.0 * vec[j] - 2.0 * K * vj;
+            A[(k + 1 + i) * LD + k + 1 + j] -= vi * wj + wi * vj;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += 256) dT[i] = A[i * LD + i];
+    if (tid == 0 && n >= 2) eT[n - 2] = A[(n - 1) * LD + n - 2];
+    if (tid == 0) eT[n - 1] = 0.0;
+    // Householder vectors to global (lower part), then Q = H_0 ... H_{n-3} in LDS
+    for (int idx = tid; idx < n * n; idx += 256) {
+        const int i = idx / n, j = idx % n;
+        gQ[i * kPsp + j] = (j + 2 < n && i > j) ? A[i * LD + j] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += 256) A[(idx / n) * LD + idx % n] = (idx / n == idx % n) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int k = n - 3; k >= 0; --k) {
+        const int m = n - k - 1;
+        for (int c = tid; c < n; c += 256) {
+            double s = 0.0;
+            for (int r = 0; r < m; ++r) s += gQ[(k + 1 + r) * kPsp + k] * A[(k + 1 + r) * LD + c];
+            s *= 2.0;
+            for (int r = 0; r < m; ++r) A[(k + 1 + r) * LD + c] -= s * gQ[(k + 1 + r) * kPsp + k];
+        }
+        __syncthreads();
+    }
+    // lowest eigenvalue of T by bisection (Sturm counts), then inverse iteration
+    if (tid == 0) {
+        double lo = 1e300, hi = -1e300;
+        for (int i = 0; i < n; ++i) {
+            const double r = (i > 0 ? fabs(eT[i - 1]) : 0.0) + (i + 1 < n ? fabs(eT[i]) : 0.0);
+            lo = fmin(lo, dT[i] - r);
+            hi = fmax(hi, dT[i] + r);
+        }
+        const double span = fmax(hi - lo, 1e-300);
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * span; ++it) {
+            const double x = 0.5 * (lo + hi);
+            int cnt = 0;
+            double q = 1.0;
+            for (int i = 0; i < n; ++i) {
+                q = dT[i] - x - (i > 0 ? eT[i - 1] * eT[i - 1] / q : 0.0);
+                if (q == 0.0) q = -1e-300;
+                cnt += q < 0.0;
+            }
+            if (cnt >= 1) hi = x; else lo = x;
+        }
+        // T - sigma I positive definite; scale is the size of T's entries
+        // (floored, so that a zero or one-element T still gives finite pivots)
+        const double scale = fmax(span + fabs(lo), 1e-30);
+        const double sigma = lo - 1e-10 * scale;
+        auto clampp = [scale](double p) { return fabs(p) < 1e-14 * scale ? (p >= 0.0 ? 1e-14 : -1e-14) * scale : p; };
+        double *z = vec, *cp = cpv;
+        for (int i = 0; i < n; ++i) z[i] = 1.0;
+        for (int rep = 0; rep < 3; ++rep) {
+            // Thomas on (T - sigma I) z_new = z
+            double piv = clampp(dT[0] - sigma);
+            cp[0] = (n > 1 ? eT[0] : 0.0) / piv;
+            z[0] = z[0] / piv;
+            for (int i = 1; i < n; ++i) {
+                piv = clampp(dT[i] - sigma - eT[i - 1] * cp[i - 1]);
+                cp[i] = (i + 1 < n ? eT[i] : 0.0) / piv;
+                z[i] = (z[i] - eT[i - 1] * z[i - 1]) / piv;
+            }
+            for (int i = n - 2; i >= 0; --i) z[i] -= cp[i] * z[i + 1];
+            double mz = 0.0;
+            for (int i = 0; i < n; ++i) mz = fmax(mz, fabs(z[i]));
+            double nz = 0.0;
+            for (int i = 0; i < n; ++i) {
+                z[i] /= mz;
+                nz += z[i] * z[i];
+            }
+            nz = 1.0 / sqrt(nz);
+            for (int i = 0; i < n; ++i) z[i] *= nz;
+        }
+    }
+    __syncthreads();
+    // y = Q z, Q to global
+    for (int i = tid; i < n; i += 256) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += A[i * LD + j] * vec[j];
+        yv[i] = s;
+    }
+    for (int idx = tid; idx < n * n; idx += 256) gQ[(idx / n) * kPsp + idx % n] = A[(idx / n) * LD + idx % n];
+}
+
+size_t psp_factor_lds() { return sizeof(double) * ((size_t)kPsp * (kPsp + 1) + 2 * kPsp + 8); }
+
+hipError_t launch_pspace(const Batch &b, hipStream_t s) {
+    if (b.psp <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_psp_select, dim3(b.B), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_psp_build, dim3(b.B), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_psp_factor, dim3(b.B), dim3(256), psp_factor_lds(), s, b);
+    return hipGetLastError();
+}
+
+// V_0 += lowest eigenvector of H_PP on the P determinants; the change of
+// |V_0|^2 into the extra partial block.
+__global__ __launch_bounds__(kPsp) void k_psp_guess(Batch b) {
+    const int t = blockIdx.x, i = threadIdx.x, n = b.psp;
+    double *v0 = b.V + (int64_t)t * b.max_space * b.dim;
+    const double *yv = b.pT + (int64_t)t * 3 * kPsp + 2 * kPsp;
+    double dn = 0.0;
+    if (i < n) {
+        const int64_t d = b.pidx[(int64_t)t * kPsp + i];
+        const double o = v0[d], nv = o + yv[i];
+        v0[d] = nv;
+        dn = nv * nv - o * o;
+    }
+    __shared__ double sh[2];
+    dn = wave_sum(dn);
+    if ((i & 63) == 0) sh[i >> 6] = dn;
+    __syncthreads();
+    if (i == 0) {
+        double *px = parts(b, t, b.nblk);
+        px[0] = sh[0] + (kPsp > 64 ? sh[1] : 0.0);
+    }
+}
+
+// After k_ritz: T on the P determinants <- (theta - H_PP)^-1 r_P, solved as
+// Q (theta - T)^-1 Q^T r_P (Thomas, pivots kept away from zero like the
+// diagonal preconditioner); the changes of |T|^2 and of the projections
+// V_i . T (x . T on restart) go to the extra partial block.
+template <int MS>
+__global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
+    const int t = blockIdx.x, i = threadIdx.x, n = b.psp;
+    if (b.status[t] != ST_RUNNING) return;
+    const int m = b.m[t], rs = b.restart[t];
+    const double th = b.theta[t];
+    const double *yy = b.y + (int64_t)t * kMaxSpace;
+    const double *V = b.V + (int64_t)t * b.max_space * b.dim;
+    const double *S = b.S + (int64_t)t * b.max_space * b.dim;
+    double *T = b.T + (int64_t)t * b.dim;
+    const double *Q = b.pQ + (int64_t)t * kPsp * kPsp;
+    const double *dT = b.pT + (int64_t)t * 3 * kPsp, *eT = dT + kPsp;
+    __shared__ double r[kPsp], w[kPsp], cp[kPsp], red[2][MS + 2];
+    int64_t d = 0;
+    double x = 0.0, told = 0.0;
+    if (i < n) {
+        d = b.pidx[(int64_t)t * kPsp + i];
+        double ax = 0.0;
+        if (rs) {
+            x = V[d];
+            ax = S[d];
+        } else {
+#pragma unroll
+            for (int k = 0; k < MS; ++k)
+                if (k < m) {
+                    x += yy[k] * V[(int64_t)k * b.dim + d];
+                    ax += yy[k] * S[(int64_t)k * b.dim + d];
+                }
+        }
+        r[i] = ax - th * x;
+        told = T[d];
+    }
+    __syncthreads();
+    if (i < n) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += Q[k * kPsp + i] * r[k];
+        w[i] = s;
+    }
+    __syncthreads();
+    if (i == 0) {
+        auto clampp = [](double p) { return fabs(p) < 1e-8 ? (p >= 0.0 ? 1e-8 : -1e-8) : p; };
+        double piv = clampp(th - dT[0]);
+        cp[0] = (n > 1 ? -eT[0] : 0.0) / piv;
+        w[0] = w[0] / piv;
+        for (int k = 1; k < n; ++k) {
+            piv = clampp(th - dT[k] + eT[k - 1] * cp[k - 1]);
+            cp[k] = (k + 1 < n ? -eT[k] : 0.0) / piv;
+            w[k] = (w[k] + eT[k - 1] * w[k - 1]) / piv;
+        }
+        for (int k = n - 2; k >= 0; --k) w[k] -= cp[k] * w[k + 1];
+    }
+    __syncthreads();
+    double acc[MS + 2];
+#pragma unroll
+    for (int k = 0; k < MS + 2; ++k) acc[k] = 0.0;
+    if (i < n) {
+        double tv = 0.0;
+        for (int k = 0; k < n; ++k) tv += Q[i * kPsp + k] * w[k];
+        T[d] = tv;
+        const double dt = tv - told;
+        acc[1] = tv * tv - told * told;
+        if (rs) {
+            acc[2] = x * dt;
+        } else {
+#pragma unroll
+            for (int k = 0; k < MS; ++k)
+                if (k < m) acc[2 + k] = V[(int64_t)k * b.dim + d] * dt;
+        }
+    }
+    const int nx = 2 + (rs ? 1 : m);
+#pragma unroll
+    for (int k = 0; k < MS + 2; ++k) {
+        if (k < nx) {
+            const double v = wave_sum(acc[k]);
+            if ((i & 63) == 0) red[i >> 6][k] = v;
+        }
+    }
+    __syncthreads();
+    if (i < nx) parts(b, t, b.nblk)[i] = red[0][i] + (kPsp > 64 ? red[1][i] : 0.0);
 }
 
 __device__ __forceinline__ double guess_noise(int64_t d) {
@@ -931,15 +1329,18 @@ __global__ void k_guess_pick(Batch b) {
     b.coef[(int64_t)t * kMaxSpace] = bi;
 }
 
-// V_0 = e_imin + 1e-3 * noise(d), partial norm^2
+// V_0 = e_imin + 1e-3 * noise(d) (with a P space: the noise alone, the P
+// eigenvector follows), partial norm^2
 __global__ __launch_bounds__(256) void k_guess_fill(Batch b) {
     const int t = blockIdx.y;
     const int64_t imin = (int64_t)b.coef[(int64_t)t * kMaxSpace];
     double *v0 = b.V + (int64_t)t * b.max_space * b.dim;
+    // a P space that is the whole space gives the exact eigenvector: no admixture
+    const double amp = (b.psp > 0 && b.psp >= b.dim) ? 0.0 : 1e-3;
     double acc[kParts];
     acc[0] = 0.0;
     for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-        const double v = (d == imin ? 1.0 : 0.0) + 1e-3 * guess_noise(d);
+        const double v = (d == imin && b.psp <= 0 ? 1.0 : 0.0) + amp * guess_noise(d);
         v0[d] = v;
         acc[0] += v * v;
     }
@@ -948,7 +1349,7 @@ __global__ __launch_bounds__(256) void k_guess_fill(Batch b) {
 
 __global__ void k_guess_norm(Batch b) {
     const int t = blockIdx.x;
-    if (threadIdx.x == 0) b.coef[(int64_t)t * kMaxSpace] = 1.0 / sqrt(sum_parts(b, t, 0));
+    if (threadIdx.x == 0) b.coef[(int64_t)t * kMaxSpace] = 1.0 / sqrt(sum_parts_x(b, t, 0));
 }
 
 __global__ __launch_bounds__(256) void k_scale_v0(Batch b) {
@@ -964,6 +1365,7 @@ hipError_t launch_guess(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_guess_min, grid, dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_guess_pick, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_guess_fill, grid, dim3(256), 0, s, b);
+    if (b.psp > 0) hipLaunchKernelGGL(k_psp_guess, dim3(b.B), dim3(kPsp), 0, s, b);
     hipLaunchKernelGGL(k_guess_norm, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_scale_v0, grid, dim3(256), 0, s, b);
     return hipGetLastError();
@@ -1187,7 +1589,7 @@ __global__ void k_converge(Batch b) {
     const double rn = sqrt(sum_parts(b, t, 0));
     const double th = b.theta[t];
     b.rnorm[t] = rn;
-    b.tnorm0[t] = sqrt(sum_parts(b, t, 1));
+    b.tnorm0[t] = sqrt(sum_parts_x(b, t, 1));
     int st = ST_RUNNING;
     if (!isfinite(rn) || !isfinite(th)) st = ST_NONFINITE;
     else if (rn < b.r_tol && fabs(th - b.theta_prev[t]) < b.e_tol) st = ST_DONE;
@@ -1209,13 +1611,17 @@ __global__ void k_coef1(Batch b) {
     const int t = blockIdx.x;
     if (b.status[t] != ST_RUNNING) return;
     const int m = b.m[t];
-    if ((int)threadIdx.x < m) b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = sum_parts(b, t, 2 + threadIdx.x);
+    if ((int)threadIdx.x < m) b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = sum_parts_x(b, t, 2 + threadIdx.x);
 }
 
 hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_small_eig, dim3(b.B), dim3(64), 0, s, b);
     if (b.max_space <= 12) hipLaunchKernelGGL(k_ritz<12>, dim3(b.nblk, b.B), dim3(256), 0, s, b);
     else hipLaunchKernelGGL(k_ritz<kMaxSpace>, dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    if (b.psp > 0) {
+        if (b.max_space <= 12) hipLaunchKernelGGL(k_psp_fix<12>, dim3(b.B), dim3(kPsp), 0, s, b);
+        else hipLaunchKernelGGL(k_psp_fix<kMaxSpace>, dim3(b.B), dim3(kPsp), 0, s, b);
+    }
     hipLaunchKernelGGL(k_converge, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_coef1, dim3(b.B), dim3(64), 0, s, b);
     return hipGetLastError();
@@ -1456,6 +1862,25 @@ __global__ void k_finalize(Batch b) {
 hipError_t launch_finalize(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3((b.B + 255) / 256), dim3(256), 0, s, b);
     return hipGetLastError();
+}
+
+hipError_t init_kernels() {
+    hipError_t e = hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_psp_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)psp_factor_lds());
+    if (e != hipSuccess) return e;
+    const void *strips[] = {(const void *)k_sigma_strip<1>,  (const void *)k_sigma_strip<2>,
+                            (const void *)k_sigma_strip<3>,  (const void *)k_sigma_strip<4>,
+                            (const void *)k_sigma_strip<5>,  (const void *)k_sigma_strip<6>,
+                            (const void *)k_sigma_strip<7>,  (const void *)k_sigma_strip<8>,
+                            (const void *)k_sigma_strip<9>,  (const void *)k_sigma_strip<10>,
+                            (const void *)k_sigma_strip<11>, (const void *)k_sigma_strip<12>,
+                            (const void *)k_sigma_strip<13>};
+    for (const void *f : strips) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace mbefci

@@ -218,6 +218,7 @@ struct ClassPlan {
     ParamLayout pl;
     int nblk;
     int variant;
+    int psp;   // P-space size of the Davidson preconditioner (0: diagonal only)
     bool rdm;
     int nblk_r, NP;
     size_t fixed_bytes, per_tuple;
@@ -239,6 +240,8 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     const int want = ctx->opt.sigma_variant;
     const bool fits = strip_fits(cp.pl, cp.ta->nstr, cp.ta->nent, cp.tb->nent);
     cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
+    cp.psp = (davidson && cp.variant == SIGMA_STRIP && ctx->opt.pspace > 0)
+                 ? (int)std::min<int64_t>(ctx->opt.pspace, cp.dim) : 0;
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
@@ -253,7 +256,8 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     if (cp.variant == SIGMA_WMAT) pt += 8 * (size_t)cp.pl.P * cp.dim;            // W
     else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr +                             // H_b, H_a
                (key.na != key.nb ? 8 * (size_t)cp.ta->nstr * cp.ta->nstr : 0);
-    pt += 8 * (size_t)cp.nblk * kParts;                      // partials
+    pt += 8 * (size_t)(cp.nblk + 1) * kParts;                // partials (+ P-space block)
+    if (cp.psp > 0) pt += 4 * (size_t)kPsp + 8 * (size_t)kPsp * kPsp + 24 * (size_t)kPsp + 3 * 256;
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
@@ -327,7 +331,16 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.Ha = b.na == b.nb ? b.Hb : cv.take<double>((size_t)B * b.Na * b.Na);
     }
     b.nblk = cp.nblk;
-    b.part = cv.take<double>((size_t)B * b.nblk * kParts);
+    b.part = cv.take<double>((size_t)B * (b.nblk + 1) * kParts);
+    b.psp = cp.psp;
+    if (cp.psp > 0) {
+        b.pidx = cv.take<int32_t>((size_t)B * kPsp);
+        b.pQ = cv.take<double>((size_t)B * kPsp * kPsp);
+        b.pT = cv.take<double>((size_t)B * 3 * kPsp);
+    } else {
+        b.pidx = nullptr;
+        b.pQ = b.pT = nullptr;
+    }
     b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.y = cv.take<double>((size_t)B * kMaxSpace);
     b.coef = cv.take<double>((size_t)B * kMaxSpace);
@@ -423,6 +436,7 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     if ((e = launch_build_hb(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if ((e = launch_hdiag(b, b.Hd, b.dim, 0, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if ((e = launch_init_state(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    if ((e = launch_pspace(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if ((e = launch_guess(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     const int64_t tstride = (int64_t)b.max_space * b.dim;
     VecRef vm{b.V, tstride, b.m, 0}, sm{b.S, tstride, b.m, 0};
@@ -766,6 +780,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->r_tol = 1e-6;
     o->max_iter = 200;
     o->max_space = 12;
+    o->pspace = kPsp;
     o->batched = 1;
     o->keep_vectors = 0;
     o->profile = 0;
@@ -899,6 +914,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->max_iter < 1) return ctx->fail(MBEFCI_EINVAL, "max_iter must be >= 1");
     if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
     if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
+    if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
     ctx->opt = *o;
     return MBEFCI_OK;
 }
