@@ -23,8 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |ΔE|≤1e-9 Eh"
 # HBM bytes per k_sigma_strip dispatch from the calibrated FETCH_SIZE / WRITE_SIZE
 # passes in profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md, valid only for
-# the kernel source they were taken on.
-TRAFFIC = {"kernels_sha1": "fdcb7558b17b6312d8f0785f93ef8add4cb8c765", "bytes_per_launch": 798330178.9}
+# the strip kernel source they were taken on (kernels_sha1 below).
+TRAFFIC = {"kernels_sha1": "3e3529d96fca46ed098f68867c5fdfa572d98582", "bytes_per_launch": 852005808.6}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -50,9 +50,13 @@ def count_tuples(res):
 
 
 def kernels_sha1():
+    """sha1 over the strip kernel's sources (sigma.hip, then device.h)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1905_02786_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+    h = hashlib.sha1()
+    for name in ("sigma.hip", "device.h"):
+        with open(os.path.join(ROOT, "paper_1905_02786_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(msg):

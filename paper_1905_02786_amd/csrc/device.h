@@ -1,0 +1,60 @@
+// Device helpers shared by the kernel sources.
+#pragma once
+#include "internal.h"
+
+namespace mbefci {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+#define ERI_AT(eri, n, p, q, r, s) (eri)[((((int64_t)(p) * (n) + (q)) * (n) + (r)) * (n) + (s))]
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block (blockDim.x a multiple of 64, at most 1024); result valid
+// in every thread.  `sh` holds >= 16 doubles.
+__device__ inline double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+    return r;
+}
+
+__device__ __forceinline__ void pair_of(int P, int &p, int &q) {
+    p = 0;
+    while ((p + 1) * (p + 2) / 2 <= P) ++p;
+    q = P - p * (p + 1) / 2;
+}
+
+__device__ __forceinline__ const double *vref(const VecRef &r, int t, int64_t dim) {
+    const int32_t k = r.idx ? r.idx[t] : r.idx_const;
+    return r.base + (int64_t)t * r.tstride + (int64_t)k * dim;
+}
+
+__device__ __forceinline__ void link_decode(uint32_t L, int &J, int &Q, double &sg) {
+    J = (int)(L & 0xFFFFFu);
+    Q = (int)((L >> 20) & 0x3FFu);
+    sg = (L >> 31) ? -1.0 : 1.0;
+}
+
+// Block partials of tuple t: [B][nblk + 1][kParts] (the extra block holds the
+// P-space corrections of the Davidson reductions).
+__device__ __forceinline__ double *parts(const Batch &b, int t, int blk) {
+    return b.part + ((int64_t)t * (b.nblk + 1) + blk) * kParts;
+}
+
+static inline int grid_for(int64_t work, int per_block, int cap) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace mbefci

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host planner (mbefci.cpp) and the HIP
-// kernels (kernels.hip) of libmbefci.so.
+// kernels (kernels.hip, sigma.hip) of libmbefci.so.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -102,12 +102,19 @@ struct Batch {
     double *rdm_G;          // [B][NP*NP]
 };
 
-// kernels.hip
+// kernels.hip and sigma.hip
 hipError_t init_kernels();
+hipError_t init_sigma_kernels();   // LDS limits of the sigma kernels (called by init_kernels)
 hipError_t launch_gather(const Batch &b, hipStream_t s);
 hipError_t launch_hdiag(const Batch &b, double *out, int64_t ostride, int add_ecore, hipStream_t s);
-hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done,
+// sigma = (H + shift) c; with `dots` and the column-strip variant the GEMM
+// also leaves the partial dots V_i . sig, i <= m, in partial blocks
+// 0 .. gemm_blocks(b) - 1 (sigma_fuses_dots)
+hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done, bool dots,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2);
+inline bool sigma_fuses_dots(const Batch &b) { return b.sigma_variant == SIGMA_STRIP; }
+int gemm_blocks(const Batch &b);
+hipError_t launch_update_G(const Batch &b, int nsum, hipStream_t s);
 hipError_t launch_guess(const Batch &b, hipStream_t s);
 hipError_t launch_init_state(const Batch &b, hipStream_t s);
 hipError_t launch_dots(const Batch &b, VecRef y, int nx_extra, hipStream_t s);

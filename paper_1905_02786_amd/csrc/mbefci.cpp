@@ -1,6 +1,7 @@
 // Host side of libmbefci.so: context, validation, string tables, the MBE
 // planner (tuple generation, screening, increment assembly; Eq. 1-3) and the
-// batch driver of the Davidson solver whose kernels live in kernels.hip.
+// batch driver of the Davidson solver whose kernels live in kernels.hip and
+// sigma.hip.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -237,6 +238,9 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.dim = cp.ta->nstr * cp.tb->nstr;
     cp.pl.init(key.nA);
     cp.nblk = nblk_for(cp.dim);
+    // the strip variant's GEMM writes one partial block per output tile (at
+    // most this many: 64 x 64 tiles)
+    cp.nblk = std::max<int64_t>(cp.nblk, ((cp.ta->nstr + 63) / 64) * ((cp.tb->nstr + 63) / 64));
     const int want = ctx->opt.sigma_variant;
     const bool fits = strip_fits(cp.pl, cp.ta->nstr, cp.ta->nent, cp.tb->nent);
     cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
@@ -408,13 +412,13 @@ void flush_sigma_time(mbefci_ctx *ctx) {
 }
 
 mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, double shift, bool skip_done,
-                        int64_t napps) {
+                        int64_t napps, bool dots = false) {
     const bool prof = ctx->opt.profile != 0;
     if (prof && ctx->sigma_pending) {   // a sigma whose events were not read yet
         HIPCHK(hipEventSynchronize(ctx->ev[2]));
         flush_sigma_time(ctx);
     }
-    hipError_t e = launch_sigma(b, c, s, shift, skip_done, ctx->stream, prof ? ctx->ev[0] : nullptr,
+    hipError_t e = launch_sigma(b, c, s, shift, skip_done, dots, ctx->stream, prof ? ctx->ev[0] : nullptr,
                                 prof ? ctx->ev[1] : nullptr, prof ? ctx->ev[2] : nullptr);
     if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, std::string("sigma launch: ") + hipGetErrorString(e));
     ctx->stats.sigma_launches += 1;
@@ -440,9 +444,17 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     if ((e = launch_guess(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     const int64_t tstride = (int64_t)b.max_space * b.dim;
     VecRef vm{b.V, tstride, b.m, 0}, sm{b.S, tstride, b.m, 0};
-    mbefci_status rc = run_sigma(ctx, b, vm, sm, 0.0, true, b.B);
+    // sigma of V_m into S_m, then column m of G (from the GEMM's partial dots
+    // where the sigma variant computes them)
+    auto sigma_and_G = [&](int64_t napps) -> mbefci_status {
+        const bool fused = sigma_fuses_dots(b);
+        mbefci_status r = run_sigma(ctx, b, vm, sm, 0.0, true, napps, fused);
+        if (r != MBEFCI_OK) return r;
+        hipError_t e2 = fused ? launch_update_G(b, gemm_blocks(b), s) : launch_dots(b, sm, 1, s);
+        return e2 == hipSuccess ? MBEFCI_OK : ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e2));
+    };
+    mbefci_status rc = sigma_and_G(b.B);
     if (rc != MBEFCI_OK) return rc;
-    if ((e = launch_dots(b, sm, 1, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     int32_t running = b.B;
     int iters = 0;
     for (int it = 0; it <= b.max_iter; ++it) {
@@ -454,9 +466,8 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
         ++iters;
         if (running == 0) break;
         if ((e = launch_orthonormalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-        rc = run_sigma(ctx, b, vm, sm, 0.0, true, running);
+        rc = sigma_and_G(running);
         if (rc != MBEFCI_OK) return rc;
-        if ((e = launch_dots(b, sm, 1, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     }
     if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if (gram) {
@@ -1044,7 +1055,7 @@ mbefci_status mbefci_tuple_sigma(mbefci_ctx *ctx, int32_t order, const int16_t *
     for (int v = 0; v < nvec; ++v) {
         VecRef c{const_cast<double *>(d_c), 0, nullptr, v};
         VecRef s{d_sigma, 0, nullptr, v};
-        hipError_t e = launch_sigma(b, c, s, ecore, false, ctx->stream, nullptr, nullptr, nullptr);
+        hipError_t e = launch_sigma(b, c, s, ecore, false, false, ctx->stream, nullptr, nullptr, nullptr);
         if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));

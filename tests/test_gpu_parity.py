@@ -216,6 +216,31 @@ def _solve_samples(P, fname, ws):
     print(f"{fname}: {len(g['samples'])} samples, max |dE| = {worst:.2e}")
 
 
+# Tuples spanning P spaces smaller than, equal to and larger than the CAS
+# (dims 1 ... 1225), on the strongly correlated Hubbard chain and the open-shell
+# problem; the U/t = 8 order-5 tuple is the hardest case for the P-space
+# preconditioner.
+PSPACE_CASES = [
+    ("hubbard8", (1, 2, 3, 6, 9)), ("hubbard8", (0, 2, 6)), ("hubbard8", (0,)), ("hubbard8", ()),
+    ("hubbard8", (0, 1, 2, 6)), ("openshell", ()), ("openshell", (1,)), ("openshell", (1, 4, 5, 6, 7)),
+]
+
+
+@pytest.mark.parametrize("pspace", [0, 1, 7, 128])
+def test_pspace_settings_match_oracle(ws, pspace):
+    probs = {"hubbard8": synth.config_hubbard(8.0), "openshell": PROBLEMS["openshell"]()}
+    worst = 0.0
+    for name, S in PSPACE_CASES:
+        P = probs[name]
+        ctx = _ctx(P, pspace=pspace)
+        e, st = ctx.solve_tuples(len(S), [S] if S else [()], ws)
+        e_ref = fci.casci_energy(P, S)
+        assert st[0] == 0, (name, S, pspace, st[0])
+        assert abs(e[0] - e_ref) <= 1e-10, (name, S, pspace, e[0], e_ref)
+        worst = max(worst, abs(e[0] - e_ref))
+    print(f"pspace {pspace}: max |dE| = {worst:.1e}")
+
+
 def test_sweep_sampled_tuples(ws):
     _solve_samples(synth.config_sweep(0), "sweep_sample.json", ws)
 

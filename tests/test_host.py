@@ -145,6 +145,10 @@ def test_invalid_inputs_rejected():
     assert e.value.code == -5                  # host-only context
     with pytest.raises(M.MBEFCIError):
         ctx.set_options(max_space=1)
+    for bad_psp in (-1, 129):
+        with pytest.raises(M.MBEFCIError):
+            ctx.set_options(pspace=bad_psp)
+    ctx.set_options(pspace=0)
 
 
 class _FakeTensor:
