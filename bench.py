@@ -50,10 +50,10 @@ def count_tuples(res):
 
 
 def kernels_sha1():
-    """sha1 over the strip kernel's sources (sigma.hip, then device.h)."""
+    """sha1 over the strip kernel's sources (strip.hip, then device.h)."""
     import hashlib
     h = hashlib.sha1()
-    for name in ("sigma.hip", "device.h"):
+    for name in ("strip.hip", "device.h"):
         with open(os.path.join(ROOT, "paper_1905_02786_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

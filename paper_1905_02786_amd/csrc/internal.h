@@ -1,5 +1,5 @@
 // Internal declarations shared by the host planner (mbefci.cpp) and the HIP
-// kernels (kernels.hip, sigma.hip) of libmbefci.so.
+// kernels (kernels.hip, sigma.hip, strip.hip) of libmbefci.so.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -102,9 +102,12 @@ struct Batch {
     double *rdm_G;          // [B][NP*NP]
 };
 
-// kernels.hip and sigma.hip
+// kernels.hip, sigma.hip and strip.hip
 hipError_t init_kernels();
 hipError_t init_sigma_kernels();   // LDS limits of the sigma kernels (called by init_kernels)
+hipError_t init_strip_kernels();   // the same for the strip kernels (called by init_sigma_kernels)
+// alpha-beta term of sigma (column strip, strip.hip): sig = X + shift c
+hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s);
 hipError_t launch_gather(const Batch &b, hipStream_t s);
 hipError_t launch_hdiag(const Batch &b, double *out, int64_t ostride, int add_ecore, hipStream_t s);
 // sigma = (H + shift) c; with `dots` and the column-strip variant the GEMM

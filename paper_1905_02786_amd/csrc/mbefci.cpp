@@ -1,7 +1,7 @@
 // Host side of libmbefci.so: context, validation, string tables, the MBE
 // planner (tuple generation, screening, increment assembly; Eq. 1-3) and the
-// batch driver of the Davidson solver whose kernels live in kernels.hip and
-// sigma.hip.
+// batch driver of the Davidson solver whose kernels live in kernels.hip,
+// sigma.hip and strip.hip.
 #include <algorithm>
 #include <chrono>
 #include <cmath>

@@ -1,0 +1,408 @@
+// Column-strip sigma kernel (gfx950 / CDNA4, FP64): the alpha-beta term of
+// sigma = H c for a batch of tuples of one shape class.
+#include "device.h"
+
+namespace mbefci {
+
+// ------------------------------------------------- column-strip variant --
+// With C the coefficient matrix (alpha strings x beta strings) and E^a_P,
+// E^b_P the spin parts of E+_P, the Hamiltonian splits as
+//   sigma = H_a C + C H_b^T + sum_PQ (P|Q) E^a_P C (E^b_Q)^T,
+// where H_s = sum_P k_P E^s_P + 1/2 sum_PQ (P|Q) E^s_P E^s_Q is the dense
+// string Hamiltonian of one spin (an N_s x N_s matrix per tuple, applied as
+// FP64 MFMA GEMMs).  The strip kernel computes the alpha-beta term: for each
+// alpha string K the beta part D^b_Q(K, I_b) = <I_b|E^b_Q|C(K, .)> uses row K
+// of C only; W = 1/2 (pq|rs) (2 D^b) (FP64 MFMA) is scattered through the
+// alpha links of K.  A workgroup owns 16 beta columns and keeps the sigma
+// strip sigma[:, B0..B0+15] in LDS.
+//
+// On this GPU an FP64 MFMA keeps the SIMD's vector ALU busy for its whole
+// duration, so every vector instruction of the loop costs MFMA time; the
+// loop is written to need few of them: per-item addresses and multipliers are
+// precomputed, the per-string parts of the load addresses are scalar, and the
+// host tables already hold strip byte offsets.
+
+// Pair order inside the strip kernel: the n_A diagonal pairs (p,p) first, then
+// the pairs p > q in packed order.  Returns the packed index p(p+1)/2 + q.
+__host__ __device__ inline int strip_pair_packed(int qs, int nA) {
+    if (qs < nA) return qs * (qs + 3) / 2;
+    const int m = qs - nA;
+    int p = 1;
+    while ((p + 1) * p / 2 <= m) ++p;
+    return p * (p + 1) / 2 + (m - p * (p - 1) / 2);
+}
+
+// Host tables of the strip kernel (columns in the strip pair order):
+//  * link form [N_s][P]: J in bits 0-19, bit 30 set when the string has a link
+//    through E+_Q, bit 31 its sign (a string has at most one link per pair);
+//  * scatter form [N_s + 1][P + 1]: byte offset J * 128 of the target row of
+//    the sigma strip for off-diagonal links, else the discard row (N_s * 128);
+//    bit 31 the sign; column P and row N_s are all discard.
+constexpr uint32_t kPairJ = 0xFFFFFu, kPairValid = 1u << 30, kPairSign = 1u << 31;
+
+// Compile-time shape of the strip kernel for n_A active orbitals.
+template <int NA>
+struct StripShape {
+    static constexpr int P = NA * (NA + 1) / 2;
+    static constexpr int Ppad = (P + 15) / 16 * 16;
+    static constexpr int Kpad = (P + 3) / 4 * 4;
+    static constexpr int KS = Kpad / 4;                        // MFMA K steps
+    static constexpr int DR = Kpad > P ? Kpad : P + 1;         // D rows: the K rows and a discard row (P)
+    static constexpr int MT = Ppad / 16 < 4 ? Ppad / 16 : 4;   // waves, one 16-row tile each (distinct SIMDs)
+    static constexpr int NX = Ppad / 16 - MT;                  // tiles past row 64, K split over the waves
+    static constexpr int XR = P > 64 ? P - 64 : 0;             // pair rows past 64
+    static constexpr int NTH = 64 * MT;
+    static constexpr int NXI = (XR * 16 + NTH - 1) / NTH;      // items per thread on rows past 64
+    static constexpr int KQ = (KS + 3) / 4;                    // K steps per wave in a tile past row 64
+    static constexpr int NI = 4 + NXI;                         // D / scatter items per thread
+};
+
+// LDS of the strip kernel (doubles): sigma strip [Na + 1][16] (row Na is a
+// discard row for masked-off stores), D [2][DR][16] (row P takes the masked
+// items' zeros; rows from P to Kpad meet zero A columns), per-wave partial W
+// of rows past 64 [2][4][XR][16].  For n_A = 11 and 462 alpha strings this is
+// 76.9 KB: two workgroups per CU.
+static size_t strip_lds(const ParamLayout &pl, int64_t Na) {
+    const int xr = pl.P > 64 ? pl.P - 64 : 0;
+    const int dr = pl.Kpad > pl.P ? pl.Kpad : pl.P + 1;
+    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 2 * (size_t)dr * kStrip + 8 * (size_t)xr * kStrip);
+}
+
+size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na) { return strip_lds(pl, Na); }
+
+bool strip_fits(const ParamLayout &pl, int64_t Na, int, int) {
+    return pl.nA >= 1 && pl.nA <= kMaxActive && strip_lds(pl, Na) <= 160 * 1024 && Na < (1 << 24);
+}
+
+// Workgroups are handed to the 8 XCDs round-robin by linear id; map id L to
+// (tuple, strip) so that every strip of tuple t runs on XCD t % 8 and the
+// strips of one tuple are dispatched back to back: its vector stays in that
+// XCD's L2 while they run.
+__device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, int &strip) {
+    const int64_t xcd = L % kXcds, j = L / kXcds;
+    t = (int)((j / nstrips) * kXcds + xcd);
+    strip = (int)(j % nstrips);
+    return t < B;
+}
+
+// Sum of x over the four lanes l, l^16, l^32, l^48 (the (lane >> 4) groups of
+// an MFMA output column), as ((x0 + x1) + (x2 + x3)) in every one of them:
+// row swaps of 16 and 32 lanes on the vector ALU, no LDS round trip.
+__device__ __forceinline__ double sum_over_kr(double x) {
+    const unsigned lo = __double2loint(x), hi = __double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double s = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+    const unsigned lo2 = __double2loint(s), hi2 = __double2hiint(s);
+    const auto c = __builtin_amdgcn_permlane32_swap(lo2, lo2, false, false);
+    const auto d = __builtin_amdgcn_permlane32_swap(hi2, hi2, false, false);
+    return __hiloint2double(d[0], c[0]) + __hiloint2double(d[1], c[1]);
+}
+
+// One workgroup per (tuple, 16-column strip), MT waves.  Thread items: the
+// pair rows Q = 16 w + (lane >> 4) + 4 v (v < 4) of its wave's MFMA output
+// tile, column lane & 15, plus rows past 64 spread over the block.  The same
+// thread writes D for its items and scatters W of those items (rows < 64
+// straight from the MFMA registers).  The diagonal pairs are rows 0..n_A-1,
+// all in wave 0, which sums them for the string with a lane mask and two
+// cross-lane row swaps.  Software pipeline over the alpha strings, one barrier
+// per step: in the step of string K the block
+//   - runs the MFMA of string K on D[K & 1] (results read one step later),
+//   - stores the partial rows past 64 of W(K-1) and sums its diagonal pairs,
+//   - scatters W of string K-2 into the LDS strip and adds its diagonal sum,
+//   - writes D of string K+1 into D[(K+1) & 1] from C row K+1,
+//   - loads row K+2 of C at the beta-link columns of its items and the
+//     scatter-table row of string K+2.
+// Each phase touches a buffer no other phase of the same step touches, and
+// the scatter of one string has no write conflicts: each link of a string
+// reaches a different string, and its diagonal sum goes to the string itself.
+// Masked-off stores go to the discard row, so the step has no branches
+// besides wave 0's diagonal sum.
+template <int NA>
+__global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b, VecRef cref, VecRef sref,
+                                                                          double shift, int skip_done) {
+    using S = StripShape<NA>;
+    constexpr int P = S::P, KP = S::Kpad, DR = S::DR, KS = S::KS, NX = S::NX, XR = S::XR, NTH = S::NTH,
+                  NI = S::NI, KQ = S::KQ, NXA = NX > 0 ? NX : 1;
+    constexpr uint32_t DB = DR * kStrip * sizeof(double);   // byte stride of the D buffers
+    const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
+    int t, strip_id;
+    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ar = lane & 15, kr = lane >> 4;
+    // determinant indices fit 32 bits (dim <= C(13,6)^2)
+    const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
+    const uint32_t B0 = (uint32_t)strip_id * kStrip;
+    const bool colok = B0 + ar < Nb;
+    extern __shared__ double lds[];
+    double *strip = lds;                   // [Na + 1][16]
+    double *D = strip + (Na + 1) * kStrip; // [2][DR][16]
+    double *Wx = D + 2 * DR * kStrip;      // [2][4][XR][16]
+    double *const dump = strip + Na * kStrip + ar;
+    const ParamLayout &pl = b.pl;
+    const double *prm = b.params + (int64_t)t * pl.stride;
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
+                                                                        (int)(b.dim * sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(b.scatA), (short)0, (int)((Na + 1) * (P + 1) * sizeof(uint32_t)), 0x00020000);
+
+    // A fragments of (pq|rs) (twice the stored 1/2 (pq|rs), so that D is the
+    // signed C value itself) in the strip pair order: this wave's rows, and
+    // its K quarter of the rows past 64
+    auto eri_at = [&](int r, int k) -> double {
+        return (r < P && k < P) ? 2.0 * prm[pl.off_eri + strip_pair_packed(r, NA) * KP + strip_pair_packed(k, NA)] : 0.0;
+    };
+    double af[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) af[ks] = eri_at(w * 16 + ar, ks * 4 + kr);
+    double afx[NXA][KQ];
+#pragma unroll
+    for (int x = 0; x < NXA; ++x)
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            const int ks = w * KQ + j;
+            afx[x][j] = (x < NX && ks < KS) ? eri_at(64 + 16 * x + ar, ks * 4 + kr) : 0.0;
+        }
+    // items: pair row, D slot (LDS byte address in buffer 0), beta link
+    // (byte offset in a row of C, past the buffer when there is no link so
+    // that the load gives zero; its sign as the bit flipped in the high
+    // word), scatter-table byte offset
+    int qi[NI];
+    uint32_t dsl[NI], boff[NI], qa[NI], bsg[NI];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qi[v] = w * 16 + kr + 4 * v;
+#pragma unroll
+    for (int r = 0; r < NI - 4; ++r) {
+        const int j = tid + NTH * r;
+        qi[4 + r] = j < XR * 16 ? 64 + (j >> 4) : P;
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const bool ok = colok && qi[i] < P;
+        const uint32_t eb = ok ? b.pairB[(B0 + ar) * (uint32_t)P + qi[i]] : 0u;
+        const bool vb = (eb & kPairValid) != 0;
+        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
+        bsg[i] = vb ? (eb & kPairSign) : 0u;
+        qa[i] = (uint32_t)(qi[i] < P ? qi[i] : P) * (uint32_t)sizeof(uint32_t);
+        dsl[i] = (uint32_t)(D + qi[i] * kStrip + ar - lds) * (uint32_t)sizeof(double);
+    }
+    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += NTH) strip[i] = 0.0;
+    for (int i = tid; i < 2 * DR * kStrip; i += NTH) D[i] = 0.0;
+
+    const uint32_t rowC = Nb * (uint32_t)sizeof(double), rowS = (P + 1) * (uint32_t)sizeof(uint32_t);
+    auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    double cb[NI];
+    // row byte offsets are wave-uniform: readfirstlane keeps them in scalar
+    // registers (the buffer loads' scalar offset operand)
+    auto load_c = [&](uint32_t s, int i) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                              rc, boff[i], __builtin_amdgcn_readfirstlane(s * rowC), 0));
+    };
+    auto load_s = [&](uint32_t s, int i) -> uint32_t {
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, qa[i], __builtin_amdgcn_readfirstlane(s * rowS), 0);
+    };
+    auto dval = [&](int i) -> double {   // D entry of item i: the signed C value
+        return __hiloint2double(__double2hiint(cb[i]) ^ (int)bsg[i], __double2loint(cb[i]));
+    };
+
+    // rows past 64: few of them (n_A = 11) go through vector FMAs on this
+    // wave's K quarter instead of a mostly empty MFMA tile
+    constexpr bool XV = NX == 1 && XR <= 4;
+    constexpr int XVR = XV ? XR : 1;
+    double axv[XVR][KQ];
+#pragma unroll
+    for (int r = 0; r < XVR; ++r)
+#pragma unroll
+        for (int j = 0; j < KQ; ++j) {
+            const int ks = w * KQ + j;
+            axv[r][j] = (XV && ks < KS) ? eri_at(64 + r, ks * 4 + kr) : 0.0;
+        }
+    const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
+    uint32_t eA[NI], eB[NI];   // scatter entries (string K-2 is scattered, string K-1 loaded, alternately)
+    double w2[4];              // W of string K-2 on this thread's wave rows
+    double dg1 = 0.0;          // diagonal sum of the previous string (wave 0)
+    // prologue: D of string 0 and C row 1
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        cb[i] = load_c(0, i);
+        eA[i] = load_s(Na, i);   // discard row
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NI; ++i) *lds_at(dsl[i]) = dval(i);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) cb[i] = load_c(Na > 1 ? 1u : 0u, i);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w2[v] = 0.0;
+    uint32_t sa1 = 0u;   // alpha string K-1
+    dbl4 accA[1 + NXA], accB[1 + NXA];   // the wave tile, then the rows past 64
+#pragma unroll
+    for (int j = 0; j < 1 + NXA; ++j) accA[j] = accB[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+
+    // Pipeline step of string K: MFMA of K into `an` (read back one step
+    // later, so no wave waits for its own MFMA results), epilogue of K-1
+    // from `ao`, scatter of K-2 with entries `ep` while the entries of K-1
+    // load into `en`, D of K+1, C row K+2.  Steps past the last string run on
+    // stale data whose results are discarded: their scatter entries come from
+    // the discard row and their diagonal sums are dropped.
+    auto step = [&](uint32_t K, dbl4 (&an)[1 + NXA], dbl4 (&ao)[1 + NXA], uint32_t (&ep)[NI],
+                    uint32_t (&en)[NI]) {
+        const double *Dk = D + (K & 1) * DR * kStrip;
+        {
+            double bv[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bv[ks] = Dk[(ks * 4 + kr) * kStrip + ar];
+            dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
+            an[0] = a;
+        }
+        if (NX > 0) {
+            // rows past 64: this wave's K quarter (its own B operands)
+            double bx[KQ];
+#pragma unroll
+            for (int j = 0; j < KQ; ++j) {
+                const int ks = w * KQ + j;
+                bx[j] = Dk[((ks < KS ? ks : 0) * 4 + kr) * kStrip + ar];
+            }
+            if (XV) {
+                // lane (kr, ar): partial over k = kr (mod 4) of the quarter, then summed over kr
+#pragma unroll
+                for (int r = 0; r < XVR; ++r) {
+                    double pr = 0.0;
+#pragma unroll
+                    for (int j = 0; j < KQ; ++j) pr = __builtin_fma(axv[r][j], bx[j], pr);
+                    an[1][r] = sum_over_kr(pr);
+                }
+            } else {
+#pragma unroll
+                for (int x = 0; x < NXA; ++x) {
+                    dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = 0; j < KQ; ++j) a = __builtin_amdgcn_mfma_f64_16x16x4f64(afx[x][j], bx[j], a, 0, 0, 0);
+                    an[1 + x] = a;
+                }
+            }
+        }
+        // epilogue of string K-1: this wave's partial rows past 64 to LDS
+        if (NX > 0) {
+            double *wx = Wx + (((K + 1) & 1) * 4 + w) * XR * kStrip;
+            if (XV) {
+#pragma unroll
+                for (int r = 0; r < XVR; ++r) *(kr == 0 ? wx + r * kStrip + ar : dump) = ao[1][r];
+            } else {
+#pragma unroll
+                for (int x = 0; x < NXA; ++x)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * x + kr + 4 * v;
+                        *(r < XR ? wx + r * kStrip + ar : dump) = ao[1 + x][v];
+                    }
+            }
+        }
+        // scatter of string K-2 through its off-diagonal alpha links
+        const double *wx2 = Wx + (K & 1) * 4 * XR * kStrip;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const uint32_t e = ep[i];
+            double wv;
+            if (i < 4) {
+                wv = w2[i < 4 ? i : 0];
+            } else {
+                const int r = qi[i] < P ? qi[i] - 64 : 0;
+                wv = wx2[r * kStrip + ar] + wx2[(XR + r) * kStrip + ar] + wx2[(2 * XR + r) * kStrip + ar] +
+                     wx2[(3 * XR + r) * kStrip + ar];
+            }
+            // strip row at byte offset e & 0x7FFFFFFF (a multiple of 128), column ar; sign in bit 31
+            double *d = lds_at((e & 0x7FFFFFFFu) | ar8);
+            *d += __hiloint2double(__double2hiint(wv) ^ (int)(e & kPairSign), __double2loint(wv));
+        }
+        // D of string K+1 (C row K+1 was loaded one step ago)
+#pragma unroll
+        for (int i = 0; i < NI; ++i) *lds_at(dsl[i] + ((K + 1) & 1) * DB) = dval(i);
+        // loads: C row K+2, scatter entries of string K-1 (scattered next step)
+        const uint32_t K2c = K + 2 < Na ? K + 2 : Na - 1, K1s = (K >= 1 && K - 1 < Na) ? K - 1 : Na;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            cb[i] = load_c(K2c, i);
+            en[i] = load_s(K1s, i);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w2[v] = ao[0][v];
+        // diagonal pairs: rows 0..NA-1 of wave 0.  Add the sum of string K-2,
+        // then form the sum of string K-1 (lane mask of its occupied orbitals,
+        // fixed order: v within the lane, then lanes (kr, kr^1), then (kr, kr^2)).
+        if (w == 0) {
+            if (kr == 0 && K >= 2 && K - 2 < Na) strip[(K - 2) * kStrip + ar] += dg1;
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (4 * v < NA) s += ((sa1 >> (kr + 4 * v)) & 1u) ? ao[0][v] : 0.0;
+            dg1 = sum_over_kr(s);
+        }
+        const uint32_t sk = b.strA[K < Na ? K : Na - 1];
+        sa1 = K < Na ? sk : 0u;
+        __syncthreads();
+    };
+    for (uint32_t K = 0; K < Na + 2; K += 2) {
+        step(K, accA, accB, eA, eB);
+        step(K + 1, accB, accA, eB, eA);
+    }
+    for (uint32_t i = tid; i < Na * kStrip; i += NTH) {
+        const uint32_t row = i / kStrip, col = i % kStrip;
+        if (B0 + col < Nb) {
+            const uint32_t d = row * Nb + B0 + col;
+            sg[d] = strip[i] + shift * c[d];
+        }
+    }
+}
+
+template <int NA>
+static hipError_t launch_strip_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+    const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
+    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
+    hipLaunchKernelGGL(k_sigma_strip<NA>, grid, dim3(StripShape<NA>::NTH), strip_lds(b.pl, b.Na), s, b, c, sig,
+                       shift, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+    switch (b.nA) {
+        case 1: return launch_strip_na<1>(b, c, sig, shift, skip, s);
+        case 2: return launch_strip_na<2>(b, c, sig, shift, skip, s);
+        case 3: return launch_strip_na<3>(b, c, sig, shift, skip, s);
+        case 4: return launch_strip_na<4>(b, c, sig, shift, skip, s);
+        case 5: return launch_strip_na<5>(b, c, sig, shift, skip, s);
+        case 6: return launch_strip_na<6>(b, c, sig, shift, skip, s);
+        case 7: return launch_strip_na<7>(b, c, sig, shift, skip, s);
+        case 8: return launch_strip_na<8>(b, c, sig, shift, skip, s);
+        case 9: return launch_strip_na<9>(b, c, sig, shift, skip, s);
+        case 10: return launch_strip_na<10>(b, c, sig, shift, skip, s);
+        case 11: return launch_strip_na<11>(b, c, sig, shift, skip, s);
+        case 12: return launch_strip_na<12>(b, c, sig, shift, skip, s);
+        case 13: return launch_strip_na<13>(b, c, sig, shift, skip, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t init_strip_kernels() {
+    hipError_t e = hipSuccess;
+    const void *strips[] = {(const void *)k_sigma_strip<1>,  (const void *)k_sigma_strip<2>,
+                            (const void *)k_sigma_strip<3>,  (const void *)k_sigma_strip<4>,
+                            (const void *)k_sigma_strip<5>,  (const void *)k_sigma_strip<6>,
+                            (const void *)k_sigma_strip<7>,  (const void *)k_sigma_strip<8>,
+                            (const void *)k_sigma_strip<9>,  (const void *)k_sigma_strip<10>,
+                            (const void *)k_sigma_strip<11>, (const void *)k_sigma_strip<12>,
+                            (const void *)k_sigma_strip<13>};
+    for (const void *f : strips) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mbefci
