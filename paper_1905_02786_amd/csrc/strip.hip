@@ -317,9 +317,12 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
                 wv = wx2[r * kStrip + ar] + wx2[(XR + r) * kStrip + ar] + wx2[(2 * XR + r) * kStrip + ar] +
                      wx2[(3 * XR + r) * kStrip + ar];
             }
-            // strip row at byte offset e & 0x7FFFFFFF (a multiple of 128), column ar; sign in bit 31
+            // strip row at byte offset e & 0x7FFFFFFF (a multiple of 128), column ar; sign in bit 31.
+            // The add is done by the LDS unit (no address of the step is hit
+            // twice, so this is the plain sum in the same order)
             double *d = lds_at((e & 0x7FFFFFFFu) | ar8);
-            *d += __hiloint2double(__double2hiint(wv) ^ (int)(e & kPairSign), __double2loint(wv));
+            __builtin_amdgcn_ds_atomic_fadd_f64((__attribute__((address_space(3))) double *)d,
+                                                __hiloint2double(__double2hiint(wv) ^ (int)(e & kPairSign), __double2loint(wv)));
         }
         // D of string K+1 (C row K+1 was loaded one step ago)
 #pragma unroll
