@@ -99,6 +99,39 @@ __device__ __forceinline__ double sum_over_kr(double x) {
     return __hiloint2double(d[0], c[0]) + __hiloint2double(d[1], c[1]);
 }
 
+// Row swaps of two values: 16-lane rows (odd rows of x with even rows of y)
+// and 32-lane halves (upper half of x with lower half of y).
+__device__ __forceinline__ void swap16(double &x, double &y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    x = __hiloint2double(hi[0], lo[0]);
+    y = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ void swap32(double &x, double &y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    x = __hiloint2double(hi[0], lo[0]);
+    y = __hiloint2double(hi[1], lo[1]);
+}
+
+// Four such sums at once: lane group g (lanes 16 g .. 16 g + 15) of the result
+// holds the sum of input g (a, b, c, d) over the four groups, in the same
+// order ((x0 + x1) + (x2 + x3)) as sum_over_kr.
+__device__ __forceinline__ double group_sums4(double a, double b, double c, double d) {
+    swap16(a, b);
+    swap16(c, d);
+    double s = a + b, t = c + d;   // [a0+a1, b0+b1, a2+a3, b2+b3], [c0+c1, d0+d1, c2+c3, d2+d3]
+    swap32(s, t);                  // [a01, b01, c01, d01], [a23, b23, c23, d23]
+    return s + t;
+}
+// The same for two inputs (groups 0, 2: a; 1, 3: b).
+__device__ __forceinline__ double group_sums2(double a, double b) {
+    swap16(a, b);
+    double s = a + b, t = s;
+    swap32(s, t);
+    return s + t;
+}
+
 // One workgroup per (tuple, 16-column strip), MT waves.  Thread items: the
 // pair rows Q = 16 w + (lane >> 4) + 4 v (v < 4) of its wave's MFMA output
 // tile, column lane & 15, plus rows past 64 spread over the block.  The same
@@ -210,8 +243,11 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
 
     // rows past 64: few of them (n_A = 11) go through vector FMAs on this
     // wave's K quarter instead of a mostly empty MFMA tile
-    constexpr bool XV = NX == 1 && XR <= 4;
+    constexpr bool XV = NX == 1 && XR <= 2;
     constexpr int XVR = XV ? XR : 1;
+    // With XV the group sums of the rows past 64 (groups 0 and 1) and, in
+    // wave 0, of the diagonal pairs (group 2) come from one exchange.
+    constexpr uint32_t DGK = XV ? 2u : 0u;   // lane group holding the diagonal sum
     double axv[XVR][KQ];
 #pragma unroll
     for (int r = 0; r < XVR; ++r)
@@ -223,7 +259,8 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
     const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
     uint32_t eA[NI], eB[NI];   // scatter entries (string K-2 is scattered, string K-1 loaded, alternately)
     double w2[4];              // W of string K-2 on this thread's wave rows
-    double dg1 = 0.0;          // diagonal sum of the previous string (wave 0)
+    double dg1 = 0.0;          // diagonal sum of the previous string (wave 0, lane group DGK)
+    double xp[2] = {0.0, 0.0}; // XV partials of the rows past 64 of the current string
     // prologue: D of string 0 and C row 1
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -270,13 +307,14 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
                 bx[j] = Dk[((ks < KS ? ks : 0) * 4 + kr) * kStrip + ar];
             }
             if (XV) {
-                // lane (kr, ar): partial over k = kr (mod 4) of the quarter, then summed over kr
+                // lane (kr, ar): partial over k = kr (mod 4) of the quarter,
+                // summed over kr at the end of the step
 #pragma unroll
                 for (int r = 0; r < XVR; ++r) {
                     double pr = 0.0;
 #pragma unroll
                     for (int j = 0; j < KQ; ++j) pr = __builtin_fma(axv[r][j], bx[j], pr);
-                    an[1][r] = sum_over_kr(pr);
+                    xp[r] = pr;
                 }
             } else {
 #pragma unroll
@@ -292,8 +330,7 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
         if (NX > 0) {
             double *wx = Wx + (((K + 1) & 1) * 4 + w) * XR * kStrip;
             if (XV) {
-#pragma unroll
-                for (int r = 0; r < XVR; ++r) *(kr == 0 ? wx + r * kStrip + ar : dump) = ao[1][r];
+                *(kr < XVR ? wx + kr * kStrip + ar : dump) = ao[1][0];   // row kr from lane group kr
             } else {
 #pragma unroll
                 for (int x = 0; x < NXA; ++x)
@@ -340,12 +377,21 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
         // then form the sum of string K-1 (lane mask of its occupied orbitals,
         // fixed order: v within the lane, then lanes (kr, kr^1), then (kr, kr^2)).
         if (w == 0) {
-            if (kr == 0 && K >= 2 && K - 2 < Na) strip[(K - 2) * kStrip + ar] += dg1;
-            double s = 0.0;
+            if (kr == DGK && K >= 2 && K - 2 < Na)
+                __builtin_amdgcn_ds_atomic_fadd_f64((__attribute__((address_space(3))) double *)(strip + (K - 2) * kStrip + ar), dg1);
+            double s = ((sa1 >> kr) & 1u) ? ao[0][0] : 0.0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 1; v < 4; ++v)
                 if (4 * v < NA) s += ((sa1 >> (kr + 4 * v)) & 1u) ? ao[0][v] : 0.0;
-            dg1 = sum_over_kr(s);
+            if (XV) {
+                const double g = group_sums4(xp[0], XVR > 1 ? xp[1] : 0.0, s, 0.0);
+                an[1][0] = g;
+                dg1 = g;
+            } else {
+                dg1 = sum_over_kr(s);
+            }
+        } else if (XV) {
+            an[1][0] = group_sums2(xp[0], XVR > 1 ? xp[1] : 0.0);
         }
         const uint32_t sk = b.strA[K < Na ? K : Na - 1];
         sa1 = K < Na ? sk : 0u;
