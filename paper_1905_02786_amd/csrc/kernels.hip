@@ -799,16 +799,22 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     for (int i = tid; i < mm; i += 64) order[i] = i;
     __syncthreads();
     const int half = mm / 2;
+    // rotation loops: for mm <= 16 item idx is pair idx >> 4, row or column
+    // idx & 15 (no integer division); larger subspaces use idx / mm, idx % mm
+    const bool small = mm <= 16;
     for (int sweep = 0; sweep < 30; ++sweep) {
-        if (tid == 0) {
+        {
+            // off-diagonal and total squared norms (lane-parallel, fixed order)
             double off = 0.0, tot = 0.0;
-            for (int r = 0; r < m; ++r)
-                for (int c = 0; c < m; ++c) {
-                    const double a2 = A[r][c] * A[r][c];
-                    tot += a2;
-                    if (r != c) off += a2;
-                }
-            done = (off <= 1e-34 * tot) ? 1 : 0;
+            for (int i = tid; i < m * m; i += 64) {
+                const int r = i / m, c = i % m;
+                const double a2 = A[r][c] * A[r][c];
+                tot += a2;
+                if (r != c) off += a2;
+            }
+            off = wave_sum(off);
+            tot = wave_sum(tot);
+            if (tid == 0) done = (off <= 1e-34 * tot) ? 1 : 0;
         }
         __syncthreads();
         if (done) break;
@@ -831,8 +837,9 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
             }
             __syncthreads();
             // columns: A <- A J, V <- V J
-            for (int idx = tid; idx < half * mm; idx += 64) {
-                const int k = idx / mm, r = idx % mm;
+            for (int idx = tid; idx < half * (small ? 16 : mm); idx += 64) {
+                const int k = small ? idx >> 4 : idx / mm, r = small ? idx & 15 : idx % mm;
+                if (r >= mm) continue;
                 const int p = pa[k], q = pb[k];
                 const double c = cs[k], s = sn[k];
                 const double arp = A[r][p], arq = A[r][q];
@@ -844,8 +851,9 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
             }
             __syncthreads();
             // rows: A <- J^T A
-            for (int idx = tid; idx < half * mm; idx += 64) {
-                const int k = idx / mm, col = idx % mm;
+            for (int idx = tid; idx < half * (small ? 16 : mm); idx += 64) {
+                const int k = small ? idx >> 4 : idx / mm, col = small ? idx & 15 : idx % mm;
+                if (col >= mm) continue;
                 const int p = pa[k], q = pb[k];
                 const double c = cs[k], s = sn[k];
                 const double apc = A[p][col], aqc = A[q][col];
