@@ -885,7 +885,7 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
 // partials |r|^2, |T|^2 and the first Gram-Schmidt projections V_i . T of the
 // subspace the correction is added to (V_i, i < m, or x alone on restart).
 // On restart, V_0 <- x and S_0 <- Ax in place (each thread owns its d).
-template <int MS>
+template <int MS, bool V2>
 __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     const int t = blockIdx.y;
     if (b.status[t] != ST_RUNNING) return;
@@ -902,32 +902,72 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     double acc[MS + 2];
 #pragma unroll
     for (int i = 0; i < MS + 2; ++i) acc[i] = 0.0;
-    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-        double x = 0.0, ax = 0.0, vd[MS];
-#pragma unroll
-        for (int i = 0; i < MS; ++i) {
-            vd[i] = 0.0;
-            if (i < m) {
-                vd[i] = V[(int64_t)i * b.dim + d];
-                x += yy[i] * vd[i];
-                ax += yy[i] * S[(int64_t)i * b.dim + d];
-            }
-        }
+    // one determinant: Ritz vector, residual, preconditioned correction and
+    // the first Gram-Schmidt projections
+    auto one = [&](const double (&vd)[MS], double x, double ax, double h) -> double {
         const double r = ax - th * x;
         acc[0] += r * r;
-        double den = th - hd[d];
+        double den = th - h;
         if (fabs(den) < 1e-8) den = (den >= 0.0) ? 1e-8 : -1e-8;
         const double tv = r / den;
-        T[d] = tv;
         acc[1] += tv * tv;
         if (rs) {
-            V[d] = x;
-            S[d] = ax;
             acc[2] += x * tv;
         } else {
 #pragma unroll
             for (int i = 0; i < MS; ++i)
                 if (i < m) acc[2 + i] += vd[i] * tv;
+        }
+        return tv;
+    };
+    if (V2) {
+        // pairs of determinants with 16-byte loads (dim even: every vector 16-byte aligned)
+        typedef double dbl2 __attribute__((ext_vector_type(2)));
+        const int64_t n2 = b.dim >> 1;
+        for (int64_t d2 = (int64_t)blockIdx.x * 256 + threadIdx.x; d2 < n2; d2 += (int64_t)gridDim.x * 256) {
+            const int64_t d = d2 << 1;
+            double v0[MS], v1[MS];
+            double x0 = 0.0, x1 = 0.0, a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < MS; ++i) {
+                v0[i] = v1[i] = 0.0;
+                if (i < m) {
+                    const dbl2 vv = *reinterpret_cast<const dbl2 *>(V + (int64_t)i * b.dim + d);
+                    const dbl2 ss = *reinterpret_cast<const dbl2 *>(S + (int64_t)i * b.dim + d);
+                    v0[i] = vv.x;
+                    v1[i] = vv.y;
+                    x0 += yy[i] * vv.x;
+                    x1 += yy[i] * vv.y;
+                    a0 += yy[i] * ss.x;
+                    a1 += yy[i] * ss.y;
+                }
+            }
+            const dbl2 h = *reinterpret_cast<const dbl2 *>(hd + d);
+            const double t0 = one(v0, x0, a0, h.x);
+            const double t1 = one(v1, x1, a1, h.y);
+            *reinterpret_cast<dbl2 *>(T + d) = dbl2{t0, t1};
+            if (rs) {
+                *reinterpret_cast<dbl2 *>(V + d) = dbl2{x0, x1};
+                *reinterpret_cast<dbl2 *>(S + d) = dbl2{a0, a1};
+            }
+        }
+    } else {
+        for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
+            double x = 0.0, ax = 0.0, vd[MS];
+#pragma unroll
+            for (int i = 0; i < MS; ++i) {
+                vd[i] = 0.0;
+                if (i < m) {
+                    vd[i] = V[(int64_t)i * b.dim + d];
+                    x += yy[i] * vd[i];
+                    ax += yy[i] * S[(int64_t)i * b.dim + d];
+                }
+            }
+            T[d] = one(vd, x, ax, hd[d]);
+            if (rs) {
+                V[d] = x;
+                S[d] = ax;
+            }
         }
     }
     store_block_partials<MS + 2>(b, t, acc, 2 + (rs ? 1 : m));
@@ -967,8 +1007,14 @@ __global__ void k_coef1(Batch b) {
 
 hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_small_eig, dim3(b.B), dim3(64), 0, s, b);
-    if (b.max_space <= 12) hipLaunchKernelGGL(k_ritz<12>, dim3(b.nblk, b.B), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL(k_ritz<kMaxSpace>, dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    const bool v2 = (b.dim & 1) == 0;
+    if (b.max_space <= 12) {
+        if (v2) hipLaunchKernelGGL((k_ritz<12, true>), dim3(b.nblk, b.B), dim3(256), 0, s, b);
+        else hipLaunchKernelGGL((k_ritz<12, false>), dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    } else {
+        if (v2) hipLaunchKernelGGL((k_ritz<kMaxSpace, true>), dim3(b.nblk, b.B), dim3(256), 0, s, b);
+        else hipLaunchKernelGGL((k_ritz<kMaxSpace, false>), dim3(b.nblk, b.B), dim3(256), 0, s, b);
+    }
     if (b.psp > 0) {
         if (b.max_space <= 12) hipLaunchKernelGGL(k_psp_fix<12>, dim3(b.B), dim3(kPsp), 0, s, b);
         else hipLaunchKernelGGL(k_psp_fix<kMaxSpace>, dim3(b.B), dim3(kPsp), 0, s, b);
@@ -987,7 +1033,7 @@ __global__ void k_coef(Batch b) {
 }
 
 // T -= sum_i coef_i V_i, partial |T|^2 (second pass: flagged tuples only)
-template <int MS>
+template <int MS, bool V2>
 __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
     const int t = blockIdx.y;
     if (b.status[t] != ST_RUNNING || (only2 && !b.cgs2[t])) return;
@@ -1000,13 +1046,36 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
     double *T = b.T + (int64_t)t * b.dim;
     double acc[1];
     acc[0] = 0.0;
-    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-        double v = T[d];
+    if (V2) {
+        // pairs of determinants with 16-byte loads (dim even), all loads first
+        typedef double dbl2 __attribute__((ext_vector_type(2)));
+        const int64_t n2 = b.dim >> 1;
+        for (int64_t d2 = (int64_t)blockIdx.x * 256 + threadIdx.x; d2 < n2; d2 += (int64_t)gridDim.x * 256) {
+            const int64_t d = d2 << 1;
+            dbl2 vv[MS];
 #pragma unroll
-        for (int i = 0; i < MS; ++i)
-            if (i < m) v -= cf[i] * V[(int64_t)i * b.dim + d];
-        T[d] = v;
-        acc[0] += v * v;
+            for (int i = 0; i < MS; ++i)
+                vv[i] = (i < m) ? *reinterpret_cast<const dbl2 *>(V + (int64_t)i * b.dim + d) : dbl2{0.0, 0.0};
+            dbl2 v = *reinterpret_cast<const dbl2 *>(T + d);
+#pragma unroll
+            for (int i = 0; i < MS; ++i)
+                if (i < m) {
+                    v.x -= cf[i] * vv[i].x;
+                    v.y -= cf[i] * vv[i].y;
+                }
+            *reinterpret_cast<dbl2 *>(T + d) = v;
+            acc[0] += v.x * v.x;
+            acc[0] += v.y * v.y;
+        }
+    } else {
+        for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
+            double v = T[d];
+#pragma unroll
+            for (int i = 0; i < MS; ++i)
+                if (i < m) v -= cf[i] * V[(int64_t)i * b.dim + d];
+            T[d] = v;
+            acc[0] += v * v;
+        }
     }
     store_block_partials<1>(b, t, acc, 1);
 }
@@ -1054,15 +1123,22 @@ hipError_t launch_orthonormalize(const Batch &b, hipStream_t s) {
     const dim3 grid(b.nblk, b.B);
     VecRef tr{b.T, b.dim, nullptr, 0};
     // first pass: projections from k_ritz, coefficients from k_coef1
-    const bool small = b.max_space <= 12;
-    if (small) hipLaunchKernelGGL(k_axpy<12>, grid, dim3(256), 0, s, b, 0);
-    else hipLaunchKernelGGL(k_axpy<kMaxSpace>, grid, dim3(256), 0, s, b, 0);
+    const bool small = b.max_space <= 12, v2 = (b.dim & 1) == 0;
+    auto axpy = [&](int only2) {
+        if (small) {
+            if (v2) hipLaunchKernelGGL((k_axpy<12, true>), grid, dim3(256), 0, s, b, only2);
+            else hipLaunchKernelGGL((k_axpy<12, false>), grid, dim3(256), 0, s, b, only2);
+        } else {
+            if (v2) hipLaunchKernelGGL((k_axpy<kMaxSpace, true>), grid, dim3(256), 0, s, b, only2);
+            else hipLaunchKernelGGL((k_axpy<kMaxSpace, false>), grid, dim3(256), 0, s, b, only2);
+        }
+    };
+    axpy(0);
     hipLaunchKernelGGL(k_cgs_check, dim3((b.B + 63) / 64), dim3(64), 0, s, b);
     if (small) hipLaunchKernelGGL(k_dots<12>, grid, dim3(256), 0, s, b, tr, 0, 1);
     else hipLaunchKernelGGL(k_dots<kMaxSpace>, grid, dim3(256), 0, s, b, tr, 0, 1);
     hipLaunchKernelGGL(k_coef, dim3(b.B), dim3(64), 0, s, b);
-    if (small) hipLaunchKernelGGL(k_axpy<12>, grid, dim3(256), 0, s, b, 1);
-    else hipLaunchKernelGGL(k_axpy<kMaxSpace>, grid, dim3(256), 0, s, b, 1);
+    axpy(1);
     hipLaunchKernelGGL(k_tnorm, dim3(b.B), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_store_t, grid, dim3(256), 0, s, b);
     return hipGetLastError();
