@@ -357,15 +357,18 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
             // strip row at byte offset e & 0x7FFFFFFF (a multiple of 128), column ar; sign in bit 31.
             // The add is done by the LDS unit (no address of the step is hit
             // twice, so this is the plain sum in the same order)
-            double *d = lds_at((e & 0x7FFFFFFFu) | ar8);
-            __builtin_amdgcn_ds_atomic_fadd_f64((__attribute__((address_space(3))) double *)d,
+            // (the strip starts the dynamic LDS block, which starts at LDS
+            // address 0: the kernel has no static LDS, checked at set-up)
+            const uint32_t addr = (e & 0x7FFFFFFFu) | ar8;
+            __builtin_amdgcn_ds_atomic_fadd_f64((__attribute__((address_space(3))) double *)(uintptr_t)addr,
                                                 __hiloint2double(__double2hiint(wv) ^ (int)(e & kPairSign), __double2loint(wv)));
         }
         // D of string K+1 (C row K+1 was loaded one step ago)
 #pragma unroll
         for (int i = 0; i < NI; ++i) *lds_at(dsl[i] + ((K + 1) & 1) * DB) = dval(i);
         // loads: C row K+2, scatter entries of string K-1 (scattered next step)
-        const uint32_t K2c = K + 2 < Na ? K + 2 : Na - 1, K1s = (K >= 1 && K - 1 < Na) ? K - 1 : Na;
+        // (K - 1 wraps to 2^32 - 1 at K = 0: the discard row)
+        const uint32_t K2c = K + 2 < Na ? K + 2 : Na - 1, K1s = K - 1 < Na ? K - 1 : Na;
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             cb[i] = load_c(K2c, i);
@@ -450,6 +453,11 @@ hipError_t init_strip_kernels() {
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
+        // the scatter addresses the strip by raw LDS address: no static LDS
+        hipFuncAttributes fa;
+        e = hipFuncGetAttributes(&fa, f);
+        if (e != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     }
     return hipSuccess;
 }
