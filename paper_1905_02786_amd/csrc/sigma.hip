@@ -180,11 +180,17 @@ constexpr int kGK = 16;
 // past the end) or feed rows and columns that are not stored.
 // With `dots` (Davidson, sigma of V_m into S_m) the block also writes the
 // partial dots V_i . S_m, i <= m, of its finished tile to partial block
-// (blockIdx.y * gridDim.x + blockIdx.x) of the tuple.
+// (its tile index) of the tuple.
+// Grid: one block per (tuple, output tile), mapped so that every tile of
+// tuple t runs on XCD t % 8 and the tiles of one tuple are dispatched back to
+// back: the K-chunks they all read stay in that XCD's L2.
 template <int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sref, int skip_done, int dots) {
     constexpr int BM = 32 * WM, BN = 32 * WN;
-    const int t = blockIdx.z;
+    const int tx = (int)((b.Nb + BN - 1) / BN), ntiles = tx * (int)((b.Na + BM - 1) / BM);
+    const int64_t L = blockIdx.x, j = L / kXcds;
+    const int t = (int)((j / ntiles) * kXcds + L % kXcds), tile = (int)(j % ntiles);
+    if (t >= b.B) return;
     if (skip_done && b.status[t] != ST_RUNNING) return;
     const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
     const double *C = vref(cref, t, b.dim);
@@ -201,7 +207,7 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
     __shared__ double Bs[2][kGK][BN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wy = wave >> 1, wx = wave & 1;
-    const uint32_t r0 = blockIdx.y * BM, c0 = blockIdx.x * BN;
+    const uint32_t r0 = (uint32_t)(tile / tx) * BM, c0 = (uint32_t)(tile % tx) * BN;
     // staging: A element j at row (tid >> 4) + 16 j, k = tid & 15; B element j at
     // k row (tid >> 5) + 8 (j / WN), column (tid & 31) + 32 (j % WN)
     const uint32_t ar = tid >> 4, ak = tid & 15, bk = tid >> 5, bc = tid & 31;
@@ -305,7 +311,7 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
         if (lane == 0) red[wave][k] = a;
     }
     __syncthreads();
-    if (tid <= m) parts(b, t, blockIdx.y * gridDim.x + blockIdx.x)[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    if (tid <= m) parts(b, t, tile)[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // Tile choice: the smaller padded area of 96 x 96 and 64 x 64 tiles, 96 on a
@@ -322,7 +328,8 @@ int gemm_blocks(const Batch &b) {
 
 template <int WM, int WN>
 static void launch_gemm_hx(const Batch &b, VecRef c, VecRef sig, int skip, int dots, hipStream_t s) {
-    const dim3 grid((unsigned)((b.Nb + 32 * WN - 1) / (32 * WN)), (unsigned)((b.Na + 32 * WM - 1) / (32 * WM)), b.B);
+    const int64_t ntiles = ((b.Nb + 32 * WN - 1) / (32 * WN)) * ((b.Na + 32 * WM - 1) / (32 * WM));
+    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * ntiles));
     hipLaunchKernelGGL((k_gemm_hx<WM, WN>), grid, dim3(256), 0, s, b, c, sig, skip, dots);
 }
 
