@@ -384,7 +384,9 @@ __global__ __launch_bounds__(256) void k_psp_factor(Batch b) {
         // p = B v (B symmetric, lower triangle stored)
         for (int i = tid; i < m; i += 256) {
             double acc = 0.0;
+#pragma unroll 8
             for (int j = 0; j <= i; ++j) acc += B[i * LD + j] * v[j * LD];
+#pragma unroll 8
             for (int j = i + 1; j < m; ++j) acc += B[j * LD + i] * v[j * LD];
             vec[i] = acc;
         }
@@ -421,8 +423,10 @@ __global__ __launch_bounds__(256) void k_psp_factor(Batch b) {
         __syncthreads();
         for (int c = k + 1 + tid; c < n; c += 256) {
             double acc = 0.0;
+#pragma unroll 8
             for (int r = 0; r < m; ++r) acc += vec[r] * A[(k + 1 + r) * LD + c];
             acc *= 2.0;
+#pragma unroll 8
             for (int r = 0; r < m; ++r) A[(k + 1 + r) * LD + c] -= acc * vec[r];
         }
         __syncthreads();
@@ -489,6 +493,7 @@ __global__ __launch_bounds__(256) void k_psp_factor(Batch b) {
     // y = Q z, Q to global
     for (int i = tid; i < n; i += 256) {
         double acc = 0.0;
+#pragma unroll 8
         for (int j = 0; j < n; ++j) acc += A[i * LD + j] * vec[j];
         yv[i] = acc;
     }
@@ -568,6 +573,7 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     __syncthreads();
     if (i < n) {
         double s = 0.0;
+#pragma unroll 8
         for (int k = 0; k < n; ++k) s += Q[k * kPsp + i] * r[k];
         w[i] = s;
     }
@@ -590,6 +596,7 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     for (int k = 0; k < MS + 2; ++k) acc[k] = 0.0;
     if (i < n) {
         double tv = 0.0;
+#pragma unroll 8
         for (int k = 0; k < n; ++k) tv += Q[i * kPsp + k] * w[k];
         T[d] = tv;
         const double dt = tv - told;
