@@ -794,7 +794,6 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     __shared__ double Vv[kMaxSpace + 1][kMaxSpace + 2];
     __shared__ double cs[(kMaxSpace + 2) / 2], sn[(kMaxSpace + 2) / 2];
     __shared__ int pa[(kMaxSpace + 2) / 2], pb[(kMaxSpace + 2) / 2];
-    __shared__ int order[kMaxSpace + 2];
     __shared__ int done;
     const int tid = threadIdx.x;
     const double *G = b.G + (int64_t)t * kMaxSpace * kMaxSpace;
@@ -803,8 +802,10 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
         A[r][c] = (r < m && c < m) ? G[r * kMaxSpace + c] : 0.0;
         Vv[r][c] = (r == c) ? 1.0 : 0.0;
     }
-    for (int i = tid; i < mm; i += 64) order[i] = i;
     __syncthreads();
+    // round-robin schedule: position 0 keeps player 0, positions 1 .. mm-1
+    // rotate by one per round (period mm - 1)
+    auto player = [&](int pos, int round) { return pos == 0 ? 0 : 1 + (pos - 1 + (mm - 1) - round) % (mm - 1); };
     const int half = mm / 2;
     // rotation loops: for mm <= 16 item idx is pair idx >> 4, row or column
     // idx & 15 (no integer division); larger subspaces use idx / mm, idx % mm
@@ -827,7 +828,7 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
         if (done) break;
         for (int round = 0; round < mm - 1; ++round) {
             if (tid < half) {
-                int p = order[tid], q = order[mm - 1 - tid];
+                int p = player(tid, round), q = player(mm - 1 - tid, round);
                 if (p > q) { const int x = p; p = q; q = x; }
                 double c = 1.0, s = 0.0;
                 if (q < m && A[p][q] != 0.0) {
@@ -866,13 +867,6 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
                 const double apc = A[p][col], aqc = A[q][col];
                 A[p][col] = c * apc - s * aqc;
                 A[q][col] = s * apc + c * aqc;
-            }
-            __syncthreads();
-            // round-robin: keep order[0], rotate the others
-            if (tid == 0) {
-                const int last = order[mm - 1];
-                for (int i = mm - 1; i > 1; --i) order[i] = order[i - 1];
-                order[1] = last;
             }
             __syncthreads();
         }

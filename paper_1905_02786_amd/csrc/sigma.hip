@@ -127,41 +127,62 @@ __global__ __launch_bounds__(256) void k_sigma_g(Batch b, VecRef cref, VecRef sr
 // strip kernel (strip.hip); the string Hamiltonians H_s and their GEMMs
 // follow here.
 
-// Dense string Hamiltonian of one spin (symmetric, N x N per tuple); thread J
-// writes row J:
+// Dense string Hamiltonian of one spin (symmetric, N x N per tuple); lane r
+// of a block accumulates row J = J0 + r in LDS:
 //   H e_J = sum_{links (Q,K,s) of J} s [ k_Q e_K + 1/2 sum_{links (P,I,s') of K} s' (P|Q) e_I ].
-__global__ __launch_bounds__(64) void k_build_h(Batch b, int beta) {
-    const int t = blockIdx.y;
+// Only that lane adds into its row, by LDS atomic adds issued in program
+// order, so every entry is summed in the link order; the block then writes
+// its rows out coalesced.  rows = rows per block (dynamic LDS rows * N doubles).
+__global__ __launch_bounds__(64) void k_build_h(Batch b, int beta, int rows) {
+    const int t = blockIdx.y, lane = threadIdx.x;
     const int64_t N = beta ? b.Nb : b.Na;
     const int nent = beta ? b.nentB : b.nentA;
     const uint32_t *links = beta ? b.linkB : b.linkA;
-    const int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (J >= N) return;
-    const ParamLayout &pl = b.pl;
-    const double *prm = b.params + (int64_t)t * pl.stride;
-    double *row = (beta ? b.Hb : b.Ha) + ((int64_t)t * N + J) * N;
-    for (int64_t i = 0; i < N; ++i) row[i] = 0.0;
-    const uint32_t *lj = links + J * nent;
-    for (int e = 0; e < nent; ++e) {
-        int K, Q;
-        double s;
-        link_decode(lj[e], K, Q, s);
-        row[K] += s * prm[pl.off_k + Q];
-        const uint32_t *lk = links + (int64_t)K * nent;
-        for (int f = 0; f < nent; ++f) {
-            int I, P;
-            double s2;
-            link_decode(lk[f], I, P, s2);
-            row[I] += s * s2 * prm[pl.off_eri + P * pl.Kpad + Q];   // stored as 1/2 (P|Q)
+    const int64_t J0 = (int64_t)blockIdx.x * rows;
+    const int nr = (int)(N - J0 < rows ? N - J0 : rows);
+    extern __shared__ double hrow[];   // [rows][N]
+    for (int64_t i = lane; i < (int64_t)nr * N; i += 64) hrow[i] = 0.0;
+    __syncthreads();
+    if (lane < nr) {
+        const ParamLayout &pl = b.pl;
+        const double *prm = b.params + (int64_t)t * pl.stride;
+        auto add = [&](int64_t col, double v) {
+            __builtin_amdgcn_ds_atomic_fadd_f64((__attribute__((address_space(3))) double *)(hrow + lane * N + col), v);
+        };
+        const uint32_t *lj = links + (J0 + lane) * nent;
+        for (int e = 0; e < nent; ++e) {
+            int K, Q;
+            double sg;
+            link_decode(lj[e], K, Q, sg);
+            add(K, sg * prm[pl.off_k + Q]);
+            const uint32_t *lk = links + (int64_t)K * nent;
+            for (int f = 0; f < nent; ++f) {
+                int I, P;
+                double s2;
+                link_decode(lk[f], I, P, s2);
+                add(I, sg * s2 * prm[pl.off_eri + P * pl.Kpad + Q]);   // stored as 1/2 (P|Q)
+            }
         }
     }
+    __syncthreads();
+    double *H = (beta ? b.Hb : b.Ha) + ((int64_t)t * N + J0) * N;
+    for (int64_t i = lane; i < (int64_t)nr * N; i += 64) H[i] = hrow[i];
+}
+
+// rows per block: up to 64, at most 80 KB of LDS (two blocks per CU)
+static int build_h_rows(int64_t N) {
+    const int64_t r = (80 * 1024) / (8 * (N > 0 ? N : 1));
+    return (int)(r < 1 ? 1 : (r > 64 ? 64 : r));
 }
 
 hipError_t launch_build_hb(const Batch &b, hipStream_t s) {
     if (b.sigma_variant != SIGMA_STRIP) return hipSuccess;
-    hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Nb + 63) / 64), b.B), dim3(64), 0, s, b, 1);
+    const int rb = build_h_rows(b.Nb), ra = build_h_rows(b.Na);
+    hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Nb + rb - 1) / rb), b.B), dim3(64), (size_t)rb * b.Nb * sizeof(double),
+                       s, b, 1, rb);
     if (b.Ha != b.Hb)
-        hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Na + 63) / 64), b.B), dim3(64), 0, s, b, 0);
+        hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Na + ra - 1) / ra), b.B), dim3(64),
+                           (size_t)ra * b.Na * sizeof(double), s, b, 0, ra);
     return hipGetLastError();
 }
 
@@ -374,6 +395,8 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
 
 hipError_t init_sigma_kernels() {
     hipError_t e = hipFuncSetAttribute((const void *)k_sigma_w, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_build_h, hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
     if (e != hipSuccess) return e;
     return init_strip_kernels();
 }
