@@ -203,8 +203,8 @@ def main():
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
                      "traffic": TRAFFIC["bytes_per_launch"] if kernels_sha1() == TRAFFIC["kernels_sha1"] else None,
                      "algorithmic_bytes_per_launch": st["sigma_bytes"] / max(1, st["sigma_launches"]),
-                     "kernel": "k_sigma_strip (column-strip sigma: D gather, FP64 MFMA with 1/2 (pq|rs), "
-                               "W scattered through alpha links in LDS)",
+                     "kernel": "k_sigma_strip (alpha-beta term of sigma by 16-column strips: D gathered from C, "
+                               "FP64 MFMA with (pq|rs), W scattered through the alpha links into the LDS strip)",
                      "per_launch_flops": st["sigma_flops"] / max(1, st["sigma_launches"]),
                      "avg_launch_ms": st["sigma_ms"] / max(1, st["sigma_launches"])},
     }
