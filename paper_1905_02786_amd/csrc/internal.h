@@ -94,6 +94,7 @@ struct Batch {
     int psp;
     int32_t *pidx;          // [B][kPsp] determinant indices
     double *pQ;             // [B][kPsp][kPsp] H_PP, then Q
+    double *pQt;            // [B][kPsp][kPsp] Q transposed (coalesced reads of Q w)
     double *pT;             // [B][3][kPsp] diagonal, subdiagonal of T, lowest eigenvector of H_PP
     int32_t *counter;       // [1] running tuples
     // RDM pass (backward): Gram partials and sums

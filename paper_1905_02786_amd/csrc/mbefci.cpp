@@ -261,7 +261,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr +                             // H_b, H_a
                (key.na != key.nb ? 8 * (size_t)cp.ta->nstr * cp.ta->nstr : 0);
     pt += 8 * (size_t)(cp.nblk + 1) * kParts;                // partials (+ P-space block)
-    if (cp.psp > 0) pt += 4 * (size_t)kPsp + 8 * (size_t)kPsp * kPsp + 24 * (size_t)kPsp + 3 * 256;
+    if (cp.psp > 0) pt += 4 * (size_t)kPsp + 16 * (size_t)kPsp * kPsp + 24 * (size_t)kPsp + 4 * 256;
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
@@ -340,10 +340,11 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     if (cp.psp > 0) {
         b.pidx = cv.take<int32_t>((size_t)B * kPsp);
         b.pQ = cv.take<double>((size_t)B * kPsp * kPsp);
+        b.pQt = cv.take<double>((size_t)B * kPsp * kPsp);
         b.pT = cv.take<double>((size_t)B * 3 * kPsp);
     } else {
         b.pidx = nullptr;
-        b.pQ = b.pT = nullptr;
+        b.pQ = b.pQt = b.pT = nullptr;
     }
     b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.y = cv.take<double>((size_t)B * kMaxSpace);
