@@ -206,8 +206,10 @@ mbefci_status tuple_shape(mbefci_ctx *ctx, int order, const int16_t *tup, TupleS
     return MBEFCI_OK;
 }
 
+// Blocks per tuple of the Davidson vector kernels: about 4096 determinants
+// (16 per thread) per block; the per-tuple kernels then sum few partials.
 int nblk_for(int64_t dim) {
-    int64_t g = (dim + 1023) / 1024;
+    int64_t g = (dim + 4095) / 4096;
     return (int)std::max<int64_t>(1, std::min<int64_t>(256, g));
 }
 
