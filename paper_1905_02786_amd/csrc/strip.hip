@@ -163,6 +163,9 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
     if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
     if (skip_done && b.status[t] != ST_RUNNING) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the wave index as a scalar: branches on it are taken per wave, so a
+    // wave does not issue the other side's instructions under an empty mask
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     const int ar = lane & 15, kr = lane >> 4;
     // determinant indices fit 32 bits (dim <= C(13,6)^2)
     const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
         // diagonal pairs: rows 0..NA-1 of wave 0.  Add the sum of string K-2,
         // then form the sum of string K-1 (lane mask of its occupied orbitals,
         // fixed order: v within the lane, then lanes (kr, kr^1), then (kr, kr^2)).
-        if (w == 0) {
+        if (wu == 0) {
             if (kr == DGK && K >= 2 && K - 2 < Na)
                 __builtin_amdgcn_ds_atomic_fadd_f64((__attribute__((address_space(3))) double *)(strip + (K - 2) * kStrip + ar), dg1);
             double s = ((sa1 >> kr) & 1u) ? ao[0][0] : 0.0;
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
             for (int v = 1; v < 4; ++v)
                 if (4 * v < NA) s += ((sa1 >> (kr + 4 * v)) & 1u) ? ao[0][v] : 0.0;
             if (XV) {
-                const double g = group_sums4(xp[0], XVR > 1 ? xp[1] : 0.0, s, 0.0);
+                const double g = group_sums4(xp[0], XVR > 1 ? xp[1] : 0.0, s, s);   // group 3 unused
                 an[1][0] = g;
                 dg1 = g;
             } else {
