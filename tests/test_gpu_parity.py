@@ -241,6 +241,25 @@ def test_pspace_settings_match_oracle(ws, pspace):
     print(f"pspace {pspace}: max |dE| = {worst:.1e}")
 
 
+@pytest.mark.parametrize("max_space", [4, 20, 32])
+def test_max_space_settings_match_oracle(ws, max_space):
+    """Subspace bounds other than the default: frequent restarts (4) and the
+    32-vector kernel instantiations, on odd and even dimensions."""
+    probs = {"hubbard8": synth.config_hubbard(8.0), "sweep": synth.config_sweep(0)}
+    cases = [("hubbard8", (1, 2, 3, 6, 9)), ("hubbard8", (0, 1, 2, 6)), ("hubbard8", (0, 2, 6, 8)),
+             ("sweep", (1,)), ("sweep", (9, 18))]
+    worst = 0.0
+    for name, S in cases:
+        P = probs[name]
+        ctx = _ctx(P, max_space=max_space, max_iter=400)
+        e, st = ctx.solve_tuples(len(S), [S], ws)
+        e_ref = fci.casci_energy(P, S)
+        assert st[0] == 0, (name, S, max_space, st[0])
+        assert abs(e[0] - e_ref) <= 1e-10, (name, S, max_space, e[0], e_ref)
+        worst = max(worst, abs(e[0] - e_ref))
+    print(f"max_space {max_space}: max |dE| = {worst:.1e}")
+
+
 def test_sweep_sampled_tuples(ws):
     _solve_samples(synth.config_sweep(0), "sweep_sample.json", ws)
 
