@@ -335,11 +335,14 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
     if (tid <= m) parts(b, t, tile)[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
-// Tile choice: the smaller padded area of 96 x 96 and 64 x 64 tiles, 96 on a
-// tie (measured faster for 462, 330 and 165 strings, 64 for 252 and 210).
+// Tile choice: the smaller padded area of 96 x 96 and 64 x 64 tiles; on a tie
+// 96 for matrices of at least 256 x 256 strings, else 64 (measured with the
+// Davidson dots: 96 faster for 462 and 330 strings, 64 for 252, 210 and 165).
 static int gemm_tile(const Batch &b) {
     auto padded = [&](int64_t t) { return ((b.Na + t - 1) / t * t) * ((b.Nb + t - 1) / t * t); };
-    return padded(96) <= padded(64) ? 96 : 64;
+    const int64_t p96 = padded(96), p64 = padded(64);
+    if (p96 != p64) return p96 < p64 ? 96 : 64;
+    return b.Na * b.Nb >= 256 * 256 ? 96 : 64;
 }
 
 int gemm_blocks(const Batch &b) {
