@@ -1002,12 +1002,36 @@ __global__ void k_converge(Batch b) {
     if (st == ST_RUNNING) atomicAdd(b.counter, 1);
 }
 
-// projection coefficients of the first Gram-Schmidt pass (partials 2..m+1 of k_ritz)
+// Projection coefficients c_i of the first Gram-Schmidt pass (partials
+// 2..m+1 of k_ritz), and the norm that pass keeps, |T|^2 - sum c_i^2.  One
+// pass suffices when it keeps at least 1/sqrt(2) of the norm (Kahan's
+// criterion; the difference of squares is then accurate to a few ulps): the
+// pass writes V_m = (T - sum c_i V_i) / norm directly (scale in
+// coef[kMaxSpace - 1], never a coefficient since m < max_space <= kMaxSpace).
+// Otherwise cgs2 is set and the second pass and k_tnorm decide.  One block of
+// 64 threads per tuple.
 __global__ void k_coef1(Batch b) {
     const int t = blockIdx.x;
     if (b.status[t] != ST_RUNNING) return;
     const int m = b.m[t];
-    if ((int)threadIdx.x < m) b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = sum_parts_x(b, t, 2 + threadIdx.x);
+    double c = 0.0;
+    if ((int)threadIdx.x < m) {
+        c = sum_parts_x(b, t, 2 + threadIdx.x);
+        b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = c;
+    }
+    const double c2 = wave_sum(c * c);
+    if (threadIdx.x == 0) {
+        const double t2 = b.tnorm0[t] * b.tnorm0[t];
+        const double kept = t2 - c2;
+        const int two = !(kept >= 0.5 * t2);
+        b.cgs2[t] = two;
+        if (!two) {
+            if (!(kept > 1e-300) || m >= b.max_space)
+                b.status[t] = b.rnorm[t] < b.r_tol ? ST_DONE : (m > 1 ? ST_RESTART : ST_STALLED);
+            else
+                b.coef[(int64_t)t * kMaxSpace + kMaxSpace - 1] = 1.0 / sqrt(kept);
+        }
+    }
 }
 
 hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
@@ -1049,6 +1073,10 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
     for (int i = 0; i < MS; ++i) cf[i] = (i < m) ? cp[i] : 0.0;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     double *T = b.T + (int64_t)t * b.dim;
+    // first pass of a one-pass tuple: the result goes scaled into V_m
+    const bool direct = !only2 && !b.cgs2[t];
+    const double sc = direct ? b.coef[(int64_t)t * kMaxSpace + kMaxSpace - 1] : 1.0;
+    double *out = direct ? b.V + ((int64_t)t * b.max_space + m) * b.dim : T;
     double acc[1];
     acc[0] = 0.0;
     if (V2) {
@@ -1068,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
                     v.x -= cf[i] * vv[i].x;
                     v.y -= cf[i] * vv[i].y;
                 }
-            *reinterpret_cast<dbl2 *>(T + d) = v;
+            *reinterpret_cast<dbl2 *>(out + d) = dbl2{v.x * sc, v.y * sc};
             acc[0] += v.x * v.x;
             acc[0] += v.y * v.y;
         }
@@ -1078,20 +1106,11 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
 #pragma unroll
             for (int i = 0; i < MS; ++i)
                 if (i < m) v -= cf[i] * V[(int64_t)i * b.dim + d];
-            T[d] = v;
+            out[d] = v * sc;
             acc[0] += v * v;
         }
     }
-    store_block_partials<1>(b, t, acc, 1);
-}
-
-// One classical Gram-Schmidt pass suffices when it kept at least 1/sqrt(2)
-// of the correction's norm (Kahan's criterion); otherwise project again.
-__global__ void k_cgs_check(Batch b) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= b.B || b.status[t] != ST_RUNNING) return;
-    const double n1 = sqrt(sum_parts(b, t, 0));
-    b.cgs2[t] = (n1 >= 0.70710678118654752 * b.tnorm0[t]) ? 0 : 1;
+    if (only2) store_block_partials<1>(b, t, acc, 1);   // |T|^2 after the second pass, for k_tnorm
 }
 
 // 1/|T| into coef[0].  A correction that lies inside the subspace (its
@@ -1102,7 +1121,7 @@ __global__ void k_cgs_check(Batch b) {
 // subspace already is that one vector.
 __global__ void k_tnorm(Batch b) {
     const int t = blockIdx.x;
-    if (threadIdx.x != 0 || b.status[t] != ST_RUNNING) return;
+    if (threadIdx.x != 0 || b.status[t] != ST_RUNNING || !b.cgs2[t]) return;
     const double tn = sqrt(sum_parts(b, t, 0));
     if (!(tn > 1e-8 * b.tnorm0[t]) || !(tn > 1e-300) || b.m[t] >= b.max_space) {
         b.status[t] = b.rnorm[t] < b.r_tol ? ST_DONE : (b.m[t] > 1 ? ST_RESTART : ST_STALLED);
@@ -1111,10 +1130,10 @@ __global__ void k_tnorm(Batch b) {
     b.coef[(int64_t)t * kMaxSpace] = 1.0 / tn;
 }
 
-// V_m = T / |T|
+// V_m = T / |T| (tuples that took the second pass)
 __global__ __launch_bounds__(256) void k_store_t(Batch b) {
     const int t = blockIdx.y;
-    if (b.status[t] != ST_RUNNING) return;
+    if (b.status[t] != ST_RUNNING || !b.cgs2[t]) return;
     const double s = b.coef[(int64_t)t * kMaxSpace];
     double *vm = b.V + ((int64_t)t * b.max_space + b.m[t]) * b.dim;
     const double *T = b.T + (int64_t)t * b.dim;
@@ -1147,7 +1166,6 @@ hipError_t launch_orthonormalize(const Batch &b, hipStream_t s) {
         }
     };
     axpy(0);
-    hipLaunchKernelGGL(k_cgs_check, dim3((b.B + 63) / 64), dim3(64), 0, s, b);
     if (small) hipLaunchKernelGGL(k_dots<12>, grid, dim3(256), 0, s, b, tr, 0, 1);
     else hipLaunchKernelGGL(k_dots<kMaxSpace>, grid, dim3(256), 0, s, b, tr, 0, 1);
     hipLaunchKernelGGL(k_coef, dim3(b.B), dim3(64), 0, s, b);
