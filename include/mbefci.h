@@ -99,14 +99,20 @@ typedef struct {
                                elsewhere; 0..128, 0 = diagonal only (default 128).  Only for
                                column-strip classes; the result does not depend on it beyond
                                the convergence tolerances. */
-    int32_t reserved[5];
+    int32_t linked_rows;    /* column-strip alpha-beta term: 1 (default) forms W only on the pair
+                               rows that link each alpha string to another (1 + n_a (n_A - n_a)
+                               rows, at most 32; the diagonal pairs summed first) where n_A >= 10
+                               and they fit; 0 always forms all P_A pair rows.  Same result up to
+                               rounding. */
+    int32_t reserved[4];
 } mbefci_options;
 
 typedef struct {
     int64_t ntuples;            /* tuples solved by the last solve/run call */
     int64_t sigma_calls;        /* sigma applications (one per tuple per iteration) */
     int64_t sigma_launches;     /* launches of the dominant sigma kernel */
-    double sigma_flops;         /* algorithmic FLOPs, 2 * P_A^2 * dim per application */
+    double sigma_flops;         /* algorithmic FLOPs, 2 * R * P_A * dim per application: R = P_A pair
+                                   rows, or 1 + n_a (n_A - n_a) with linked rows */
     double sigma_bytes;         /* algorithmic bytes, 16 * dim + 8 * P_A^2 per application */
     double sigma_ms;            /* HIP-event time of the dominant sigma kernel (profile = 1) */
     double sigma_total_ms;      /* HIP-event time of all sigma kernels (profile = 1) */

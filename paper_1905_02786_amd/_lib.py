@@ -19,7 +19,8 @@ class Options(ctypes.Structure):
     _fields_ = [("a", c_double), ("max_order", c_int32), ("e_tol", c_double), ("r_tol", c_double),
                 ("max_iter", c_int32), ("max_space", c_int32), ("batched", c_int32),
                 ("keep_vectors", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
-                ("pspace", c_int32), ("reserved", c_int32 * 5)]
+                ("pspace", c_int32), ("linked_rows", c_int32),
+                ("reserved", c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):

@@ -71,6 +71,12 @@ struct Batch {
     const double *h, *eri;  // resident integrals (n^2, n^4)
     const uint32_t *strA, *strB, *linkA, *linkB;
     const uint32_t *scatA, *pairB;   // column-strip sigma: alpha scatter table, beta pair links
+    // linked-row strip sigma (null la: the all-pairs strip kernel): per alpha
+    // string the A-row offsets and sigma-strip targets of its 32 row slots
+    // [Na + 1][32], and the per-tuple A table [B][la_stride]
+    const uint32_t *lrow, *lscat;
+    double *la;
+    int64_t la_stride;
     const int32_t *act;     // [B * nA] active orbitals (ascending)
     const int32_t *core;    // [B * nC] core orbitals
     double *params;         // [B * pl.stride]
@@ -109,6 +115,21 @@ hipError_t init_sigma_kernels();   // LDS limits of the sigma kernels (called by
 hipError_t init_strip_kernels();   // the same for the strip kernels (called by init_sigma_kernels)
 // alpha-beta term of sigma (column strip, strip.hip): sig = X + shift c
 hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s);
+// linked-row strip kernel: row slots per alpha string, fit check, per-tuple
+// A-table size (doubles) and its build (once per batch, after the gather)
+constexpr int kLinkedRows = 32;
+constexpr int kLinkedMinActive = 10;   // smallest n_A that uses the linked-row kernel
+// Per-tuple A table of the linked-row kernel: with kLinkedSigned the rows are
+// A, -A (the alpha link sign picked by the row), then the diagonal sums;
+// without it A, then the diagonal sums, and the sign rides on the scatter
+// entry (bit 31).  Row length (doubles) for a padded pair count Kpad: the
+// columns of two consecutive MFMA K steps are interleaved (linked_pos), 8
+// doubles per K-step pair.
+constexpr bool kLinkedSigned = false;
+__host__ __device__ inline int linked_row_len(int Kpad) { return (Kpad / 4 + 1) / 2 * 8; }
+bool linked_fits(const ParamLayout &pl, int64_t Na, int nel);
+int64_t linked_a_stride(const ParamLayout &pl, int64_t Na);
+hipError_t launch_linked_a(const Batch &b, hipStream_t s);
 hipError_t launch_gather(const Batch &b, hipStream_t s);
 hipError_t launch_hdiag(const Batch &b, double *out, int64_t ostride, int add_ecore, hipStream_t s);
 // sigma = (H + shift) c; with `dots` and the column-strip variant the GEMM
@@ -128,6 +149,8 @@ hipError_t launch_finalize(const Batch &b, hipStream_t s);
 size_t sigma_lds_bytes(const ParamLayout &pl);
 size_t strip_lds_bytes(const ParamLayout &pl, int64_t Na);
 bool strip_fits(const ParamLayout &pl, int64_t Na, int nentA, int nentB);
+// per-batch set-up of the column-strip sigma: string Hamiltonians and, for
+// the linked-row kernel, the per-tuple A tables (after the gather)
 hipError_t launch_build_hb(const Batch &b, hipStream_t s);
 hipError_t launch_form_x(const Batch &b, hipStream_t s);
 hipError_t launch_pspace(const Batch &b, hipStream_t s);

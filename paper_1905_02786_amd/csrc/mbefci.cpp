@@ -27,6 +27,7 @@ struct Tables {
     std::vector<uint32_t> links;     // [nstr][nent]
     std::vector<uint32_t> pairs;     // [nstr][P]: link of each string per pair, strip pair order
     std::vector<uint32_t> scat;      // [nstr + 1][P + 1]: scatter form for the strip kernel
+    std::vector<uint32_t> lrow, lscat;   // [nstr + 1][32]: linked-row form (empty if the links need more slots)
 };
 
 // Strings with `nel` of `nA` bits set, ascending; for each string I the
@@ -87,6 +88,41 @@ void build_tables(int nA, int nel, Tables &T) {
             const uint32_t J = L & 0xFFFFFu, sign = L & 0x80000000u;
             T.pairs[(size_t)I * np + col] = J | sign | (1u << 30);
             if (p != q) T.scat[(size_t)I * (np + 1) + col] = J * 128u | sign;
+        }
+    }
+    // Linked-row form for the linked-row strip kernel, 32 slots per string
+    // (row nstr all discard), as byte offsets: lrow = the slot's row of the
+    // per-tuple A table (rows of Kpad doubles: pair col, np + col for the
+    // negated row, 2 np + I for the diagonal sum of string I), lscat = its
+    // target row of the sigma strip (128 bytes a row).  Slot 0 is the
+    // diagonal sum (target I), then the off-diagonal links in link order
+    // (target J, the negated row for a negative sign); unused slots read row
+    // 0 and go to the discard row nstr.
+    T.lrow.clear();
+    T.lscat.clear();
+    if (1 + nel * (nA - nel) <= kLinkedRows) {
+        const uint32_t kp8 = (uint32_t)linked_row_len((np + 3) / 4 * 4) * 8u;
+        const uint32_t dg = kLinkedSigned ? 2 * np : np;   // first diagonal-sum row
+        T.lrow.assign((size_t)(T.nstr + 1) * kLinkedRows, 0u);
+        T.lscat.assign((size_t)(T.nstr + 1) * kLinkedRows, discard);
+        for (int64_t I = 0; I < T.nstr; ++I) {
+            uint32_t *lr = &T.lrow[(size_t)I * kLinkedRows], *ls = &T.lscat[(size_t)I * kLinkedRows];
+            lr[0] = (uint32_t)(dg + I) * kp8;
+            ls[0] = (uint32_t)I * 128u;
+            int slot = 1;
+            for (int e = 0; e < T.nent; ++e) {
+                const uint32_t L = T.links[(size_t)I * T.nent + e];
+                const int P = (int)((L >> 20) & 0x3FFu);
+                int p = 0;
+                while ((p + 1) * (p + 2) / 2 <= P) ++p;
+                const int q = P - p * (p + 1) / 2;
+                if (p == q) continue;
+                const int col = nA + P - p;
+                const uint32_t neg = L & 0x80000000u;
+                lr[slot] = (uint32_t)(col + ((kLinkedSigned && neg) ? np : 0)) * kp8;
+                ls[slot] = (L & 0xFFFFFu) * 128u | (kLinkedSigned ? 0u : neg);
+                ++slot;
+            }
         }
     }
 }
@@ -222,6 +258,7 @@ struct ClassPlan {
     int nblk;
     int variant;
     int psp;   // P-space size of the Davidson preconditioner (0: diagonal only)
+    bool linked;   // linked-row strip kernel
     bool rdm;
     int nblk_r, NP;
     size_t fixed_bytes, per_tuple;
@@ -248,11 +285,15 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
     cp.psp = (davidson && cp.variant == SIGMA_STRIP && ctx->opt.pspace > 0)
                  ? (int)std::min<int64_t>(ctx->opt.pspace, cp.dim) : 0;
+    // linked rows pay off where they replace at least four MFMA row tiles
+    cp.linked = cp.variant == SIGMA_STRIP && ctx->opt.linked_rows != 0 && key.nA >= kLinkedMinActive &&
+                !cp.ta->lrow.empty() && linked_fits(cp.pl, cp.ta->nstr, key.na);
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
                      align256(4 * (size_t)(cp.ta->nstr + 1) * (cp.pl.P + 1)) +
                      align256(4 * (size_t)cp.tb->nstr * cp.pl.P) +
+                     (cp.linked ? 2 * align256(4 * (size_t)(cp.ta->nstr + 1) * kLinkedRows) : 0) +
                      64 * 256;
     const int ms = davidson ? ctx->opt.max_space : 0;
     size_t pt = 0;
@@ -263,6 +304,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     else pt += 8 * (size_t)cp.tb->nstr * cp.tb->nstr +                             // H_b, H_a
                (key.na != key.nb ? 8 * (size_t)cp.ta->nstr * cp.ta->nstr : 0);
     pt += 8 * (size_t)(cp.nblk + 1) * kParts;                // partials (+ P-space block)
+    if (cp.linked) pt += 8 * (size_t)linked_a_stride(cp.pl, cp.ta->nstr);   // A table
     if (cp.psp > 0) pt += 4 * (size_t)kPsp + 16 * (size_t)kPsp * kPsp + 24 * (size_t)kPsp + 4 * 256;
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
@@ -313,6 +355,16 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.linkB = cv.take<uint32_t>((size_t)b.Nb * b.nentB);
     b.scatA = cv.take<uint32_t>((size_t)(b.Na + 1) * (cp.pl.P + 1));
     b.pairB = cv.take<uint32_t>((size_t)b.Nb * cp.pl.P);
+    if (cp.linked) {
+        b.lrow = cv.take<uint32_t>((size_t)(b.Na + 1) * kLinkedRows);
+        b.lscat = cv.take<uint32_t>((size_t)(b.Na + 1) * kLinkedRows);
+        b.la_stride = linked_a_stride(cp.pl, b.Na);
+        b.la = cv.take<double>((size_t)B * b.la_stride);
+    } else {
+        b.lrow = b.lscat = nullptr;
+        b.la = nullptr;
+        b.la_stride = 0;
+    }
     b.act = cv.take<int32_t>((size_t)B * b.nA + 1);
     b.core = cv.take<int32_t>((size_t)B * b.nC + 1);
     b.params = cv.take<double>((size_t)B * cp.pl.stride);
@@ -384,6 +436,12 @@ mbefci_status upload_tables(mbefci_ctx *ctx, const ClassPlan &cp, const Batch &b
                           hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync((void *)b.pairB, cp.tb->pairs.data(), 4 * (size_t)b.Nb * b.pl.P, hipMemcpyHostToDevice,
                           ctx->stream));
+    if (b.la) {
+        HIPCHK(hipMemcpyAsync((void *)b.lrow, cp.ta->lrow.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync((void *)b.lscat, cp.ta->lscat.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
+                              hipMemcpyHostToDevice, ctx->stream));
+    }
     return MBEFCI_OK;
 }
 
@@ -398,7 +456,12 @@ mbefci_status upload_shapes(mbefci_ctx *ctx, const Batch &b, const std::vector<c
     return MBEFCI_OK;
 }
 
-double sigma_flops(const Batch &b) { return 2.0 * (double)b.pl.P * b.pl.P * (double)b.dim; }
+// W = A D on the rows the kernel must form: all P pair rows, or with the
+// linked-row kernel the 1 + n_a (n_A - n_a) rows that link each alpha string
+double sigma_flops(const Batch &b) {
+    const double rows = b.la ? 1.0 + (double)b.na * (b.nA - b.na) : (double)b.pl.P;
+    return 2.0 * rows * b.pl.P * (double)b.dim;
+}
 double sigma_bytes(const Batch &b) { return 16.0 * (double)b.dim + 8.0 * (double)b.pl.P * b.pl.P; }
 
 // Accumulate the HIP-event time of the last sigma launch pair (profile mode).
@@ -795,6 +858,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->max_iter = 200;
     o->max_space = 12;
     o->pspace = kPsp;
+    o->linked_rows = 1;
     o->batched = 1;
     o->keep_vectors = 0;
     o->profile = 0;
@@ -929,6 +993,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
     if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
     if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
+    if (o->linked_rows != 0 && o->linked_rows != 1) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be 0 or 1");
     ctx->opt = *o;
     return MBEFCI_OK;
 }

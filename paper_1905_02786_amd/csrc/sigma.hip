@@ -177,6 +177,10 @@ static int build_h_rows(int64_t N) {
 
 hipError_t launch_build_hb(const Batch &b, hipStream_t s) {
     if (b.sigma_variant != SIGMA_STRIP) return hipSuccess;
+    if (b.la) {
+        const hipError_t e = launch_linked_a(b, s);
+        if (e != hipSuccess) return e;
+    }
     const int rb = build_h_rows(b.Nb), ra = build_h_rows(b.Na);
     hipLaunchKernelGGL(k_build_h, dim3((unsigned)((b.Nb + rb - 1) / rb), b.B), dim3(64), (size_t)rb * b.Nb * sizeof(double),
                        s, b, 1, rb);

@@ -416,6 +416,283 @@ __global__ __launch_bounds__(64 * StripShape<NA>::MT) void k_sigma_strip(Batch b
     }
 }
 
+// ------------------------------------------------- linked-row variant --
+// Only the rows of W whose pair links alpha string K to some string reach
+// sigma: the n (n_A - n) off-diagonal pairs with one orbital occupied in K,
+// and the n occupied diagonal pairs, which all land on K itself and can be
+// summed before the product instead of after it:
+//   sum_{p in K} W_(pp) = (sum_{p in K} A_(pp)) D.
+// That leaves 1 + n (n_A - n) rows per string, at most 32 for n_A <= 11: two
+// 16-row MFMA tiles where the all-pairs kernel needs ceil(P / 16) tiles.  The
+// A rows of a string are gathered from a per-tuple table (A, -A with the
+// alpha link sign folded into the choice of row, and the diagonal row sum of
+// every alpha string), and a workgroup of four waves runs two strings per
+// step, one per pair of waves.
+
+// Rows of the per-tuple A table and the first diagonal-sum row.
+__host__ __device__ static inline int64_t linked_a_rows(int P, int64_t Na) { return (kLinkedSigned ? 2 * (int64_t)P : P) + Na; }
+
+int64_t linked_a_stride(const ParamLayout &pl, int64_t Na) {
+    return (linked_a_rows(pl.P, Na) * linked_row_len(pl.Kpad) + 31) / 32 * 32;
+}
+
+// LDS: sigma strip [Na + 1][16] and D of the step's two strings [2][Kpad][16].
+static size_t linked_lds(const ParamLayout &pl, int64_t Na) {
+    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 2 * (size_t)pl.Kpad * kStrip);
+}
+
+bool linked_fits(const ParamLayout &pl, int64_t Na, int nel) {
+    return pl.nA >= 2 && pl.nA <= kMaxActive && 1 + nel * (pl.nA - nel) <= kLinkedRows &&
+           linked_lds(pl, Na) <= 160 * 1024 && Na < (1 << 24);
+}
+
+// The per-tuple A table.  Row r holds twice the stored 1/2 (pq|rs) of pair
+// row r (strip pair order) against every pair column k, in the interleaved
+// column order: column k = 4 ks + kr sits at (ks / 2) * 8 + 2 kr + (ks & 1), so
+// that one 16-byte load gives a lane its values for K steps 2j and 2j + 1;
+// positions past the last K step and columns k >= P are zero.  Rows: A
+// [0, P), with kLinkedSigned -A [P, 2P), then for alpha string K the sum of
+// the diagonal rows (p,p) over its occupied orbitals p, in ascending p.
+__global__ __launch_bounds__(256) void k_linked_a(Batch b) {
+    const ParamLayout &pl = b.pl;
+    const int t = blockIdx.y, P = pl.P, KP = pl.Kpad, nA = b.nA, RL = linked_row_len(KP);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= linked_a_rows(P, b.Na) * RL) return;
+    const int64_t r = i / RL;
+    const int pos = (int)(i % RL);
+    const int k = 4 * (2 * (pos >> 3) + (pos & 1)) + ((pos & 7) >> 1);
+    const double *prm = b.params + (int64_t)t * pl.stride;
+    auto a_at = [&](int row) -> double {
+        return k < P ? 2.0 * prm[pl.off_eri + strip_pair_packed(row, nA) * KP + strip_pair_packed(k, nA)] : 0.0;
+    };
+    const int64_t dg = kLinkedSigned ? 2 * P : P;   // first diagonal-sum row
+    double v;
+    if (r < P) {
+        v = a_at((int)r);
+    } else if (r < dg) {
+        v = -a_at((int)(r - P));
+    } else {
+        const uint32_t m = b.strA[r - dg];
+        v = 0.0;
+        for (int p = 0; p < nA; ++p)
+            if (m >> p & 1u) v += a_at(p);
+    }
+    b.la[(int64_t)t * b.la_stride + i] = v;
+}
+
+hipError_t launch_linked_a(const Batch &b, hipStream_t s) {
+    if (!b.la) return hipSuccess;
+    const int64_t n = linked_a_rows(b.pl.P, b.Na) * linked_row_len(b.pl.Kpad);
+    hipLaunchKernelGGL(k_linked_a, dim3((unsigned)((n + 255) / 256), b.B), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// One workgroup per (tuple, 16-column strip), four waves; wave w runs row
+// tile w & 1 of string g = w >> 1 of each step's pair.  Host tables per
+// alpha string K, 32 slots each (row N_a: all discard): lrow = byte offset of
+// the slot's row in the A table (slot 0 the diagonal sum, then the
+// off-diagonal links, A or -A by the link sign; unused slots row 0), lscat =
+// byte offset of its target row in the sigma strip (K for slot 0, the linked
+// string J for the others, the discard row N_a for unused slots).
+// Step n, two phases split by a barrier:
+//   1. MFMAs of string 2n + g (D[g] and this wave's gathered A rows), loads
+//      of the A rows of string 2n + 2 + g, scatter of string 2n - 2 (waves
+//      0, 1);
+//   2. scatter of string 2n - 1 (waves 2, 3), D of strings 2n + 2 and 2n + 3
+//      from the C rows loaded one step ago, loads of C rows 2n + 4, 2n + 5,
+//      of the scatter entries of string 2n + g and of the A-row offsets of
+//      string 2n + 6 + g.
+// D is read in phase 1 and rewritten in phase 2; one string is scattered per
+// phase, and its targets are distinct, so the adds into every sigma entry
+// come in string order, as in the all-pairs kernel.  Strings past the last
+// read clamped C rows and the discard table row.
+template <int NA>
+__global__ __launch_bounds__(256) void k_sigma_linked(Batch b, VecRef cref, VecRef sref, double shift,
+                                                      int skip_done) {
+    constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4, NID = (KP + 15) / 16;
+    constexpr int RL = (KS + 1) / 2 * 8;   // A-table row length (linked_row_len)
+    constexpr uint32_t DB = KP * kStrip * sizeof(double);   // bytes of one string's D
+    const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
+    int t, strip_id;
+    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = wu >> 1, h = wu & 1;
+    const int ar = lane & 15, kr = lane >> 4;
+    const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
+    const uint32_t B0 = (uint32_t)strip_id * kStrip;
+    const bool colok = B0 + ar < Nb;
+    extern __shared__ double lds[];
+    double *strip = lds;                                                // [Na + 1][16]
+    const uint32_t D0 = (Na + 1) * kStrip * (uint32_t)sizeof(double);   // LDS byte address of D [2][KP][16]
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
+                                                                        (int)(b.dim * sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+        b.la + (int64_t)t * b.la_stride, (short)0, (int)(linked_a_rows(P, Na) * RL * sizeof(double)), 0x00020000);
+    const int tbytes = (int)((Na + 1) * kLinkedRows * sizeof(uint32_t));
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lrow), (short)0,
+                                                                        tbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lscat), (short)0,
+                                                                        tbytes, 0x00020000);
+    // D items: row q = 16 i + (tid >> 4) of each string, column ar; item i is
+    // present in wave w when 16 i + 4 w < KP (then all four of its rows are),
+    // so the items cover the rows [0, KP) exactly.  Beta link of the column
+    // for pair q as a byte offset in a row of C (past the vector when there
+    // is none, so that the load gives zero) and its sign bit.
+    uint32_t boff[NID], bsg[NID];
+#pragma unroll
+    for (int i = 0; i < NID; ++i) {
+        const int q = 16 * i + (tid >> 4);
+        const uint32_t eb = (colok && q < P) ? b.pairB[(B0 + ar) * (uint32_t)P + q] : 0u;
+        const bool vb = (eb & kPairValid) != 0;
+        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
+        bsg[i] = vb ? (eb & kPairSign) : 0u;
+    }
+    // wave-uniform; only the last item can be partial
+    auto item_on = [&](int i) { return 16 * i + 16 <= KP || 16 * i + 4 * wu < KP; };
+    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += 256) strip[i] = 0.0;
+
+    const uint32_t rowC = Nb * (uint32_t)sizeof(double), rowT = kLinkedRows * (uint32_t)sizeof(uint32_t);
+    auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    auto crow = [&](uint32_t s) -> uint32_t { return s < Na ? s : Na - 1; };   // C row of string s
+    auto trow = [&](uint32_t s) -> uint32_t { return s < Na ? s : Na; };       // table row of string s
+    auto load_c = [&](uint32_t s, int i) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                              rc, boff[i], crow(s) * rowC, 0));
+    };
+    auto load_row = [&](uint32_t s) -> uint32_t {   // A-row offset of this lane's A slot 16 h + ar
+        return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u,
+                                                    trow(s) * rowT, 0);
+    };
+    auto load_scat = [&](uint32_t s, int v) -> uint32_t {   // target of output row 16 h + kr + 4 v
+        return __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(16 * h + kr + 4 * v) * 4u,
+                                                    trow(s) * rowT, 0);
+    };
+    // this lane's A values for all K steps of the row at byte offset ra: one
+    // 16-byte load per K-step pair (interleaved row layout)
+    auto load_a = [&](uint32_t ra, double (&af)[KS]) {
+        const uint32_t o = ra + (uint32_t)kr * 16u;
+#pragma unroll
+        for (int j = 0; j < KS / 2; ++j) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rl, o + (uint32_t)j * 64u, 0, 0);
+            af[2 * j] = __hiloint2double((int)v[1], (int)v[0]);
+            af[2 * j + 1] = __hiloint2double((int)v[3], (int)v[2]);
+        }
+        if (KS & 1)
+            af[KS - 1] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rl, o + (uint32_t)(KS / 2) * 64u, 0, 0));
+    };
+    auto dval = [&](double x, int i) -> double {   // D entry: the C value with the beta link sign
+        return __hiloint2double(__double2hiint(x) ^ (int)bsg[i], __double2loint(x));
+    };
+    const uint32_t dw = D0 + (uint32_t)tid * (uint32_t)sizeof(double);   // D item 0 of string 0
+    const uint32_t dr = D0 + (uint32_t)g * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
+    const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
+
+    // Loads run two steps ahead of their use (A rows one step), in register
+    // sets that alternate between even (A) and odd (B) steps.
+    double afA[KS], afB[KS], cbA[2][NID], cbB[2][NID];
+    uint32_t eA[4], eB[4];
+    dbl4 accA = {0.0, 0.0, 0.0, 0.0}, accB = {0.0, 0.0, 0.0, 0.0};
+    // prologue: A rows of string g, D of strings 0 and 1, C rows 2 to 5,
+    // scatter entries of strings g - 2 (discard) and g
+    {
+        const uint32_t r0 = load_row(g);
+        load_a(r0, afA);
+    }
+    uint32_t raA = load_row(2 + g), raB = load_row(4 + g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        eA[v] = load_scat(Na, v);
+        eB[v] = load_scat(g, v);
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int i = 0; i < NID; ++i)
+            if (item_on(i)) *lds_at(dw + s2 * DB + i * 2048u) = dval(load_c(s2, i), i);
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int i = 0; i < NID; ++i) {
+            cbA[s2][i] = item_on(i) ? load_c(2 + s2, i) : 0.0;
+            cbB[s2][i] = item_on(i) ? load_c(4 + s2, i) : 0.0;
+        }
+    __syncthreads();
+
+    auto scatter = [&](const dbl4 &w, const uint32_t (&e)[4]) {
+        // target row e (a multiple of 128 bytes), column ar; the add is done
+        // by the LDS unit (the strip starts the dynamic LDS block at address
+        // 0: the kernel has no static LDS, checked at set-up)
+        // (without kLinkedSigned the link sign is bit 31 of the entry)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double x = kLinkedSigned ? w[v]
+                                           : __hiloint2double(__double2hiint(w[v]) ^ (int)(e[v] & kPairSign),
+                                                              __double2loint(w[v]));
+            __builtin_amdgcn_ds_atomic_fadd_f64(
+                (__attribute__((address_space(3))) double *)(uintptr_t)((e[v] & 0x7FFFFFFFu) | ar8), x);
+        }
+    };
+    // step n: MFMAs of string 2n + g into `an`, scatter of string 2n - 2 + g
+    // from `ao` with entries `e`, D of strings 2n + 2, 2n + 3 from `cb`;
+    // reloads: A rows of string 2n + 2 + g into `afn` (with `ra`), then `ra`
+    // for string 2n + 6 + g, `e` for string 2n + 2 + g, `cb` with C rows
+    // 2n + 6, 2n + 7
+    auto step = [&](uint32_t n, double (&afc)[KS], double (&afn)[KS], dbl4 &an, dbl4 &ao, uint32_t (&e)[4],
+                    uint32_t &ra, double (&cb)[2][NID]) {
+        {
+            double bv[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bv[ks] = *lds_at(dr + ks * 4u * kStrip * (uint32_t)sizeof(double));
+            dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(afc[ks], bv[ks], a, 0, 0, 0);
+            an = a;
+        }
+        load_a(ra, afn);
+        ra = load_row(2 * n + 6 + g);
+        if (g == 0) scatter(ao, e);
+        __syncthreads();
+        if (g == 1) scatter(ao, e);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[v] = load_scat(2 * n + 2 + g, v);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int i = 0; i < NID; ++i)
+                if (item_on(i)) *lds_at(dw + s2 * DB + i * 2048u) = dval(cb[s2][i], i);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int i = 0; i < NID; ++i)
+                if (item_on(i)) cb[s2][i] = load_c(2 * n + 6 + s2, i);
+        __syncthreads();
+    };
+    const uint32_t nsteps = (Na + 1) / 2 + 1;
+    for (uint32_t n = 0; n < nsteps; n += 2) {
+        step(n, afA, afB, accA, accB, eA, raA, cbA);
+        step(n + 1, afB, afA, accB, accA, eB, raB, cbB);
+    }
+    for (uint32_t i = tid; i < Na * kStrip; i += 256) {
+        const uint32_t row = i / kStrip, col = i % kStrip;
+        if (B0 + col < Nb) {
+            const uint32_t d = row * Nb + B0 + col;
+            sg[d] = strip[i] + shift * c[d];
+        }
+    }
+}
+
+template <int NA>
+static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+    const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
+    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
+    hipLaunchKernelGGL(k_sigma_linked<NA>, grid, dim3(256), linked_lds(b.pl, b.Na), s, b, c, sig, shift, skip);
+    return hipGetLastError();
+}
+
 template <int NA>
 static hipError_t launch_strip_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
@@ -426,6 +703,21 @@ static hipError_t launch_strip_na(const Batch &b, VecRef c, VecRef sig, double s
 }
 
 hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+    if (b.la) {   // linked-row variant (the planner checked linked_fits)
+        switch (b.nA) {
+            case 4: return launch_linked_na<4>(b, c, sig, shift, skip, s);
+            case 5: return launch_linked_na<5>(b, c, sig, shift, skip, s);
+            case 6: return launch_linked_na<6>(b, c, sig, shift, skip, s);
+            case 7: return launch_linked_na<7>(b, c, sig, shift, skip, s);
+            case 8: return launch_linked_na<8>(b, c, sig, shift, skip, s);
+            case 9: return launch_linked_na<9>(b, c, sig, shift, skip, s);
+            case 10: return launch_linked_na<10>(b, c, sig, shift, skip, s);
+            case 11: return launch_linked_na<11>(b, c, sig, shift, skip, s);
+            case 12: return launch_linked_na<12>(b, c, sig, shift, skip, s);
+            case 13: return launch_linked_na<13>(b, c, sig, shift, skip, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (b.nA) {
         case 1: return launch_strip_na<1>(b, c, sig, shift, skip, s);
         case 2: return launch_strip_na<2>(b, c, sig, shift, skip, s);
@@ -452,7 +744,12 @@ hipError_t init_strip_kernels() {
                             (const void *)k_sigma_strip<7>,  (const void *)k_sigma_strip<8>,
                             (const void *)k_sigma_strip<9>,  (const void *)k_sigma_strip<10>,
                             (const void *)k_sigma_strip<11>, (const void *)k_sigma_strip<12>,
-                            (const void *)k_sigma_strip<13>};
+                            (const void *)k_sigma_strip<13>, (const void *)k_sigma_linked<4>,
+                            (const void *)k_sigma_linked<5>,  (const void *)k_sigma_linked<6>,
+                            (const void *)k_sigma_linked<7>,  (const void *)k_sigma_linked<8>,
+                            (const void *)k_sigma_linked<9>,  (const void *)k_sigma_linked<10>,
+                            (const void *)k_sigma_linked<11>, (const void *)k_sigma_linked<12>,
+                            (const void *)k_sigma_linked<13>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

@@ -77,13 +77,15 @@ SIGMA_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+# (sigma_variant, linked_rows): column strip with linked rows where n_A >= 10
+# (the default), column strip on all pair rows, materialised W
+@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (2, 1)])
 @pytest.mark.parametrize("name,S", SIGMA_CASES)
-def test_hdiag_and_sigma_match_oracle(ws, name, S, variant):
+def test_hdiag_and_sigma_match_oracle(ws, name, S, variant, linked):
     P = PROBLEMS[name]()
-    ctx = _ctx(P, sigma_variant=variant)
+    ctx = _ctx(P, sigma_variant=variant, linked_rows=linked)
     sp = fci.cas_space(P, S)
-    print(f"case {name} {S} dim {sp.dim}", flush=True)
+    print(f"case {name} {S} dim {sp.dim} variant {variant} linked {linked}", flush=True)
     rng = np.random.default_rng(sum(S) + 7)
     c = rng.standard_normal((2, sp.dim))
     sg = core_order_signs(sp)
@@ -154,6 +156,24 @@ def test_sigma_variants_agree(ws):
     e2, s2 = _ctx(P, sigma_variant=2).solve_tuples(3, tuples, ws)
     assert (s1 == 0).all() and (s2 == 0).all()
     assert np.abs(e1 - e2).max() <= 1e-10
+
+
+def test_linked_rows_solves(ws):
+    """Order-5 tuples of the 24-orbital sweep (n_A = 11, the linked-row strip
+    kernel): a repeat run and the per-solve path give bitwise the same
+    energies, and the all-pairs strip kernel the same within 1e-10."""
+    P = synth.config_sweep(0)
+    import itertools
+    tuples = list(itertools.combinations(P.expansion_space(), 5))[::1500][:4]
+    ctx = _ctx(P)
+    assert all(ctx.tuple_shape(5, S)["n_active"] == 11 for S in tuples)
+    e1, s1 = ctx.solve_tuples(5, tuples, ws)
+    e2, s2 = _ctx(P).solve_tuples(5, tuples, ws)
+    e3, s3 = _ctx(P, batched=0).solve_tuples(5, tuples, ws)
+    e4, s4 = _ctx(P, linked_rows=0).solve_tuples(5, tuples, ws)
+    assert all((s == 0).all() for s in (s1, s2, s3, s4))
+    assert np.array_equal(e1, e2) and np.array_equal(e1, e3)
+    assert np.abs(e1 - e4).max() <= 1e-10
 
 
 def test_repeat_runs_are_bitwise_identical(ws):
