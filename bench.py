@@ -205,7 +205,7 @@ def main():
                      "algorithmic_bytes_per_launch": st["sigma_bytes"] / max(1, st["sigma_launches"]),
                      "kernel": "k_sigma_linked / k_sigma_strip (alpha-beta term of sigma by 16-column strips: "
                                "D gathered from C, FP64 MFMA with (pq|rs) on the pair rows that link each alpha "
-                               "string (all pair rows for n_A < 10), W scattered through the alpha links into "
+                               "string (all pair rows for n_A < 9), W scattered through the alpha links into "
                                "the LDS strip; FLOPs counted on the rows formed)",
                      "per_launch_flops": st["sigma_flops"] / max(1, st["sigma_launches"]),
                      "avg_launch_ms": st["sigma_ms"] / max(1, st["sigma_launches"])},

@@ -101,7 +101,7 @@ typedef struct {
                                the convergence tolerances. */
     int32_t linked_rows;    /* column-strip alpha-beta term: 1 (default) forms W only on the pair
                                rows that link each alpha string to another (1 + n_a (n_A - n_a)
-                               rows, at most 32; the diagonal pairs summed first) where n_A >= 10
+                               rows, at most 32; the diagonal pairs summed first) where n_A >= 9
                                and they fit; 0 always forms all P_A pair rows.  Same result up to
                                rounding. */
     int32_t reserved[4];

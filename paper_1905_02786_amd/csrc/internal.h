@@ -118,7 +118,7 @@ hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int 
 // linked-row strip kernel: row slots per alpha string, fit check, per-tuple
 // A-table size (doubles) and its build (once per batch, after the gather)
 constexpr int kLinkedRows = 32;
-constexpr int kLinkedMinActive = 10;   // smallest n_A that uses the linked-row kernel
+constexpr int kLinkedMinActive = 9;    // smallest n_A that uses the linked-row kernel
 // Per-tuple A table of the linked-row kernel: with kLinkedSigned the rows are
 // A, -A (the alpha link sign picked by the row), then the diagonal sums;
 // without it A, then the diagonal sums, and the sign rides on the scatter
@@ -127,6 +127,9 @@ constexpr int kLinkedMinActive = 10;   // smallest n_A that uses the linked-row 
 // doubles per K-step pair.
 constexpr bool kLinkedSigned = false;
 __host__ __device__ inline int linked_row_len(int Kpad) { return (Kpad / 4 + 1) / 2 * 8; }
+// Position of row slot s = 16 h + kr + 4 v (MFMA output row of tile h held by
+// lanes kr in register v) in a string's scatter-entry row: 16 h + 4 kr + v.
+inline int linked_scat_pos(int s) { return (s & 16) | ((s & 3) << 2) | ((s >> 2) & 3); }
 bool linked_fits(const ParamLayout &pl, int64_t Na, int nel);
 int64_t linked_a_stride(const ParamLayout &pl, int64_t Na);
 hipError_t launch_linked_a(const Batch &b, hipStream_t s);

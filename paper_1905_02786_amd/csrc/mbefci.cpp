@@ -97,7 +97,9 @@ void build_tables(int nA, int nel, Tables &T) {
     // target row of the sigma strip (128 bytes a row).  Slot 0 is the
     // diagonal sum (target I), then the off-diagonal links in link order
     // (target J, the negated row for a negative sign); unused slots read row
-    // 0 and go to the discard row nstr.
+    // 0 and go to the discard row nstr.  lscat is stored in the order of the
+    // MFMA output rows of a lane (linked_scat_pos), so that a lane's four
+    // entries are one 16-byte load.
     T.lrow.clear();
     T.lscat.clear();
     if (1 + nel * (nA - nel) <= kLinkedRows) {
@@ -108,7 +110,7 @@ void build_tables(int nA, int nel, Tables &T) {
         for (int64_t I = 0; I < T.nstr; ++I) {
             uint32_t *lr = &T.lrow[(size_t)I * kLinkedRows], *ls = &T.lscat[(size_t)I * kLinkedRows];
             lr[0] = (uint32_t)(dg + I) * kp8;
-            ls[0] = (uint32_t)I * 128u;
+            ls[linked_scat_pos(0)] = (uint32_t)I * 128u;
             int slot = 1;
             for (int e = 0; e < T.nent; ++e) {
                 const uint32_t L = T.links[(size_t)I * T.nent + e];
@@ -120,7 +122,7 @@ void build_tables(int nA, int nel, Tables &T) {
                 const int col = nA + P - p;
                 const uint32_t neg = L & 0x80000000u;
                 lr[slot] = (uint32_t)(col + ((kLinkedSigned && neg) ? np : 0)) * kp8;
-                ls[slot] = (L & 0xFFFFFu) * 128u | (kLinkedSigned ? 0u : neg);
+                ls[linked_scat_pos(slot)] = (L & 0xFFFFFu) * 128u | (kLinkedSigned ? 0u : neg);
                 ++slot;
             }
         }
@@ -285,7 +287,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
     cp.psp = (davidson && cp.variant == SIGMA_STRIP && ctx->opt.pspace > 0)
                  ? (int)std::min<int64_t>(ctx->opt.pspace, cp.dim) : 0;
-    // linked rows pay off where they replace at least four MFMA row tiles
+    // linked rows pay off where they replace at least three MFMA row tiles
     cp.linked = cp.variant == SIGMA_STRIP && ctx->opt.linked_rows != 0 && key.nA >= kLinkedMinActive &&
                 !cp.ta->lrow.empty() && linked_fits(cp.pl, cp.ta->nstr, key.na);
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +

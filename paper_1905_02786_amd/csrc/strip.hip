@@ -491,9 +491,10 @@ hipError_t launch_linked_a(const Batch &b, hipStream_t s) {
 // tile w & 1 of string g = w >> 1 of each step's pair.  Host tables per
 // alpha string K, 32 slots each (row N_a: all discard): lrow = byte offset of
 // the slot's row in the A table (slot 0 the diagonal sum, then the
-// off-diagonal links, A or -A by the link sign; unused slots row 0), lscat =
-// byte offset of its target row in the sigma strip (K for slot 0, the linked
-// string J for the others, the discard row N_a for unused slots).
+// off-diagonal links; unused slots row 0), lscat = byte offset of its target
+// row in the sigma strip (K for slot 0, the linked string J for the others,
+// the discard row N_a for unused slots), bit 31 the alpha link sign, in the
+// order of the MFMA output rows of a lane (linked_scat_pos).
 // Step n, two phases split by a barrier:
 //   1. MFMAs of string 2n + g (D[g] and this wave's gathered A rows), loads
 //      of the A rows of string 2n + 2 + g, scatter of string 2n - 2 (waves
@@ -567,9 +568,12 @@ __global__ __launch_bounds__(256) void k_sigma_linked(Batch b, VecRef cref, VecR
         return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u,
                                                     trow(s) * rowT, 0);
     };
-    auto load_scat = [&](uint32_t s, int v) -> uint32_t {   // target of output row 16 h + kr + 4 v
-        return __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(16 * h + kr + 4 * v) * 4u,
-                                                    trow(s) * rowT, 0);
+    // targets of this lane's output rows 16 h + kr + 4 v, v = 0..3 (stored
+    // side by side at 16 h + 4 kr)
+    auto load_scat = [&](uint32_t s, uint32_t (&e)[4]) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)(16 * h + 4 * kr) * 4u, trow(s) * rowT, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = v[k];
     };
     // this lane's A values for all K steps of the row at byte offset ra: one
     // 16-byte load per K-step pair (interleaved row layout)
@@ -603,11 +607,8 @@ __global__ __launch_bounds__(256) void k_sigma_linked(Batch b, VecRef cref, VecR
         load_a(r0, afA);
     }
     uint32_t raA = load_row(2 + g), raB = load_row(4 + g);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        eA[v] = load_scat(Na, v);
-        eB[v] = load_scat(g, v);
-    }
+    load_scat(Na, eA);
+    load_scat(g, eB);
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
@@ -657,8 +658,7 @@ __global__ __launch_bounds__(256) void k_sigma_linked(Batch b, VecRef cref, VecR
         if (g == 0) scatter(ao, e);
         __syncthreads();
         if (g == 1) scatter(ao, e);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) e[v] = load_scat(2 * n + 2 + g, v);
+        load_scat(2 * n + 2 + g, e);
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll

@@ -77,7 +77,7 @@ SIGMA_CASES = [
 ]
 
 
-# (sigma_variant, linked_rows): column strip with linked rows where n_A >= 10
+# (sigma_variant, linked_rows): column strip with linked rows where n_A >= 9
 # (the default), column strip on all pair rows, materialised W
 @pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (2, 1)])
 @pytest.mark.parametrize("name,S", SIGMA_CASES)
