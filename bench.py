@@ -24,7 +24,7 @@ METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |Î”E|â‰
 # HBM bytes per k_sigma_strip dispatch from the calibrated FETCH_SIZE / WRITE_SIZE
 # passes in profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md, valid only for
 # the strip kernel source they were taken on (kernels_sha1 below).
-TRAFFIC = {"kernels_sha1": "9d2ad170d3354fde853a48f960cc4366a738d640", "bytes_per_launch": 847052888.2}
+TRAFFIC = {"kernels_sha1": "7f51a7372b9fb8c5542d95b1b5a73dbf61a9acbd", "bytes_per_launch": 960010127.4}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
