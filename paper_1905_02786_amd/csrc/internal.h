@@ -73,10 +73,12 @@ struct Batch {
     const uint32_t *scatA, *pairB;   // column-strip sigma: alpha scatter table, beta pair links
     // linked-row strip sigma (null la: the all-pairs strip kernel): per alpha
     // string the A-row offsets and sigma-strip targets of its 32 row slots
-    // [Na + 1][32], and the per-tuple A table [B][la_stride]
+    // [Na + 1][32], the per-tuple A table [B][la_stride] and the string order
     const uint32_t *lrow, *lscat;
     double *la;
     int64_t la_stride;
+    const int32_t *lperm;   // [2 (lpairs + 5)] alpha strings in pairs (N_a: dummy)
+    int lpairs;
     const int32_t *act;     // [B * nA] active orbitals (ascending)
     const int32_t *core;    // [B * nC] core orbitals
     double *params;         // [B * pl.stride]

@@ -28,7 +28,58 @@ struct Tables {
     std::vector<uint32_t> pairs;     // [nstr][P]: link of each string per pair, strip pair order
     std::vector<uint32_t> scat;      // [nstr + 1][P + 1]: scatter form for the strip kernel
     std::vector<uint32_t> lrow, lscat;   // [nstr + 1][32]: linked-row form (empty if the links need more slots)
+    std::vector<int32_t> lperm;          // [2 (lpairs + 5)]: string order of the linked-row kernel
+    int lpairs = 0;
 };
+
+// Order of the alpha strings for the linked-row kernel: pairs of strings
+// that differ in at least three orbitals (then neither reaches the other,
+// nor a common string, by one replacement: they share no scatter target),
+// padded with the dummy index nstr, plus five dummy pairs at the end.
+// Greedy, most constrained first: a pair starts with the unplaced string
+// that has the fewest unplaced compatible strings and takes the compatible
+// one with the fewest (lowest index on ties).
+void pair_strings(Tables &T) {
+    const int64_t N = T.nstr;
+    const size_t W = (size_t)(N + 63) / 64;
+    std::vector<uint64_t> comp((size_t)N * W, 0), avail(W, 0), cand(W);
+    std::vector<int64_t> deg(N, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        avail[i / 64] |= 1ull << (i % 64);
+        for (int64_t j = 0; j < N; ++j)
+            if (j != i && __builtin_popcount(T.strings[i] & T.strings[j]) <= T.nel - 3) {
+                comp[(size_t)i * W + j / 64] |= 1ull << (j % 64);
+                ++deg[i];
+            }
+    }
+    auto pick = [&](const std::vector<uint64_t> &set) -> int64_t {
+        int64_t best = -1;
+        for (size_t w = 0; w < W; ++w)
+            for (uint64_t m = set[w]; m; m &= m - 1) {
+                const int64_t i = (int64_t)(w * 64 + __builtin_ctzll(m));
+                if (best < 0 || deg[i] < deg[best]) best = i;
+            }
+        return best;
+    };
+    auto take = [&](int64_t i) {
+        avail[i / 64] &= ~(1ull << (i % 64));
+        for (size_t w = 0; w < W; ++w)
+            for (uint64_t m = comp[(size_t)i * W + w]; m; m &= m - 1) --deg[w * 64 + __builtin_ctzll(m)];
+    };
+    T.lperm.clear();
+    for (int64_t left = N; left > 0;) {
+        const int64_t a = pick(avail);
+        take(a);
+        for (size_t w = 0; w < W; ++w) cand[w] = avail[w] & comp[(size_t)a * W + w];
+        const int64_t b = pick(cand);
+        if (b >= 0) take(b);
+        T.lperm.push_back((int32_t)a);
+        T.lperm.push_back(b >= 0 ? (int32_t)b : (int32_t)N);
+        left -= b >= 0 ? 2 : 1;
+    }
+    T.lpairs = (int)(T.lperm.size() / 2);
+    T.lperm.resize(T.lperm.size() + 10, (int32_t)N);
+}
 
 // Strings with `nel` of `nA` bits set, ascending; for each string I the
 // entries (p, q) with q in I and (p not in I or p == q): diagonal entries
@@ -102,6 +153,8 @@ void build_tables(int nA, int nel, Tables &T) {
     // entries are one 16-byte load.
     T.lrow.clear();
     T.lscat.clear();
+    T.lperm.clear();
+    T.lpairs = 0;
     if (1 + nel * (nA - nel) <= kLinkedRows) {
         const uint32_t kp8 = (uint32_t)linked_row_len((np + 3) / 4 * 4) * 8u;
         const uint32_t dg = kLinkedSigned ? 2 * np : np;   // first diagonal-sum row
@@ -126,6 +179,7 @@ void build_tables(int nA, int nel, Tables &T) {
                 ++slot;
             }
         }
+        pair_strings(T);
     }
 }
 
@@ -295,7 +349,8 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
                      align256(4 * (size_t)(cp.ta->nstr + 1) * (cp.pl.P + 1)) +
                      align256(4 * (size_t)cp.tb->nstr * cp.pl.P) +
-                     (cp.linked ? 2 * align256(4 * (size_t)(cp.ta->nstr + 1) * kLinkedRows) : 0) +
+                     (cp.linked ? 2 * align256(4 * (size_t)(cp.ta->nstr + 1) * kLinkedRows) +
+                                      align256(4 * cp.ta->lperm.size()) : 0) +
                      64 * 256;
     const int ms = davidson ? ctx->opt.max_space : 0;
     size_t pt = 0;
@@ -362,10 +417,14 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.lscat = cv.take<uint32_t>((size_t)(b.Na + 1) * kLinkedRows);
         b.la_stride = linked_a_stride(cp.pl, b.Na);
         b.la = cv.take<double>((size_t)B * b.la_stride);
+        b.lperm = cv.take<int32_t>(cp.ta->lperm.size());
+        b.lpairs = cp.ta->lpairs;
     } else {
         b.lrow = b.lscat = nullptr;
         b.la = nullptr;
         b.la_stride = 0;
+        b.lperm = nullptr;
+        b.lpairs = 0;
     }
     b.act = cv.take<int32_t>((size_t)B * b.nA + 1);
     b.core = cv.take<int32_t>((size_t)B * b.nC + 1);
@@ -443,6 +502,8 @@ mbefci_status upload_tables(mbefci_ctx *ctx, const ClassPlan &cp, const Batch &b
                               hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync((void *)b.lscat, cp.ta->lscat.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
                               hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync((void *)b.lperm, cp.ta->lperm.data(), 4 * cp.ta->lperm.size(), hipMemcpyHostToDevice,
+                              ctx->stream));
     }
     return MBEFCI_OK;
 }

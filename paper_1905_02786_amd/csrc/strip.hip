@@ -437,13 +437,30 @@ int64_t linked_a_stride(const ParamLayout &pl, int64_t Na) {
 }
 
 // LDS: sigma strip [Na + 1][16] and D of the step's two strings [2][Kpad][16].
-static size_t linked_lds(const ParamLayout &pl, int64_t Na) {
+static size_t linked_lds_gat(const ParamLayout &pl, int64_t Na) {
     return sizeof(double) * ((size_t)(Na + 1) * kStrip + 2 * (size_t)pl.Kpad * kStrip);
+}
+
+// LDS: sigma strip [Na + 1][16], D of the two halves' pairs [2][2][Kpad][16],
+// the A rows [P][row length] and the two halves' staged diagonal sums [2][2].
+static size_t linked_lds_res(const ParamLayout &pl, int64_t Na) {
+    const size_t rl = (size_t)linked_row_len(pl.Kpad);
+    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 4 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 4) * rl);
+}
+
+// The resident-A kernel (A rows in LDS, one eight-wave workgroup in two
+// halves) needs more LDS than the gathered-A kernel (four waves, A rows
+// loaded through the vector memory path, which they saturate); it is used
+// where that costs no occupancy: two of its workgroups fit a CU, or the
+// gathered-A kernel fits at most two.
+static bool linked_resident(const ParamLayout &pl, int64_t Na) {
+    const size_t res = linked_lds_res(pl, Na), gat = linked_lds_gat(pl, Na);
+    return res <= 160 * 1024 && (2 * res <= 160 * 1024 || 3 * gat > 160 * 1024);
 }
 
 bool linked_fits(const ParamLayout &pl, int64_t Na, int nel) {
     return pl.nA >= 2 && pl.nA <= kMaxActive && 1 + nel * (pl.nA - nel) <= kLinkedRows &&
-           linked_lds(pl, Na) <= 160 * 1024 && Na < (1 << 24);
+           (linked_resident(pl, Na) || linked_lds_gat(pl, Na) <= 160 * 1024) && Na < (1 << 24);
 }
 
 // The per-tuple A table.  Row r holds twice the stored 1/2 (pq|rs) of pair
@@ -487,7 +504,8 @@ hipError_t launch_linked_a(const Batch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One workgroup per (tuple, 16-column strip), four waves; wave w runs row
+// Gathered-A kernel.  One workgroup per (tuple, 16-column strip), four
+// waves; wave w runs row
 // tile w & 1 of string g = w >> 1 of each step's pair.  Host tables per
 // alpha string K, 32 slots each (row N_a: all discard): lrow = byte offset of
 // the slot's row in the A table (slot 0 the diagonal sum, then the
@@ -508,7 +526,7 @@ hipError_t launch_linked_a(const Batch &b, hipStream_t s) {
 // come in string order, as in the all-pairs kernel.  Strings past the last
 // read clamped C rows and the discard table row.
 template <int NA>
-__global__ __launch_bounds__(256) void k_sigma_linked(Batch b, VecRef cref, VecRef sref, double shift,
+__global__ __launch_bounds__(256) void k_sigma_linked_gat(Batch b, VecRef cref, VecRef sref, double shift,
                                                       int skip_done) {
     constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4, NID = (KP + 15) / 16;
     constexpr int RL = (KS + 1) / 2 * 8;   // A-table row length (linked_row_len)
@@ -685,11 +703,224 @@ __global__ __launch_bounds__(256) void k_sigma_linked(Batch b, VecRef cref, VecR
     }
 }
 
+// Resident-A kernel.  One workgroup of eight waves per (tuple, 16-column
+// strip), in two halves
+// of four (waves 0-3 and 4-7: one wave of each half per SIMD).  The alpha
+// strings are taken in pairs (lperm, host order: the two strings of a pair
+// differ in at least three orbitals, so they share no scatter target), and
+// pair q belongs to half q & 1.  Phase p (one barrier after each):
+//   * half p & 1 runs the MFMAs of pair p: wave 4x + 2g + h computes row
+//     tile h of string g of the pair, with its B operand from the pair's D
+//     tile and its A operand from the A rows held in LDS for the whole strip
+//     (the slot-0 lanes from the pair's staged diagonal sums);
+//   * the other half scatters its pair p - 1 from the MFMA registers, writes
+//     D and the diagonal sums of its pair p + 1 and issues the loads for its
+//     next phases (A-row offsets of pair p + 1, scatter entries of pair
+//     p + 1, C rows and diagonal sums of pair p + 3).
+// So on every SIMD one wave feeds the matrix pipe while the other does the
+// memory work, and the halves swap at each barrier.  One pair is scattered
+// per phase, in pair order, so every sigma entry gets its adds in a fixed
+// order.  Host tables per alpha string K, 32 slots each (row N_a: all
+// discard): lrow = byte offset of the slot's A row (slot 0, the diagonal
+// sum, is read from the staged row instead; unused slots row 0), lscat = byte
+// offset of its target row in the sigma strip (K for slot 0, the linked
+// string J for the others, the discard row N_a for unused slots), bit 31 the
+// alpha link sign, in the order of the MFMA output rows of a lane
+// (linked_scat_pos).  Dummy strings (index N_a) pad the last pair.
+template <int NA>
+__global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, VecRef sref, double shift,
+                                                      int skip_done) {
+    constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4;
+    constexpr int RL = (KS + 1) / 2 * 8;                      // A-table row length (linked_row_len)
+    constexpr uint32_t RLB = RL * sizeof(double);
+    constexpr uint32_t DB = KP * kStrip * sizeof(double);     // bytes of one string's D
+    constexpr int NDI = (2 * KP * kStrip + 255) / 256;        // D items per thread of a half
+    const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
+    int t, strip_id;
+    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int x = wu >> 2, lw = wu & 3, g = lw >> 1, h = lw & 1;   // half, wave in half, string, tile
+    const int th = tid & 255;                                      // thread in half
+    const int ar = lane & 15, kr = lane >> 4;
+    const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
+    const uint32_t B0 = (uint32_t)strip_id * kStrip;
+    const bool colok = B0 + ar < Nb;
+    extern __shared__ double lds[];
+    double *strip = lds;                                                // [Na + 1][16]
+    const uint32_t D0 = (Na + 1) * kStrip * (uint32_t)sizeof(double);   // D [2 halves][2][KP][16]
+    const uint32_t A0 = D0 + 4 * DB;                                    // A rows [P][RL]
+    const uint32_t G0 = A0 + P * RLB;                                   // diagonal sums [2 halves][2][RL]
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const int32_t *perm = b.lperm;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
+                                                                        (int)(b.dim * sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+        b.la + (int64_t)t * b.la_stride, (short)0, (int)(linked_a_rows(P, Na) * RLB), 0x00020000);
+    const int tbytes = (int)((Na + 1) * kLinkedRows * sizeof(uint32_t));
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lrow), (short)0,
+                                                                        tbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lscat), (short)0,
+                                                                        tbytes, 0x00020000);
+    // D items of a half: element j = th + 256 i of its D [2][KP][16] (string
+    // j / (16 KP), row (j / 16) % KP, column ar).  A wave's 64 elements of an
+    // item lie in one string (16 KP is a multiple of 64), so the string is
+    // wave-uniform, and so is the presence of the last item.  Beta link of
+    // the column for the item's pair as a byte offset in a row of C (past the
+    // vector when there is none, so that the load gives zero) and its sign.
+    uint32_t boff[NDI], bsg[NDI];
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) {
+        const int j = th + 256 * i, q = (j >> 4) % KP;
+        const uint32_t eb = (colok && j < 2 * KP * kStrip && q < P) ? b.pairB[(B0 + ar) * (uint32_t)P + q] : 0u;
+        const bool vb = (eb & kPairValid) != 0;
+        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
+        bsg[i] = vb ? (eb & kPairSign) : 0u;
+    }
+    // wave-uniform; only the last item can be partial
+    auto item_on = [&](int i) { return 256 * (i + 1) <= 2 * KP * kStrip || 64 * lw + 256 * i < 2 * KP * kStrip; };
+    auto item_str = [&](int i) { return (64 * lw + 256 * i) / (KP * kStrip); };
+
+    const uint32_t rowC = Nb * (uint32_t)sizeof(double), rowT = kLinkedRows * (uint32_t)sizeof(uint32_t);
+    auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    auto str = [&](uint32_t q, int k) -> uint32_t { return (uint32_t)perm[2 * q + k]; };   // string k of pair q
+    auto crow = [&](uint32_t s) -> uint32_t { return s < Na ? s : 0u; };   // C row (dummy: any row)
+    auto trow = [&](uint32_t s) -> uint32_t { return s < Na ? s : Na; };   // table row (dummy: discard)
+    auto load_c = [&](uint32_t s, int i) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[i], crow(s) * rowC, 0));
+    };
+    auto load_row = [&](uint32_t s) -> uint32_t {   // A-row offset of this lane's A slot 16 h + ar
+        return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u, trow(s) * rowT, 0);
+    };
+    // targets of this lane's output rows 16 h + kr + 4 v, v = 0..3 (stored
+    // side by side at 16 h + 4 kr)
+    auto load_scat = [&](uint32_t s, uint32_t (&e)[4]) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)(16 * h + 4 * kr) * 4u, trow(s) * rowT, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = v[k];
+    };
+    // diagonal sum of string s: 16 bytes per lane, lanes < RL / 2 of waves
+    // 2g of a half (one wave per string of the pair)
+    const bool dgl = h == 0 && lane < RL / 2;
+    auto load_dg = [&](uint32_t s) -> dbl2v {
+        const uint32_t r = (uint32_t)P + (s < Na ? s : 0u);
+        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, r * RLB, 0));
+    };
+    auto dval = [&](double v, int i) -> double {   // D entry: the C value with the beta link sign
+        return __hiloint2double(__double2hiint(v) ^ (int)bsg[i], __double2loint(v));
+    };
+    const uint32_t dw = D0 + (uint32_t)x * 2 * DB + (uint32_t)th * (uint32_t)sizeof(double);   // D element th of the half
+    const uint32_t dr = D0 + (uint32_t)(2 * x + g) * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
+    const uint32_t gd = G0 + (uint32_t)(2 * x + g) * RLB;                  // staged diagonal sum of string g
+    const uint32_t gw = gd + (uint32_t)lane * 16u;
+    const bool isdg = h == 0 && ar == 0;                                   // lanes of slot 0
+    const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
+
+    // prologue: sigma strip zero, A rows into LDS, D and diagonal sums of
+    // pair 0; registers for the first phases of each half
+    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += 512) strip[i] = 0.0;
+    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 512)
+        *reinterpret_cast<dbl2v *>(lds_at(A0 + 16u * i)) =
+            __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * i, 0, 0));
+    if (x == 0) {
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(load_c(str(0, item_str(i)), i), i);
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = load_dg(str(0, g));
+    }
+    // half 0 runs pair 0 in phase 0, scatters it and prepares pair 2 in phase
+    // 1; half 1 scatters nothing in phase 0 (pair -1: discard) and prepares
+    // pair 1
+    uint32_t ra = load_row(x == 0 ? str(0, g) : Na);
+    uint32_t e[4];
+    load_scat(x == 0 ? str(0, g) : Na, e);
+    double cb[NDI];
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) cb[i] = item_on(i) ? load_c(str(2 - x, item_str(i)), i) : 0.0;
+    dbl2v dg = {0.0, 0.0};
+    if (dgl) dg = load_dg(str(2 - x, g));
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+
+    // the MFMAs of this half's pair (phase p = its pair)
+    auto mphase = [&]() {
+        double bv[KS], af[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = *lds_at(dr + ks * 4u * kStrip * (uint32_t)sizeof(double));
+        const uint32_t arow = (isdg ? gd : A0 + ra) + (uint32_t)kr * 16u;
+#pragma unroll
+        for (int j = 0; j < KS / 2; ++j) {
+            const dbl2v v = *reinterpret_cast<const dbl2v *>(lds_at(arow + 64u * j));
+            af[2 * j] = v[0];
+            af[2 * j + 1] = v[1];
+        }
+        if (KS & 1) af[KS - 1] = *lds_at(arow + 64u * (KS / 2));
+        dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
+        acc = a;
+    };
+    // the memory work of this half in phase p: scatter of pair p - 1, D and
+    // diagonal sums of pair p + 1, loads
+    auto nphase = [&](uint32_t p) {
+        ra = load_row(str(p + 1, g));
+        // target row e & 0x7FFFFFFF (a multiple of 128 bytes), column ar, link
+        // sign in bit 31; the add is done by the LDS unit (the strip starts the
+        // dynamic LDS block at address 0: the kernel has no static LDS, checked
+        // at set-up)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            __builtin_amdgcn_ds_atomic_fadd_f64(
+                (__attribute__((address_space(3))) double *)(uintptr_t)((e[v] & 0x7FFFFFFFu) | ar8),
+                __hiloint2double(__double2hiint(acc[v]) ^ (int)(e[v] & kPairSign), __double2loint(acc[v])));
+        load_scat(str(p + 1, g), e);
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(cb[i], i);
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = dg;
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) cb[i] = load_c(str(p + 3, item_str(i)), i);
+        if (dgl) dg = load_dg(str(p + 3, g));
+    };
+    // one loop per half (straight-line bodies, the same number of barriers)
+    const uint32_t nph = (uint32_t)b.lpairs + 1;   // the last pair is scattered in phase lpairs
+    if (x == 0) {
+        for (uint32_t p = 0; p < nph; p += 2) {
+            mphase();
+            __syncthreads();
+            nphase(p + 1);
+            __syncthreads();
+        }
+    } else {
+        for (uint32_t p = 0; p < nph; p += 2) {
+            nphase(p);
+            __syncthreads();
+            mphase();
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = tid; i < Na * kStrip; i += 512) {
+        const uint32_t row = i / kStrip, col = i % kStrip;
+        if (B0 + col < Nb) {
+            const uint32_t d = row * Nb + B0 + col;
+            sg[d] = strip[i] + shift * c[d];
+        }
+    }
+}
+
 template <int NA>
 static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    hipLaunchKernelGGL(k_sigma_linked<NA>, grid, dim3(256), linked_lds(b.pl, b.Na), s, b, c, sig, shift, skip);
+    if (linked_resident(b.pl, b.Na))
+        hipLaunchKernelGGL(k_sigma_linked_res<NA>, grid, dim3(512), linked_lds_res(b.pl, b.Na), s, b, c, sig,
+                           shift, skip);
+    else
+        hipLaunchKernelGGL(k_sigma_linked_gat<NA>, grid, dim3(256), linked_lds_gat(b.pl, b.Na), s, b, c, sig,
+                           shift, skip);
     return hipGetLastError();
 }
 
@@ -744,12 +975,17 @@ hipError_t init_strip_kernels() {
                             (const void *)k_sigma_strip<7>,  (const void *)k_sigma_strip<8>,
                             (const void *)k_sigma_strip<9>,  (const void *)k_sigma_strip<10>,
                             (const void *)k_sigma_strip<11>, (const void *)k_sigma_strip<12>,
-                            (const void *)k_sigma_strip<13>, (const void *)k_sigma_linked<4>,
-                            (const void *)k_sigma_linked<5>,  (const void *)k_sigma_linked<6>,
-                            (const void *)k_sigma_linked<7>,  (const void *)k_sigma_linked<8>,
-                            (const void *)k_sigma_linked<9>,  (const void *)k_sigma_linked<10>,
-                            (const void *)k_sigma_linked<11>, (const void *)k_sigma_linked<12>,
-                            (const void *)k_sigma_linked<13>};
+                            (const void *)k_sigma_strip<13>,
+                            (const void *)k_sigma_linked_res<4>,  (const void *)k_sigma_linked_gat<4>,
+                            (const void *)k_sigma_linked_res<5>,  (const void *)k_sigma_linked_gat<5>,
+                            (const void *)k_sigma_linked_res<6>,  (const void *)k_sigma_linked_gat<6>,
+                            (const void *)k_sigma_linked_res<7>,  (const void *)k_sigma_linked_gat<7>,
+                            (const void *)k_sigma_linked_res<8>,  (const void *)k_sigma_linked_gat<8>,
+                            (const void *)k_sigma_linked_res<9>,  (const void *)k_sigma_linked_gat<9>,
+                            (const void *)k_sigma_linked_res<10>, (const void *)k_sigma_linked_gat<10>,
+                            (const void *)k_sigma_linked_res<11>, (const void *)k_sigma_linked_gat<11>,
+                            (const void *)k_sigma_linked_res<12>, (const void *)k_sigma_linked_gat<12>,
+                            (const void *)k_sigma_linked_res<13>, (const void *)k_sigma_linked_gat<13>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
