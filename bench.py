@@ -24,7 +24,7 @@ METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |Î”E|â‰
 # HBM bytes per k_sigma_strip dispatch from the calibrated FETCH_SIZE / WRITE_SIZE
 # passes in profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md, valid only for
 # the strip kernel source they were taken on (kernels_sha1 below).
-TRAFFIC = {"kernels_sha1": "7f51a7372b9fb8c5542d95b1b5a73dbf61a9acbd", "bytes_per_launch": 960010127.4}
+TRAFFIC = {"kernels_sha1": "9d5fad88313fa1f46ea5bea990990a7ace0ef9ac", "bytes_per_launch": 806707181.6}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -203,10 +203,10 @@ def main():
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
                      "traffic": TRAFFIC["bytes_per_launch"] if kernels_sha1() == TRAFFIC["kernels_sha1"] else None,
                      "algorithmic_bytes_per_launch": st["sigma_bytes"] / max(1, st["sigma_launches"]),
-                     "kernel": "k_sigma_linked / k_sigma_strip (alpha-beta term of sigma by 16-column strips: "
-                               "D gathered from C, FP64 MFMA with (pq|rs) on the pair rows that link each alpha "
-                               "string (all pair rows for n_A < 9), W scattered through the alpha links into "
-                               "the LDS strip; FLOPs counted on the rows formed)",
+                     "kernel": "k_sigma_linked_res / k_sigma_linked_gat / k_sigma_strip (alpha-beta term of "
+                               "sigma by 16-column strips: D gathered from C, FP64 MFMA with (pq|rs) on the pair "
+                               "rows that link each alpha string (all pair rows for n_A < 9), W scattered through "
+                               "the alpha links into the LDS strip; FLOPs counted on the rows formed)",
                      "per_launch_flops": st["sigma_flops"] / max(1, st["sigma_launches"]),
                      "avg_launch_ms": st["sigma_ms"] / max(1, st["sigma_launches"])},
     }
