@@ -919,33 +919,43 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
         if (rs) {
             acc[2] += x * tv;
         } else {
+            // (vd[i] = 0 for i >= m: those sums stay unused)
 #pragma unroll
-            for (int i = 0; i < MS; ++i)
-                if (i < m) acc[2 + i] += vd[i] * tv;
+            for (int i = 0; i < MS; ++i) acc[2 + i] += vd[i] * tv;
         }
         return tv;
     };
+    // V_i and S_i, i < m, through buffer resources that end after vector m - 1:
+    // the loads of vectors past m read zero, so every load of a determinant is
+    // issued at once (no branch on m between them); the added terms are
+    // exact zeros (yy[i] = 0 there)
+    const int vbytes = (int)((int64_t)m * b.dim * (int64_t)sizeof(double));
+    const __amdgpu_buffer_rsrc_t rV = __builtin_amdgcn_make_buffer_rsrc(V, (short)0, vbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rS = __builtin_amdgcn_make_buffer_rsrc(S, (short)0, vbytes, 0x00020000);
+    const uint32_t vstride = (uint32_t)b.dim * (uint32_t)sizeof(double);
     if (V2) {
         // pairs of determinants with 16-byte loads (dim even: every vector 16-byte aligned)
         typedef double dbl2 __attribute__((ext_vector_type(2)));
         const int64_t n2 = b.dim >> 1;
         for (int64_t d2 = (int64_t)blockIdx.x * 256 + threadIdx.x; d2 < n2; d2 += (int64_t)gridDim.x * 256) {
             const int64_t d = d2 << 1;
+            const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
             double v0[MS], v1[MS];
             double x0 = 0.0, x1 = 0.0, a0 = 0.0, a1 = 0.0;
+            dbl2 vv[MS], ss[MS];
 #pragma unroll
             for (int i = 0; i < MS; ++i) {
-                v0[i] = v1[i] = 0.0;
-                if (i < m) {
-                    const dbl2 vv = *reinterpret_cast<const dbl2 *>(V + (int64_t)i * b.dim + d);
-                    const dbl2 ss = *reinterpret_cast<const dbl2 *>(S + (int64_t)i * b.dim + d);
-                    v0[i] = vv.x;
-                    v1[i] = vv.y;
-                    x0 += yy[i] * vv.x;
-                    x1 += yy[i] * vv.y;
-                    a0 += yy[i] * ss.x;
-                    a1 += yy[i] * ss.y;
-                }
+                vv[i] = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(rV, vo, (uint32_t)i * vstride, 0));
+                ss[i] = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(rS, vo, (uint32_t)i * vstride, 0));
+            }
+#pragma unroll
+            for (int i = 0; i < MS; ++i) {
+                v0[i] = vv[i].x;
+                v1[i] = vv[i].y;
+                x0 += yy[i] * vv[i].x;
+                x1 += yy[i] * vv[i].y;
+                a0 += yy[i] * ss[i].x;
+                a1 += yy[i] * ss[i].y;
             }
             const dbl2 h = *reinterpret_cast<const dbl2 *>(hd + d);
             const double t0 = one(v0, x0, a0, h.x);
@@ -958,15 +968,17 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
         }
     } else {
         for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-            double x = 0.0, ax = 0.0, vd[MS];
+            const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
+            double x = 0.0, ax = 0.0, vd[MS], sd[MS];
 #pragma unroll
             for (int i = 0; i < MS; ++i) {
-                vd[i] = 0.0;
-                if (i < m) {
-                    vd[i] = V[(int64_t)i * b.dim + d];
-                    x += yy[i] * vd[i];
-                    ax += yy[i] * S[(int64_t)i * b.dim + d];
-                }
+                vd[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rV, vo, (uint32_t)i * vstride, 0));
+                sd[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rS, vo, (uint32_t)i * vstride, 0));
+            }
+#pragma unroll
+            for (int i = 0; i < MS; ++i) {
+                x += yy[i] * vd[i];
+                ax += yy[i] * sd[i];
             }
             T[d] = one(vd, x, ax, hd[d]);
             if (rs) {
@@ -1079,33 +1091,42 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
     double *out = direct ? b.V + ((int64_t)t * b.max_space + m) * b.dim : T;
     double acc[1];
     acc[0] = 0.0;
+    // V_i, i < m, through a buffer resource that ends after vector m - 1 (the
+    // loads past it read zero, and cf[i] = 0 there): all loads at once
+    const __amdgpu_buffer_rsrc_t rV = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double *>(V), (short)0, (int)((int64_t)m * b.dim * (int64_t)sizeof(double)), 0x00020000);
+    const uint32_t vstride = (uint32_t)b.dim * (uint32_t)sizeof(double);
     if (V2) {
         // pairs of determinants with 16-byte loads (dim even), all loads first
         typedef double dbl2 __attribute__((ext_vector_type(2)));
         const int64_t n2 = b.dim >> 1;
         for (int64_t d2 = (int64_t)blockIdx.x * 256 + threadIdx.x; d2 < n2; d2 += (int64_t)gridDim.x * 256) {
             const int64_t d = d2 << 1;
+            const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
             dbl2 vv[MS];
 #pragma unroll
             for (int i = 0; i < MS; ++i)
-                vv[i] = (i < m) ? *reinterpret_cast<const dbl2 *>(V + (int64_t)i * b.dim + d) : dbl2{0.0, 0.0};
+                vv[i] = __builtin_bit_cast(dbl2, __builtin_amdgcn_raw_buffer_load_b128(rV, vo, (uint32_t)i * vstride, 0));
             dbl2 v = *reinterpret_cast<const dbl2 *>(T + d);
 #pragma unroll
-            for (int i = 0; i < MS; ++i)
-                if (i < m) {
-                    v.x -= cf[i] * vv[i].x;
-                    v.y -= cf[i] * vv[i].y;
-                }
+            for (int i = 0; i < MS; ++i) {
+                v.x -= cf[i] * vv[i].x;
+                v.y -= cf[i] * vv[i].y;
+            }
             *reinterpret_cast<dbl2 *>(out + d) = dbl2{v.x * sc, v.y * sc};
             acc[0] += v.x * v.x;
             acc[0] += v.y * v.y;
         }
     } else {
         for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-            double v = T[d];
+            const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
+            double vd[MS];
 #pragma unroll
             for (int i = 0; i < MS; ++i)
-                if (i < m) v -= cf[i] * V[(int64_t)i * b.dim + d];
+                vd[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rV, vo, (uint32_t)i * vstride, 0));
+            double v = T[d];
+#pragma unroll
+            for (int i = 0; i < MS; ++i) v -= cf[i] * vd[i];
             out[d] = v * sc;
             acc[0] += v * v;
         }
