@@ -99,11 +99,14 @@ typedef struct {
                                elsewhere; 0..128, 0 = diagonal only (default 128).  Only for
                                column-strip classes; the result does not depend on it beyond
                                the convergence tolerances. */
-    int32_t linked_rows;    /* column-strip alpha-beta term: 1 (default) forms W only on the pair
-                               rows that link each alpha string to another (1 + n_a (n_A - n_a)
-                               rows, at most 32; the diagonal pairs summed first) where n_A >= 9
-                               and they fit; 0 always forms all P_A pair rows.  Same result up to
-                               rounding. */
+    int32_t linked_rows;    /* column-strip alpha-beta term: 0 forms all P_A pair rows of W; 1
+                               (default) forms only the pair rows that link each alpha string
+                               to another (1 + n_a (n_A - n_a) rows, at most 32; the diagonal
+                               pairs summed first) where n_A >= 9 and they fit, with the A rows
+                               resident in LDS or gathered per string, whichever keeps the
+                               occupancy; 2 and 3 use linked rows wherever they fit (n_A >= 4),
+                               2 with the A rows gathered, 3 resident (each where it fits, else
+                               the other).  Same result up to rounding. */
     int32_t reserved[4];
 } mbefci_options;
 

@@ -342,7 +342,8 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.psp = (davidson && cp.variant == SIGMA_STRIP && ctx->opt.pspace > 0)
                  ? (int)std::min<int64_t>(ctx->opt.pspace, cp.dim) : 0;
     // linked rows pay off where they replace at least three MFMA row tiles
-    cp.linked = cp.variant == SIGMA_STRIP && ctx->opt.linked_rows != 0 && key.nA >= kLinkedMinActive &&
+    const int lm = ctx->opt.linked_rows;
+    cp.linked = cp.variant == SIGMA_STRIP && lm != 0 && key.nA >= (lm == 1 ? kLinkedMinActive : 4) &&
                 !cp.ta->lrow.empty() && linked_fits(cp.pl, cp.ta->nstr, key.na);
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
@@ -419,6 +420,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.la = cv.take<double>((size_t)B * b.la_stride);
         b.lperm = cv.take<int32_t>(cp.ta->lperm.size());
         b.lpairs = cp.ta->lpairs;
+        b.linked_mode = ctx->opt.linked_rows;
     } else {
         b.lrow = b.lscat = nullptr;
         b.la = nullptr;
@@ -1056,7 +1058,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
     if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
     if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
-    if (o->linked_rows != 0 && o->linked_rows != 1) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be 0 or 1");
+    if (o->linked_rows < 0 || o->linked_rows > 3) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..3");
     ctx->opt = *o;
     return MBEFCI_OK;
 }

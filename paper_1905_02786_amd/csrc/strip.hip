@@ -459,7 +459,7 @@ static bool linked_resident(const ParamLayout &pl, int64_t Na) {
 }
 
 bool linked_fits(const ParamLayout &pl, int64_t Na, int nel) {
-    return pl.nA >= 2 && pl.nA <= kMaxActive && 1 + nel * (pl.nA - nel) <= kLinkedRows &&
+    return pl.nA >= 4 && pl.nA <= kMaxActive && 1 + nel * (pl.nA - nel) <= kLinkedRows &&
            (linked_resident(pl, Na) || linked_lds_gat(pl, Na) <= 160 * 1024) && Na < (1 << 24);
 }
 
@@ -915,7 +915,9 @@ template <int NA>
 static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    if (linked_resident(b.pl, b.Na))
+    const bool res_fits = linked_lds_res(b.pl, b.Na) <= 160 * 1024, gat_fits = linked_lds_gat(b.pl, b.Na) <= 160 * 1024;
+    const bool res = b.linked_mode == 3 ? res_fits : b.linked_mode == 2 ? !gat_fits : linked_resident(b.pl, b.Na);
+    if (res)
         hipLaunchKernelGGL(k_sigma_linked_res<NA>, grid, dim3(512), linked_lds_res(b.pl, b.Na), s, b, c, sig,
                            shift, skip);
     else

@@ -78,8 +78,9 @@ SIGMA_CASES = [
 
 
 # (sigma_variant, linked_rows): column strip with linked rows where n_A >= 9
-# (the default), column strip on all pair rows, materialised W
-@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (2, 1)])
+# (the default), column strip on all pair rows, linked rows wherever they fit
+# with the A rows gathered (2) or resident in LDS (3), materialised W
+@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (1, 2), (1, 3), (2, 1)])
 @pytest.mark.parametrize("name,S", SIGMA_CASES)
 def test_hdiag_and_sigma_match_oracle(ws, name, S, variant, linked):
     P = PROBLEMS[name]()

@@ -149,6 +149,11 @@ def test_invalid_inputs_rejected():
         with pytest.raises(M.MBEFCIError):
             ctx.set_options(pspace=bad_psp)
     ctx.set_options(pspace=0)
+    for bad_lr in (-1, 4):
+        with pytest.raises(M.MBEFCIError):
+            ctx.set_options(linked_rows=bad_lr)
+    for lr in (0, 1, 2, 3):
+        ctx.set_options(linked_rows=lr)
 
 
 class _FakeTensor:
