@@ -448,19 +448,9 @@ static size_t linked_lds_res(const ParamLayout &pl, int64_t Na) {
     return sizeof(double) * ((size_t)(Na + 1) * kStrip + 4 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 4) * rl);
 }
 
-// The resident-A kernel (A rows in LDS, one eight-wave workgroup in two
-// halves) needs more LDS than the gathered-A kernel (four waves, A rows
-// loaded through the vector memory path, which they saturate); it is used
-// where that costs no occupancy: two of its workgroups fit a CU, or the
-// gathered-A kernel fits at most two.
-static bool linked_resident(const ParamLayout &pl, int64_t Na) {
-    const size_t res = linked_lds_res(pl, Na), gat = linked_lds_gat(pl, Na);
-    return res <= 160 * 1024 && (2 * res <= 160 * 1024 || 3 * gat > 160 * 1024);
-}
-
 bool linked_fits(const ParamLayout &pl, int64_t Na, int nel) {
     return pl.nA >= 4 && pl.nA <= kMaxActive && 1 + nel * (pl.nA - nel) <= kLinkedRows &&
-           (linked_resident(pl, Na) || linked_lds_gat(pl, Na) <= 160 * 1024) && Na < (1 << 24);
+           linked_lds_gat(pl, Na) <= 160 * 1024 && Na < (1 << 24);
 }
 
 // The per-tuple A table.  Row r holds twice the stored 1/2 (pq|rs) of pair
@@ -911,13 +901,32 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
     }
 }
 
+// The resident-A kernel (A rows in LDS, one eight-wave workgroup in two
+// halves) needs more LDS than the gathered-A kernel (four waves, A rows
+// loaded through the vector memory path, which they saturate, with a load
+// volume per string that grows as n_A^2).  It runs where it keeps at least as
+// many waves per CU as the gathered one (LDS and register occupancy) or n_A
+// >= 12, and there are at least as many alpha strings as pairs (its A rows
+// are staged once per strip): the faster of the two on every n_A = 9..13
+// class measured (n_alpha = n_beta = 2..5).
+template <int NA>
+static bool use_resident(const Batch &b) {
+    const size_t res = linked_lds_res(b.pl, b.Na), gat = linked_lds_gat(b.pl, b.Na);
+    const bool res_fits = res <= 160 * 1024, gat_fits = gat <= 160 * 1024;
+    if (b.linked_mode == 3) return res_fits;
+    if (b.linked_mode == 2 || !res_fits) return !gat_fits;
+    int nr = 0, ng = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nr, k_sigma_linked_res<NA>, 512, res) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&ng, k_sigma_linked_gat<NA>, 256, gat) != hipSuccess)
+        return false;
+    return (8 * nr >= 4 * ng || NA >= 12) && b.Na >= b.pl.P;
+}
+
 template <int NA>
 static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    const bool res_fits = linked_lds_res(b.pl, b.Na) <= 160 * 1024, gat_fits = linked_lds_gat(b.pl, b.Na) <= 160 * 1024;
-    const bool res = b.linked_mode == 3 ? res_fits : b.linked_mode == 2 ? !gat_fits : linked_resident(b.pl, b.Na);
-    if (res)
+    if (use_resident<NA>(b))
         hipLaunchKernelGGL(k_sigma_linked_res<NA>, grid, dim3(512), linked_lds_res(b.pl, b.Na), s, b, c, sig,
                            shift, skip);
     else
