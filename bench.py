@@ -24,7 +24,7 @@ METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |Î”E|â‰
 # HBM bytes per k_sigma_strip dispatch from the calibrated FETCH_SIZE / WRITE_SIZE
 # passes in profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md, valid only for
 # the strip kernel source they were taken on (kernels_sha1 below).
-TRAFFIC = {"kernels_sha1": "9d5fad88313fa1f46ea5bea990990a7ace0ef9ac", "bytes_per_launch": 806707181.6}
+TRAFFIC = {"kernels_sha1": "3723e1d0ccaf3826ecacd027923a1af76e66058c", "bytes_per_launch": 806788839.7}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
