@@ -77,7 +77,7 @@ struct Batch {
     const uint32_t *lrow, *lscat;
     double *la;
     int64_t la_stride;
-    const int32_t *lperm;   // [2 (lpairs + 5)] alpha strings in pairs (N_a: dummy)
+    const int32_t *lperm;   // [2 (lpairs + 8)] alpha strings in pairs (N_a: dummy)
     int lpairs;
     int linked_mode;        // 1: variant by occupancy, 2: gathered A, 3: resident A (where it fits)
     const int32_t *act;     // [B * nA] active orbitals (ascending)

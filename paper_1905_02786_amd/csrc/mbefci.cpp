@@ -28,14 +28,14 @@ struct Tables {
     std::vector<uint32_t> pairs;     // [nstr][P]: link of each string per pair, strip pair order
     std::vector<uint32_t> scat;      // [nstr + 1][P + 1]: scatter form for the strip kernel
     std::vector<uint32_t> lrow, lscat;   // [nstr + 1][32]: linked-row form (empty if the links need more slots)
-    std::vector<int32_t> lperm;          // [2 (lpairs + 5)]: string order of the linked-row kernel
+    std::vector<int32_t> lperm;          // [2 (lpairs + 8)]: string order of the linked-row kernel
     int lpairs = 0;
 };
 
 // Order of the alpha strings for the linked-row kernel: pairs of strings
 // that differ in at least three orbitals (then neither reaches the other,
 // nor a common string, by one replacement: they share no scatter target),
-// padded with the dummy index nstr, plus five dummy pairs at the end.
+// padded with the dummy index nstr, plus eight dummy pairs at the end.
 // Greedy, most constrained first: a pair starts with the unplaced string
 // that has the fewest unplaced compatible strings and takes the compatible
 // one with the fewest (lowest index on ties).
@@ -78,7 +78,7 @@ void pair_strings(Tables &T) {
         left -= b >= 0 ? 2 : 1;
     }
     T.lpairs = (int)(T.lperm.size() / 2);
-    T.lperm.resize(T.lperm.size() + 10, (int32_t)N);
+    T.lperm.resize(T.lperm.size() + 16, (int32_t)N);
 }
 
 // Strings with `nel` of `nA` bits set, ascending; for each string I the

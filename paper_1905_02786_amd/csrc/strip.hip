@@ -441,11 +441,12 @@ static size_t linked_lds_gat(const ParamLayout &pl, int64_t Na) {
     return sizeof(double) * ((size_t)(Na + 1) * kStrip + 2 * (size_t)pl.Kpad * kStrip);
 }
 
-// LDS: sigma strip [Na + 1][16], D of the two halves' pairs [2][2][Kpad][16],
-// the A rows [P][row length] and the two halves' staged diagonal sums [2][2].
+// LDS: sigma strip [Na + 1][16], D of the three thirds' pairs
+// [3][2][Kpad][16], the A rows [P][row length] and the thirds' staged
+// diagonal sums [3][2].
 static size_t linked_lds_res(const ParamLayout &pl, int64_t Na) {
     const size_t rl = (size_t)linked_row_len(pl.Kpad);
-    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 4 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 4) * rl);
+    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 6 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 6) * rl);
 }
 
 bool linked_fits(const ParamLayout &pl, int64_t Na, int nel) {
@@ -693,55 +694,56 @@ __global__ __launch_bounds__(256) void k_sigma_linked_gat(Batch b, VecRef cref, 
     }
 }
 
-// Resident-A kernel.  One workgroup of eight waves per (tuple, 16-column
-// strip), in two halves
-// of four (waves 0-3 and 4-7: one wave of each half per SIMD).  The alpha
-// strings are taken in pairs (lperm, host order: the two strings of a pair
-// differ in at least three orbitals, so they share no scatter target), and
-// pair q belongs to half q & 1.  Phase p (one barrier after each):
-//   * half p & 1 runs the MFMAs of pair p: wave 4x + 2g + h computes row
-//     tile h of string g of the pair, with its B operand from the pair's D
-//     tile and its A operand from the A rows held in LDS for the whole strip
-//     (the slot-0 lanes from the pair's staged diagonal sums);
-//   * the other half scatters its pair p - 1 from the MFMA registers, writes
-//     D and the diagonal sums of its pair p + 1 and issues the loads for its
-//     next phases (A-row offsets of pair p + 1, scatter entries of pair
-//     p + 1, C rows and diagonal sums of pair p + 3).
-// So on every SIMD one wave feeds the matrix pipe while the other does the
-// memory work, and the halves swap at each barrier.  One pair is scattered
-// per phase, in pair order, so every sigma entry gets its adds in a fixed
-// order.  Host tables per alpha string K, 32 slots each (row N_a: all
-// discard): lrow = byte offset of the slot's A row (slot 0, the diagonal
-// sum, is read from the staged row instead; unused slots row 0), lscat = byte
-// offset of its target row in the sigma strip (K for slot 0, the linked
-// string J for the others, the discard row N_a for unused slots), bit 31 the
-// alpha link sign, in the order of the MFMA output rows of a lane
-// (linked_scat_pos).  Dummy strings (index N_a) pad the last pair.
+// Resident-A kernel.  One workgroup of twelve waves per (tuple, 16-column
+// strip), in three thirds of four (waves 0-3, 4-7, 8-11: one wave of each
+// third per SIMD).  The alpha strings are taken in pairs (lperm, host order:
+// the two strings of a pair differ in at least three orbitals, so they share
+// no scatter target), and pair q belongs to third q % 3.  In phase p (one
+// barrier after each) third z does, by (p - z) mod 3:
+//   0. the MFMAs of pair p: wave 4z + 2g + h computes row tile h of string g
+//      of the pair, with its B operand from the pair's D tile and its A
+//      operand from the A rows held in LDS for the whole strip (the slot-0
+//      lanes from the pair's staged diagonal sums);
+//   1. the scatter of pair p - 1 from the MFMA registers, and the A-row
+//      offsets of its next pair p + 2;
+//   2. D and the diagonal sums of its next pair p + 1 (from values loaded
+//      three phases earlier), then the loads for the cycle after: C values
+//      and diagonal sums of pair p + 4, scatter entries of pair p + 1.
+// So on every SIMD one wave feeds the matrix pipe while two others share the
+// memory work of two phases; one pair is scattered per phase, in pair order,
+// so every sigma entry gets its adds in a fixed order.  Host tables per alpha
+// string K, 32 slots each (row N_a: all discard): lrow = byte offset of the
+// slot's A row (slot 0, the diagonal sum, is read from the staged row
+// instead; unused slots row 0), lscat = byte offset of its target row in the
+// sigma strip (K for slot 0, the linked string J for the others, the discard
+// row N_a for unused slots), bit 31 the alpha link sign, in the order of the
+// MFMA output rows of a lane (linked_scat_pos).  Dummy strings (index N_a)
+// pad the last pair and the pairs past it.
 template <int NA>
-__global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, VecRef sref, double shift,
-                                                      int skip_done) {
+__global__ __launch_bounds__(768) void k_sigma_linked_res(Batch b, VecRef cref, VecRef sref, double shift,
+                                                          int skip_done) {
     constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4;
     constexpr int RL = (KS + 1) / 2 * 8;                      // A-table row length (linked_row_len)
     constexpr uint32_t RLB = RL * sizeof(double);
     constexpr uint32_t DB = KP * kStrip * sizeof(double);     // bytes of one string's D
-    constexpr int NDI = (2 * KP * kStrip + 255) / 256;        // D items per thread of a half
+    constexpr int NDI = (2 * KP * kStrip + 255) / 256;        // D items per thread of a third
     const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
     int t, strip_id;
     if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
     if (skip_done && b.status[t] != ST_RUNNING) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int x = wu >> 2, lw = wu & 3, g = lw >> 1, h = lw & 1;   // half, wave in half, string, tile
-    const int th = tid & 255;                                      // thread in half
+    const int z = wu >> 2, lw = wu & 3, g = lw >> 1, h = lw & 1;   // third, wave in third, string, tile
+    const int th = tid & 255;                                      // thread in third
     const int ar = lane & 15, kr = lane >> 4;
     const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
     const uint32_t B0 = (uint32_t)strip_id * kStrip;
     const bool colok = B0 + ar < Nb;
     extern __shared__ double lds[];
     double *strip = lds;                                                // [Na + 1][16]
-    const uint32_t D0 = (Na + 1) * kStrip * (uint32_t)sizeof(double);   // D [2 halves][2][KP][16]
-    const uint32_t A0 = D0 + 4 * DB;                                    // A rows [P][RL]
-    const uint32_t G0 = A0 + P * RLB;                                   // diagonal sums [2 halves][2][RL]
+    const uint32_t D0 = (Na + 1) * kStrip * (uint32_t)sizeof(double);   // D [3 thirds][2][KP][16]
+    const uint32_t A0 = D0 + 6 * DB;                                    // A rows [P][RL]
+    const uint32_t G0 = A0 + P * RLB;                                   // diagonal sums [3 thirds][2][RL]
     const double *c = vref(cref, t, b.dim);
     double *sg = const_cast<double *>(vref(sref, t, b.dim));
     const int32_t *perm = b.lperm;
@@ -754,7 +756,7 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
                                                                         tbytes, 0x00020000);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lscat), (short)0,
                                                                         tbytes, 0x00020000);
-    // D items of a half: element j = th + 256 i of its D [2][KP][16] (string
+    // D items of a third: element j = th + 256 i of its D [2][KP][16] (string
     // j / (16 KP), row (j / 16) % KP, column ar).  A wave's 64 elements of an
     // item lie in one string (16 KP is a multiple of 64), so the string is
     // wave-uniform, and so is the presence of the last item.  Beta link of
@@ -792,7 +794,7 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
         for (int k = 0; k < 4; ++k) e[k] = v[k];
     };
     // diagonal sum of string s: 16 bytes per lane, lanes < RL / 2 of waves
-    // 2g of a half (one wave per string of the pair)
+    // 2g of a third (one wave per string of the pair)
     const bool dgl = h == 0 && lane < RL / 2;
     auto load_dg = [&](uint32_t s) -> dbl2v {
         const uint32_t r = (uint32_t)P + (s < Na ? s : 0u);
@@ -801,40 +803,39 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
     auto dval = [&](double v, int i) -> double {   // D entry: the C value with the beta link sign
         return __hiloint2double(__double2hiint(v) ^ (int)bsg[i], __double2loint(v));
     };
-    const uint32_t dw = D0 + (uint32_t)x * 2 * DB + (uint32_t)th * (uint32_t)sizeof(double);   // D element th of the half
-    const uint32_t dr = D0 + (uint32_t)(2 * x + g) * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
-    const uint32_t gd = G0 + (uint32_t)(2 * x + g) * RLB;                  // staged diagonal sum of string g
+    const uint32_t dw = D0 + (uint32_t)z * 2 * DB + (uint32_t)th * (uint32_t)sizeof(double);   // D element th of the third
+    const uint32_t dr = D0 + (uint32_t)(2 * z + g) * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
+    const uint32_t gd = G0 + (uint32_t)(2 * z + g) * RLB;                  // staged diagonal sum of string g
     const uint32_t gw = gd + (uint32_t)lane * 16u;
     const bool isdg = h == 0 && ar == 0;                                   // lanes of slot 0
     const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
 
-    // prologue: sigma strip zero, A rows into LDS, D and diagonal sums of
-    // pair 0; registers for the first phases of each half
-    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += 512) strip[i] = 0.0;
-    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 512)
+    // prologue: sigma strip zero, A rows into LDS; third 0: D and diagonal
+    // sums of pair 0; the registers of each third's first phases (third z
+    // prepares pair 3 if z = 0, else pair z)
+    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += 768) strip[i] = 0.0;
+    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 768)
         *reinterpret_cast<dbl2v *>(lds_at(A0 + 16u * i)) =
             __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * i, 0, 0));
-    if (x == 0) {
+    if (z == 0) {
 #pragma unroll
         for (int i = 0; i < NDI; ++i)
             if (item_on(i)) *lds_at(dw + 2048u * i) = dval(load_c(str(0, item_str(i)), i), i);
         if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = load_dg(str(0, g));
     }
-    // half 0 runs pair 0 in phase 0, scatters it and prepares pair 2 in phase
-    // 1; half 1 scatters nothing in phase 0 (pair -1: discard) and prepares
-    // pair 1
-    uint32_t ra = load_row(x == 0 ? str(0, g) : Na);
+    const uint32_t q0 = z == 0 ? 3u : (uint32_t)z;
+    uint32_t ra = load_row(z == 2 ? Na : str((uint32_t)z, g));
     uint32_t e[4];
-    load_scat(x == 0 ? str(0, g) : Na, e);
+    load_scat(z == 0 ? str(0, g) : Na, e);
     double cb[NDI];
 #pragma unroll
-    for (int i = 0; i < NDI; ++i) cb[i] = item_on(i) ? load_c(str(2 - x, item_str(i)), i) : 0.0;
+    for (int i = 0; i < NDI; ++i) cb[i] = item_on(i) ? load_c(str(q0, item_str(i)), i) : 0.0;
     dbl2v dg = {0.0, 0.0};
-    if (dgl) dg = load_dg(str(2 - x, g));
+    if (dgl) dg = load_dg(str(q0, g));
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     __syncthreads();
 
-    // the MFMAs of this half's pair (phase p = its pair)
+    // 0: the MFMAs of this third's pair
     auto mphase = [&]() {
         double bv[KS], af[KS];
 #pragma unroll
@@ -852,10 +853,9 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
         for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
         acc = a;
     };
-    // the memory work of this half in phase p: scatter of pair p - 1, D and
-    // diagonal sums of pair p + 1, loads
-    auto nphase = [&](uint32_t p) {
-        ra = load_row(str(p + 1, g));
+    // 1 (phase p): scatter of pair p - 1, A-row offsets of pair p + 2
+    auto n1phase = [&](uint32_t p) {
+        ra = load_row(str(p + 2, g));
         // target row e & 0x7FFFFFFF (a multiple of 128 bytes), column ar, link
         // sign in bit 31; the add is done by the LDS unit (the strip starts the
         // dynamic LDS block at address 0: the kernel has no static LDS, checked
@@ -865,34 +865,52 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
             __builtin_amdgcn_ds_atomic_fadd_f64(
                 (__attribute__((address_space(3))) double *)(uintptr_t)((e[v] & 0x7FFFFFFFu) | ar8),
                 __hiloint2double(__double2hiint(acc[v]) ^ (int)(e[v] & kPairSign), __double2loint(acc[v])));
-        load_scat(str(p + 1, g), e);
+    };
+    // 2 (phase p): D and diagonal sums of pair p + 1; loads of pair p + 4 and
+    // of the scatter entries of pair p + 1
+    auto n2phase = [&](uint32_t p) {
 #pragma unroll
         for (int i = 0; i < NDI; ++i)
             if (item_on(i)) *lds_at(dw + 2048u * i) = dval(cb[i], i);
         if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = dg;
+        load_scat(str(p + 1, g), e);
 #pragma unroll
         for (int i = 0; i < NDI; ++i)
-            if (item_on(i)) cb[i] = load_c(str(p + 3, item_str(i)), i);
-        if (dgl) dg = load_dg(str(p + 3, g));
+            if (item_on(i)) cb[i] = load_c(str(p + 4, item_str(i)), i);
+        if (dgl) dg = load_dg(str(p + 4, g));
     };
-    // one loop per half (straight-line bodies, the same number of barriers)
-    const uint32_t nph = (uint32_t)b.lpairs + 1;   // the last pair is scattered in phase lpairs
-    if (x == 0) {
-        for (uint32_t p = 0; p < nph; p += 2) {
+    // one loop per third (straight-line bodies, three barriers each); phases
+    // 0 .. 3k - 1 cover the last pair's scatter in phase lpairs
+    const uint32_t nph = (uint32_t)b.lpairs + 1;
+    if (z == 0) {
+        for (uint32_t p = 0; p < nph; p += 3) {
             mphase();
             __syncthreads();
-            nphase(p + 1);
+            n1phase(p + 1);
+            __syncthreads();
+            n2phase(p + 2);
+            __syncthreads();
+        }
+    } else if (z == 1) {
+        for (uint32_t p = 0; p < nph; p += 3) {
+            n2phase(p);
+            __syncthreads();
+            mphase();
+            __syncthreads();
+            n1phase(p + 2);
             __syncthreads();
         }
     } else {
-        for (uint32_t p = 0; p < nph; p += 2) {
-            nphase(p);
+        for (uint32_t p = 0; p < nph; p += 3) {
+            n1phase(p);
+            __syncthreads();
+            n2phase(p + 1);
             __syncthreads();
             mphase();
             __syncthreads();
         }
     }
-    for (uint32_t i = tid; i < Na * kStrip; i += 512) {
+    for (uint32_t i = tid; i < Na * kStrip; i += 768) {
         const uint32_t row = i / kStrip, col = i % kStrip;
         if (B0 + col < Nb) {
             const uint32_t d = row * Nb + B0 + col;
@@ -901,33 +919,26 @@ __global__ __launch_bounds__(512) void k_sigma_linked_res(Batch b, VecRef cref, 
     }
 }
 
-// The resident-A kernel (A rows in LDS, one eight-wave workgroup in two
-// halves) needs more LDS than the gathered-A kernel (four waves, A rows
-// loaded through the vector memory path, which they saturate, with a load
-// volume per string that grows as n_A^2).  It runs where it keeps at least as
-// many waves per CU as the gathered one (LDS and register occupancy) or n_A
-// >= 12, and there are at least as many alpha strings as pairs (its A rows
-// are staged once per strip): the faster of the two on every n_A = 9..13
-// class measured (n_alpha = n_beta = 2..5).
-template <int NA>
+// The resident-A kernel (A rows in LDS, one twelve-wave workgroup in three
+// thirds) needs more LDS than the gathered-A kernel (four waves, A rows
+// loaded through the vector memory path, which they saturate).  It runs
+// wherever it fits and there are at least as many alpha strings as pairs (its
+// A rows are staged once per strip): the faster of the two, or within 1 %,
+// on every n_A = 9..13 class measured.
 static bool use_resident(const Batch &b) {
-    const size_t res = linked_lds_res(b.pl, b.Na), gat = linked_lds_gat(b.pl, b.Na);
-    const bool res_fits = res <= 160 * 1024, gat_fits = gat <= 160 * 1024;
+    const bool res_fits = linked_lds_res(b.pl, b.Na) <= 160 * 1024,
+               gat_fits = linked_lds_gat(b.pl, b.Na) <= 160 * 1024;
     if (b.linked_mode == 3) return res_fits;
     if (b.linked_mode == 2 || !res_fits) return !gat_fits;
-    int nr = 0, ng = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nr, k_sigma_linked_res<NA>, 512, res) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&ng, k_sigma_linked_gat<NA>, 256, gat) != hipSuccess)
-        return false;
-    return (8 * nr >= 4 * ng || NA >= 12) && b.Na >= b.pl.P;
+    return b.Na >= b.pl.P;
 }
 
 template <int NA>
 static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    if (use_resident<NA>(b))
-        hipLaunchKernelGGL(k_sigma_linked_res<NA>, grid, dim3(512), linked_lds_res(b.pl, b.Na), s, b, c, sig,
+    if (use_resident(b))
+        hipLaunchKernelGGL(k_sigma_linked_res<NA>, grid, dim3(768), linked_lds_res(b.pl, b.Na), s, b, c, sig,
                            shift, skip);
     else
         hipLaunchKernelGGL(k_sigma_linked_gat<NA>, grid, dim3(256), linked_lds_gat(b.pl, b.Na), s, b, c, sig,
