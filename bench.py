@@ -197,7 +197,8 @@ def main():
         "sigma": {"gflops_contraction_kernel": achieved * 1e3, "gflops_sigma_all_kernels": sigma_gflops_all,
                   "applications": st["sigma_calls"], "launches": st["sigma_launches"],
                   "algorithmic_flops_per_step": st["sigma_flops"]},
-        "davidson": {"iterations_total": st["iterations_total"], "iterations_max": st["iterations_max"]},
+        "davidson": {"iterations_total": st["iterations_total"], "iterations_max": st["iterations_max"],
+                     "gs_second_pass": st["gs_second_pass"]},
         "per_order_ms": [o.wall_ms for o in res.orders],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS,

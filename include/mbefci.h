@@ -122,6 +122,8 @@ typedef struct {
     int64_t iterations_total;   /* Davidson iterations summed over tuples */
     int64_t iterations_max;
     double solve_ms;            /* host wall time inside solve/run */
+    int64_t gs_second_pass;     /* Davidson corrections that took two explicit Gram-Schmidt passes (the
+                                   rest join the subspace unchanged: it keeps V = Q U, U triangular) */
 } mbefci_stats;
 
 /* Library version string. */

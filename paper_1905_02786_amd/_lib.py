@@ -27,7 +27,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("ntuples", c_int64), ("sigma_calls", c_int64), ("sigma_launches", c_int64),
                 ("sigma_flops", c_double), ("sigma_bytes", c_double), ("sigma_ms", c_double),
                 ("sigma_total_ms", c_double), ("iterations_total", c_int64),
-                ("iterations_max", c_int64), ("solve_ms", c_double)]
+                ("iterations_max", c_int64), ("solve_ms", c_double),
+                ("gs_second_pass", c_int64)]
 
 
 ENERGY_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int64, ctypes.POINTER(ctypes.c_int16),

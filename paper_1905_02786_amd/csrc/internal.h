@@ -87,14 +87,18 @@ struct Batch {
     int max_space, max_iter;
     double e_tol, r_tol;
     double *V, *S;          // [B][max_space][dim]
-    double *Hd, *T;         // [B][dim]
+    double *Hd, *T;         // [B][dim]; T: the Ritz vector for the RDMs
     int sigma_variant;      // SIGMA_STRIP or SIGMA_WMAT
     double *W;              // [B][P][dim] sigma intermediate (SIGMA_WMAT)
     double *Ha, *Hb;        // [B][Na][Na], [B][Nb][Nb] string Hamiltonians (SIGMA_STRIP; Ha == Hb when na == nb)
     int nblk;               // blocks per tuple for vector kernels
     double *part;           // [B][nblk + 1][kParts] block partial sums (the last block: P-space corrections)
-    double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix
-    double *y, *coef;       // [B][kMaxSpace]
+    double *G;              // [B][kMaxSpace*kMaxSpace] projected matrix V^T H V of the stored basis
+    // The stored basis V is not orthonormal: V = Q U with Q orthonormal and U
+    // upper triangular; R = U^-1 (upper triangular, R[i][j] at i*kMaxSpace+j,
+    // entries j >= i used), so Q = V R
+    double *R;              // [B][kMaxSpace*kMaxSpace]
+    double *y, *coef;       // [B][kMaxSpace]; y: Ritz coefficients on the stored basis V
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
     int32_t *status, *m, *iter, *restart, *out_status; // [B]
     int32_t *cgs2;          // [B] correction needs a second Gram-Schmidt pass
@@ -105,7 +109,7 @@ struct Batch {
     double *pQ;             // [B][kPsp][kPsp] H_PP, then Q
     double *pQt;            // [B][kPsp][kPsp] Q transposed (coalesced reads of Q w)
     double *pT;             // [B][3][kPsp] diagonal, subdiagonal of T, lowest eigenvector of H_PP
-    int32_t *counter;       // [1] running tuples
+    int32_t *counter;       // [2] running tuples, tuples whose correction needs the explicit passes
     // RDM pass (backward): Gram partials and sums
     int nblk_r;
     double *rdm_part;       // [B][nblk_r][NP*NP]

@@ -541,7 +541,8 @@ __global__ __launch_bounds__(kPsp) void k_psp_guess(Batch b) {
 // After k_ritz: T on the P determinants <- (theta - H_PP)^-1 r_P, solved as
 // Q (theta - T)^-1 Q^T r_P (Thomas, pivots kept away from zero like the
 // diagonal preconditioner); the changes of |T|^2 and of the projections
-// V_i . T (x . T on restart) go to the extra partial block.
+// V_i . T (x . T on restart) go to the extra partial block.  T is the vector
+// k_ritz wrote, V_m (V_1 on restart).
 template <int MS>
 __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     const int t = blockIdx.x, i = threadIdx.x, n = b.psp;
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     const double *yy = b.y + (int64_t)t * kMaxSpace;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     const double *S = b.S + (int64_t)t * b.max_space * b.dim;
-    double *T = b.T + (int64_t)t * b.dim;
+    double *T = b.V + ((int64_t)t * b.max_space + (rs ? 1 : m)) * b.dim;
     const double *Q = b.pQ + (int64_t)t * kPsp * kPsp, *Qt = b.pQt + (int64_t)t * kPsp * kPsp;
     const double *dT = b.pT + (int64_t)t * 3 * kPsp, *eT = dT + kPsp;
     __shared__ double r[kPsp], w[kPsp], cp[kPsp], red[2][MS + 2];
@@ -727,6 +728,7 @@ __global__ void k_init_state(Batch b) {
     b.restart[t] = 0;
     b.theta[t] = 0.0;
     b.theta_prev[t] = 1e300;
+    b.R[(int64_t)t * kMaxSpace * kMaxSpace] = 1.0;   // V_0 is normalised: Q_0 = V_0
 }
 
 hipError_t launch_init_state(const Batch &b, hipStream_t s) {
@@ -786,6 +788,9 @@ hipError_t launch_update_G(const Batch &b, int nsum, hipStream_t s) {
 
 // Lowest eigenpair of the m x m projected matrix by cyclic Jacobi with a
 // parallel (round-robin) rotation order; one block of 64 threads per tuple.
+// The Jacobi matrix is the projection on the orthonormal basis Q = V R,
+// R^T G R (upper triangle computed, mirrored); its eigenvector y becomes the
+// coefficients R y on the stored basis.
 __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     const int t = blockIdx.x;
     const int32_t st0 = b.status[t];
@@ -796,14 +801,39 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     const int mm = m + (m & 1);                  // even number of players
     __shared__ double A[kMaxSpace + 1][kMaxSpace + 2];
     __shared__ double Vv[kMaxSpace + 1][kMaxSpace + 2];
+    __shared__ double Rs[kMaxSpace][kMaxSpace + 1];
     __shared__ double cs[(kMaxSpace + 2) / 2], sn[(kMaxSpace + 2) / 2];
     __shared__ int pa[(kMaxSpace + 2) / 2], pb[(kMaxSpace + 2) / 2];
     __shared__ int done;
     const int tid = threadIdx.x;
     const double *G = b.G + (int64_t)t * kMaxSpace * kMaxSpace;
+    const double *Rg = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
+    // Rs = R (upper triangle, zero below), Vv = G R, then A = R^T (G R)
+    for (int i = tid; i < m * m; i += 64) {
+        const int r = i / m, c = i % m;
+        Rs[r][c] = (r <= c) ? Rg[r * kMaxSpace + c] : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < m * m; i += 64) {
+        const int r = i / m, c = i % m;
+        double v = 0.0;
+        for (int k = 0; k <= c; ++k) v += G[r * kMaxSpace + k] * Rs[k][c];
+        Vv[r][c] = v;
+    }
+    __syncthreads();
     for (int i = tid; i < mm * mm; i += 64) {
         const int r = i / mm, c = i % mm;
-        A[r][c] = (r < m && c < m) ? G[r * kMaxSpace + c] : 0.0;
+        if (r <= c) {
+            double v = 0.0;
+            if (c < m)
+                for (int k = 0; k <= r; ++k) v += Rs[k][r] * Vv[k][c];
+            A[r][c] = v;
+            A[c][r] = v;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < mm * mm; i += 64) {
+        const int r = i / mm, c = i % mm;
         Vv[r][c] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -881,15 +911,21 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
             if (A[i][i] < A[k][k]) k = i;
         b.theta[t] = A[k][k];
         double *y = b.y + (int64_t)t * kMaxSpace;
-        for (int i = 0; i < m; ++i) y[i] = Vv[i][k];
+        for (int i = 0; i < m; ++i) {
+            double v = 0.0;
+            for (int j = i; j < m; ++j) v += Rs[i][j] * Vv[j][k];
+            y[i] = v;
+        }
         b.restart[t] = (m >= b.max_space || st0 == ST_RESTART) ? 1 : 0;
     }
 }
 
 // x = V y, Ax = S y, r = Ax - theta x, T = r / (theta - Hd) (clamped);
-// partials |r|^2, |T|^2 and the first Gram-Schmidt projections V_i . T of the
-// subspace the correction is added to (V_i, i < m, or x alone on restart).
-// On restart, V_0 <- x and S_0 <- Ax in place (each thread owns its d).
+// partials |r|^2, |T|^2 and the projections V_i . T on the subspace the
+// correction is added to (V_i, i < m, or x alone on restart).  T is stored as
+// the next basis vector itself: V_m, or V_1 on restart, where V_0 <- x and
+// S_0 <- Ax in place (each thread owns its d and reads every vector there
+// before it writes).
 template <int MS, bool V2>
 __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     const int t = blockIdx.y;
@@ -903,7 +939,7 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     double *V = b.V + (int64_t)t * b.max_space * b.dim;
     double *S = b.S + (int64_t)t * b.max_space * b.dim;
     const double *hd = b.Hd + (int64_t)t * b.dim;
-    double *T = b.T + (int64_t)t * b.dim;
+    double *T = V + (int64_t)(rs ? 1 : m) * b.dim;
     double acc[MS + 2];
 #pragma unroll
     for (int i = 0; i < MS + 2; ++i) acc[i] = 0.0;
@@ -1008,42 +1044,58 @@ __global__ void k_converge(Batch b) {
     if (b.restart[t]) {   // V_0 = x, S_0 = A x already: the subspace is {x} whatever the outcome
         b.m[t] = 1;
         b.G[(int64_t)t * kMaxSpace * kMaxSpace] = th;
+        b.R[(int64_t)t * kMaxSpace * kMaxSpace] = 1.0;   // x = Q y has unit norm
         b.y[(int64_t)t * kMaxSpace] = 1.0;
     }
     b.status[t] = st;
     if (st == ST_RUNNING) atomicAdd(b.counter, 1);
 }
 
-// Projection coefficients c_i of the first Gram-Schmidt pass (partials
-// 2..m+1 of k_ritz), and the norm that pass keeps, |T|^2 - sum c_i^2.  One
-// pass suffices when it keeps at least 1/sqrt(2) of the norm (Kahan's
-// criterion; the difference of squares is then accurate to a few ulps): the
-// pass writes V_m = (T - sum c_i V_i) / norm directly (scale in
-// coef[kMaxSpace - 1], never a coefficient since m < max_space <= kMaxSpace).
-// Otherwise cgs2 is set and the second pass and k_tnorm decide.  One block of
-// 64 threads per tuple.
+// The correction T = V_m on the orthonormal basis: c = Q^T T = R^T d with d
+// the projections V_i . T (partials 2..m+1 of k_ritz), and the norm outside
+// the subspace, kept = |T|^2 - |c|^2.  When that keeps at least half of
+// |T|^2 (Kahan's criterion for one classical Gram-Schmidt pass; the
+// difference of squares is then accurate to a few ulps) T joins the basis
+// unchanged: V = Q U gains the column (c, sqrt(kept)), so R = U^-1 gains
+// (-R c, 1) / sqrt(kept), and no vector pass is needed.  Otherwise cgs2 is set,
+// coef = R c (T - V R c is T's part outside the subspace) and the explicit
+// second pass and k_tnorm decide.  One block of 64 threads (one wave) per
+// tuple; every lane takes the same decision (the butterfly sums are equal in
+// every lane).
 __global__ void k_coef1(Batch b) {
     const int t = blockIdx.x;
     if (b.status[t] != ST_RUNNING) return;
-    const int m = b.m[t];
+    const int m = b.m[t], i = threadIdx.x;
+    double *R = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
+    __shared__ double dv[kMaxSpace], cv[kMaxSpace];
+    if (i < m) dv[i] = sum_parts_x(b, t, 2 + i);
+    __syncthreads();
     double c = 0.0;
-    if ((int)threadIdx.x < m) {
-        c = sum_parts_x(b, t, 2 + threadIdx.x);
-        b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = c;
+    if (i < m) {
+        for (int j = 0; j <= i; ++j) c += R[j * kMaxSpace + i] * dv[j];
+        cv[i] = c;
     }
     const double c2 = wave_sum(c * c);
-    if (threadIdx.x == 0) {
-        const double t2 = b.tnorm0[t] * b.tnorm0[t];
-        const double kept = t2 - c2;
-        const int two = !(kept >= 0.5 * t2);
-        b.cgs2[t] = two;
-        if (!two) {
-            if (!(kept > 1e-300) || m >= b.max_space)
-                b.status[t] = b.rnorm[t] < b.r_tol ? ST_DONE : (m > 1 ? ST_RESTART : ST_STALLED);
-            else
-                b.coef[(int64_t)t * kMaxSpace + kMaxSpace - 1] = 1.0 / sqrt(kept);
-        }
+    __syncthreads();
+    double a = 0.0;   // (R c)_i
+    if (i < m)
+        for (int j = i; j < m; ++j) a += R[i * kMaxSpace + j] * cv[j];
+    const double t2 = b.tnorm0[t] * b.tnorm0[t];
+    const double kept = t2 - c2;
+    const int two = !(kept >= 0.5 * t2);
+    if (i == 0) b.cgs2[t] = two;
+    if (two) {
+        if (i < m) b.coef[(int64_t)t * kMaxSpace + i] = a;
+        if (i == 0) atomicAdd(b.counter + 1, 1);   // the host launches the explicit passes only if some tuple needs them
+        return;
     }
+    if (!(kept > 1e-300) || m >= b.max_space) {
+        if (i == 0) b.status[t] = b.rnorm[t] < b.r_tol ? ST_DONE : (m > 1 ? ST_RESTART : ST_STALLED);
+        return;
+    }
+    const double s = 1.0 / sqrt(kept);
+    if (i < m) R[i * kMaxSpace + m] = -a * s;
+    if (i == m) R[m * kMaxSpace + m] = s;
 }
 
 hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
@@ -1065,30 +1117,42 @@ hipError_t launch_iter_head(const Batch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-// coef[i] = sum of partials i (projection coefficients of the second pass)
+// Coefficients of the second pass on the stored basis, coef = R R^T d with
+// d_i = V_i . T the sums of partials i.  One block of 64 threads per tuple.
 __global__ void k_coef(Batch b) {
     const int t = blockIdx.x;
     if (b.status[t] != ST_RUNNING || !b.cgs2[t]) return;
-    const int m = b.m[t];
-    if ((int)threadIdx.x < m) b.coef[(int64_t)t * kMaxSpace + threadIdx.x] = sum_parts(b, t, threadIdx.x);
+    const int m = b.m[t], i = threadIdx.x;
+    const double *R = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
+    __shared__ double dv[kMaxSpace], cv[kMaxSpace];
+    if (i < m) dv[i] = sum_parts(b, t, i);
+    __syncthreads();
+    if (i < m) {
+        double c = 0.0;
+        for (int j = 0; j <= i; ++j) c += R[j * kMaxSpace + i] * dv[j];
+        cv[i] = c;
+    }
+    __syncthreads();
+    if (i < m) {
+        double a = 0.0;
+        for (int j = i; j < m; ++j) a += R[i * kMaxSpace + j] * cv[j];
+        b.coef[(int64_t)t * kMaxSpace + i] = a;
+    }
 }
 
-// T -= sum_i coef_i V_i, partial |T|^2 (second pass: flagged tuples only)
+// T -= sum_i coef_i V_i in place (T = V_m; tuples whose correction needs the
+// explicit passes only), and on the second pass the partial |T|^2
 template <int MS, bool V2>
-__global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
+__global__ __launch_bounds__(256) void k_axpy(Batch b, int second) {
     const int t = blockIdx.y;
-    if (b.status[t] != ST_RUNNING || (only2 && !b.cgs2[t])) return;
+    if (b.status[t] != ST_RUNNING || !b.cgs2[t]) return;
     const int m = b.m[t];
     double cf[MS];
     const double *cp = b.coef + (int64_t)t * kMaxSpace;
 #pragma unroll
     for (int i = 0; i < MS; ++i) cf[i] = (i < m) ? cp[i] : 0.0;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
-    double *T = b.T + (int64_t)t * b.dim;
-    // first pass of a one-pass tuple: the result goes scaled into V_m
-    const bool direct = !only2 && !b.cgs2[t];
-    const double sc = direct ? b.coef[(int64_t)t * kMaxSpace + kMaxSpace - 1] : 1.0;
-    double *out = direct ? b.V + ((int64_t)t * b.max_space + m) * b.dim : T;
+    double *T = b.V + ((int64_t)t * b.max_space + m) * b.dim;
     double acc[1];
     acc[0] = 0.0;
     // V_i, i < m, through a buffer resource that ends after vector m - 1 (the
@@ -1113,7 +1177,7 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
                 v.x -= cf[i] * vv[i].x;
                 v.y -= cf[i] * vv[i].y;
             }
-            *reinterpret_cast<dbl2 *>(out + d) = dbl2{v.x * sc, v.y * sc};
+            *reinterpret_cast<dbl2 *>(T + d) = v;
             acc[0] += v.x * v.x;
             acc[0] += v.y * v.y;
         }
@@ -1127,14 +1191,15 @@ __global__ __launch_bounds__(256) void k_axpy(Batch b, int only2) {
             double v = T[d];
 #pragma unroll
             for (int i = 0; i < MS; ++i) v -= cf[i] * vd[i];
-            out[d] = v * sc;
+            T[d] = v;
             acc[0] += v * v;
         }
     }
-    if (only2) store_block_partials<1>(b, t, acc, 1);   // |T|^2 after the second pass, for k_tnorm
+    if (second) store_block_partials<1>(b, t, acc, 1);   // |T|^2 after the second pass, for k_tnorm
 }
 
-// 1/|T| into coef[0].  A correction that lies inside the subspace (its
+// 1/|T| into coef[0] and the column of R for V_m = T/|T| (orthogonal to the
+// subspace: R gains the unit column).  A correction that lies inside the subspace (its
 // projection kept less than 1e-8 of its norm) adds nothing: the Ritz pair is
 // converged if the residual is below r_tol (an invariant subspace, e.g. a
 // one-determinant space); otherwise the tuple skips this expansion and
@@ -1149,15 +1214,19 @@ __global__ void k_tnorm(Batch b) {
         return;
     }
     b.coef[(int64_t)t * kMaxSpace] = 1.0 / tn;
+    const int m = b.m[t];
+    double *R = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
+    for (int i = 0; i < m; ++i) R[i * kMaxSpace + m] = 0.0;
+    R[m * kMaxSpace + m] = 1.0;
 }
 
-// V_m = T / |T| (tuples that took the second pass)
+// V_m <- V_m / |V_m| in place (tuples that took the second pass)
 __global__ __launch_bounds__(256) void k_store_t(Batch b) {
     const int t = blockIdx.y;
     if (b.status[t] != ST_RUNNING || !b.cgs2[t]) return;
     const double s = b.coef[(int64_t)t * kMaxSpace];
     double *vm = b.V + ((int64_t)t * b.max_space + b.m[t]) * b.dim;
-    const double *T = b.T + (int64_t)t * b.dim;
+    const double *T = vm;
     if ((b.dim & 1) == 0) {   // 16-byte pairs (every vector 16-byte aligned)
         typedef double dbl2 __attribute__((ext_vector_type(2)));
         for (int64_t d2 = (int64_t)blockIdx.x * 256 + threadIdx.x; d2 < (b.dim >> 1); d2 += (int64_t)gridDim.x * 256) {
@@ -1170,20 +1239,21 @@ __global__ __launch_bounds__(256) void k_store_t(Batch b) {
     }
 }
 
-// Classical Gram-Schmidt of T against V_0..V_{m-1} (a second pass where the
-// first lost too much of the norm), then V_m = T/|T|.
+// Tuples whose correction T = V_m lies too close to the subspace: two passes
+// of classical Gram-Schmidt of T against V_0..V_{m-1} (coefficients on the
+// stored basis), then V_m = T/|T|.  Every other tuple returns at once.
 hipError_t launch_orthonormalize(const Batch &b, hipStream_t s) {
     const dim3 grid(b.nblk, b.B);
-    VecRef tr{b.T, b.dim, nullptr, 0};
+    VecRef tr{b.V, (int64_t)b.max_space * b.dim, b.m, 0};
     // first pass: projections from k_ritz, coefficients from k_coef1
     const bool small = b.max_space <= 12, v2 = (b.dim & 1) == 0;
-    auto axpy = [&](int only2) {
+    auto axpy = [&](int second) {
         if (small) {
-            if (v2) hipLaunchKernelGGL((k_axpy<12, true>), grid, dim3(256), 0, s, b, only2);
-            else hipLaunchKernelGGL((k_axpy<12, false>), grid, dim3(256), 0, s, b, only2);
+            if (v2) hipLaunchKernelGGL((k_axpy<12, true>), grid, dim3(256), 0, s, b, second);
+            else hipLaunchKernelGGL((k_axpy<12, false>), grid, dim3(256), 0, s, b, second);
         } else {
-            if (v2) hipLaunchKernelGGL((k_axpy<kMaxSpace, true>), grid, dim3(256), 0, s, b, only2);
-            else hipLaunchKernelGGL((k_axpy<kMaxSpace, false>), grid, dim3(256), 0, s, b, only2);
+            if (v2) hipLaunchKernelGGL((k_axpy<kMaxSpace, true>), grid, dim3(256), 0, s, b, second);
+            else hipLaunchKernelGGL((k_axpy<kMaxSpace, false>), grid, dim3(256), 0, s, b, second);
         }
     };
     axpy(0);

@@ -368,7 +368,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
     if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP;  // RDM Gram partials and sum
-    pt += 8 * (size_t)(kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 7;
+    pt += 8 * (size_t)(2 * kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 7;
     cp.per_tuple = pt + 256;
 }
 
@@ -464,6 +464,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.pQ = b.pQt = b.pT = nullptr;
     }
     b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
+    b.R = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.y = cv.take<double>((size_t)B * kMaxSpace);
     b.coef = cv.take<double>((size_t)B * kMaxSpace);
     b.theta = cv.take<double>(B);
@@ -477,7 +478,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.restart = cv.take<int32_t>(B);
     b.out_status = cv.take<int32_t>(B);
     b.cgs2 = cv.take<int32_t>(B);
-    b.counter = cv.take<int32_t>(1);
+    b.counter = cv.take<int32_t>(2);
     b.nblk_r = cp.nblk_r;
     if (cp.rdm) {
         b.rdm_part = cv.take<double>((size_t)B * cp.nblk_r * cp.NP * cp.NP);
@@ -586,18 +587,20 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     };
     mbefci_status rc = sigma_and_G(b.B);
     if (rc != MBEFCI_OK) return rc;
-    int32_t running = b.B;
+    int32_t cnt[2] = {b.B, 0};   // running tuples; those of them that need the explicit Gram-Schmidt passes
     int iters = 0;
     for (int it = 0; it <= b.max_iter; ++it) {
-        HIPCHK(hipMemsetAsync(b.counter, 0, sizeof(int32_t), s));
+        HIPCHK(hipMemsetAsync(b.counter, 0, 2 * sizeof(int32_t), s));
         if ((e = launch_iter_head(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-        HIPCHK(hipMemcpyAsync(&running, b.counter, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(cnt, b.counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         flush_sigma_time(ctx);
         ++iters;
-        if (running == 0) break;
-        if ((e = launch_orthonormalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-        rc = sigma_and_G(running);
+        if (cnt[0] == 0) break;
+        ctx->stats.gs_second_pass += cnt[1];
+        if (cnt[1] > 0 && (e = launch_orthonormalize(b, s)) != hipSuccess)
+            return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        rc = sigma_and_G(cnt[0]);
         if (rc != MBEFCI_OK) return rc;
     }
     if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
