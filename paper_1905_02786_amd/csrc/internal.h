@@ -101,7 +101,7 @@ struct Batch {
     double *y, *coef;       // [B][kMaxSpace]; y: Ritz coefficients on the stored basis V
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
     int32_t *status, *m, *iter, *restart, *out_status; // [B]
-    int32_t *cgs2;          // [B] correction needs a second Gram-Schmidt pass
+    int32_t *cgs2;          // [B] correction takes two explicit Gram-Schmidt passes
     // P-space preconditioner: the psp determinants of lowest diagonal energy
     // (0: diagonal preconditioner only); H_PP = Q T Q^T with T tridiagonal
     int psp;

@@ -381,14 +381,20 @@ __global__ __launch_bounds__(256) void k_psp_factor(Batch b) {
         const double inv = 1.0 / sqrt(vn2);
         for (int i = tid; i < m; i += 256) v[i * LD] = (i == 0 ? v0 : v[i * LD]) * inv;
         __syncthreads();
-        // p = B v (B symmetric, lower triangle stored)
-        for (int i = tid; i < m; i += 256) {
+        // p = B v (B symmetric, lower triangle stored): row i by threads i and
+        // i + 128, one half of the columns each (the same trip count on every
+        // lane), the halves added in a fixed order
+        {
+            const int i = tid & 127, hf = tid >> 7, jh = (m + 1) >> 1;
             double acc = 0.0;
+            if (i < m) {
+                const int j0 = hf ? jh : 0, j1 = hf ? m : jh;
 #pragma unroll 8
-            for (int j = 0; j <= i; ++j) acc += B[i * LD + j] * v[j * LD];
-#pragma unroll 8
-            for (int j = i + 1; j < m; ++j) acc += B[j * LD + i] * v[j * LD];
-            vec[i] = acc;
+                for (int j = j0; j < j1; ++j) acc += B[j <= i ? i * LD + j : j * LD + i] * v[j * LD];
+            }
+            if (hf && i < m) cpv[i] = acc;
+            __syncthreads();
+            if (!hf && i < m) vec[i] = acc + cpv[i];
         }
         __syncthreads();
         part = 0.0;
@@ -407,27 +413,42 @@ __global__ __launch_bounds__(256) void k_psp_factor(Batch b) {
     for (int i = tid; i < n; i += 256) dT[i] = A[i * LD + i];
     if (tid == 0 && n >= 2) eT[n - 2] = A[(n - 1) * LD + n - 2];
     if (tid == 0) eT[n - 1] = 0.0;
-    // Householder vectors to global (strictly below the subdiagonal band's
-    // first column entry, i.e. rows i > j for columns j < n - 2)
-    for (int i = wv; i < n; i += 4)
-        for (int j = lane; j < n; j += 64) gQ[i * kPsp + j] = (j + 2 < n && i > j) ? A[i * LD + j] : 0.0;
     __syncthreads();
-    for (int i = wv; i < n; i += 4)
-        for (int j = lane; j < n; j += 64) A[i * LD + j] = (i == j) ? 1.0 : 0.0;
+    // Q = H_0 ... H_{n-3}, applied right to left to I and formed in place:
+    // before H_k only rows and columns > k differ from I, and reflector k
+    // lies in column k below the diagonal, outside that block; once H_k is
+    // applied, row and column k become those of I.  The block starts as the
+    // identity on rows and columns >= n - 2.
+    for (int i = tid; i < 4; i += 256) {
+        const int r = n - 2 + (i >> 1), c = n - 2 + (i & 1);
+        if (r >= 0 && c >= 0) A[r * LD + c] = (r == c) ? 1.0 : 0.0;
+    }
     __syncthreads();
-    // Q = H_0 ... H_{n-3}, applied right to left to I; before H_k only rows
-    // and columns > k differ from I
     for (int k = n - 3; k >= 0; --k) {
-        const int m = n - k - 1;
-        for (int i = tid; i < m; i += 256) vec[i] = gQ[(k + 1 + i) * kPsp + k];
+        const int m = n - k - 1, rh = (m + 1) >> 1;
+        const double *v = A + (k + 1) * LD + k;   // v[r * LD], r < m
+        // column c of the block by threads c and c + 128 (halves of the rows):
+        // a_c = 2 v . Q[:, c], then Q[:, c] -= a_c v
+        const int ci = tid & 127, hf = tid >> 7, c = k + 1 + ci;
+        const int r0 = hf ? rh : 0, r1 = hf ? m : rh;
+        double acc = 0.0;
+        if (c < n) {
+#pragma unroll 8
+            for (int r = r0; r < r1; ++r) acc += v[r * LD] * A[(k + 1 + r) * LD + c];
+        }
+        if (hf && c < n) cpv[ci] = acc;
         __syncthreads();
-        for (int c = k + 1 + tid; c < n; c += 256) {
-            double acc = 0.0;
+        if (!hf && c < n) vec[ci] = acc + cpv[ci];
+        __syncthreads();
+        if (c < n) {
+            const double a = 2.0 * vec[ci];
 #pragma unroll 8
-            for (int r = 0; r < m; ++r) acc += vec[r] * A[(k + 1 + r) * LD + c];
-            acc *= 2.0;
-#pragma unroll 8
-            for (int r = 0; r < m; ++r) A[(k + 1 + r) * LD + c] -= acc * vec[r];
+            for (int r = r0; r < r1; ++r) A[(k + 1 + r) * LD + c] -= a * v[r * LD];
+        }
+        __syncthreads();
+        for (int i = tid; i < n - k; i += 256) {
+            A[(k + i) * LD + k] = (i == 0) ? 1.0 : 0.0;
+            A[k * LD + k + i] = (i == 0) ? 1.0 : 0.0;
         }
         __syncthreads();
     }
@@ -737,7 +758,7 @@ hipError_t launch_init_state(const Batch &b, hipStream_t s) {
 }
 
 // partial dots V_i . y for i < m[t] + nx_extra (running tuples only; with
-// only2, only those whose correction needs a second Gram-Schmidt pass)
+// only2, only those whose correction takes the explicit Gram-Schmidt passes)
 template <int MS>
 __global__ __launch_bounds__(256) void k_dots(Batch b, VecRef yref, int nx_extra, int only2) {
     const int t = blockIdx.y;
@@ -944,7 +965,7 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
 #pragma unroll
     for (int i = 0; i < MS + 2; ++i) acc[i] = 0.0;
     // one determinant: Ritz vector, residual, preconditioned correction and
-    // the first Gram-Schmidt projections
+    // its projections on the basis
     auto one = [&](const double (&vd)[MS], double x, double ax, double h) -> double {
         const double r = ax - th * x;
         acc[0] += r * r;
