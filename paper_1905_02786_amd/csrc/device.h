@@ -34,6 +34,14 @@ __device__ __forceinline__ void pair_of(int P, int &p, int &q) {
     q = P - p * (p + 1) / 2;
 }
 
+// First entry i of the new projected-matrix column (V_i . S_m, i <= m) that
+// the GEMM's epilogue forms: m when k_ritz supplied the others as S_i . V_m
+// (subspace bound <= kSdMax, V_m the correction as k_ritz stored it, i.e. no
+// explicit Gram-Schmidt pass changed it afterwards), else 0.
+__device__ __forceinline__ int gemm_dot_first(const Batch &b, int t, int m) {
+    return (b.max_space <= kSdMax && m > 0 && !b.cgs2[t]) ? m : 0;
+}
+
 __device__ __forceinline__ const double *vref(const VecRef &r, int t, int64_t dim) {
     const int32_t k = r.idx ? r.idx[t] : r.idx_const;
     return r.base + (int64_t)t * r.tstride + (int64_t)k * dim;

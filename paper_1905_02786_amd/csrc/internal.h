@@ -10,6 +10,13 @@ namespace mbefci {
 constexpr int kMaxActive = 13;     // n_A limit: the sigma kernel stages (P x P) in LDS
 constexpr int kMaxSpace = 32;      // Davidson subspace limit
 constexpr int kParts = kMaxSpace + 2;   // block partial sums per tuple and block
+// With a subspace bound of at most kSdMax, k_ritz also forms the dots S_i . T
+// of the new basis vector (partials kSdOff + i): they are the new column of
+// the projected matrix above the diagonal (H symmetric: V_i^T H V_m =
+// S_i . V_m), so that the GEMM's epilogue only forms the diagonal entry
+constexpr int kSdMax = 12;
+constexpr int kSdOff = 2 + kSdMax;
+static_assert(kSdOff + kSdMax <= kParts, "S-dot partials past the partial block");
 constexpr int kPsp = 128;          // largest P space of the Davidson preconditioner
 constexpr int kTile = 64;          // determinants per sigma tile (materialised-W variant)
 constexpr int kStrip = 16;         // beta columns per workgroup (column-strip variant)
@@ -99,6 +106,7 @@ struct Batch {
     // entries j >= i used), so Q = V R
     double *R;              // [B][kMaxSpace*kMaxSpace]
     double *y, *coef;       // [B][kMaxSpace]; y: Ritz coefficients on the stored basis V
+    double *sdot;           // [B][kMaxSpace] S_i . V_m, i < m, of the basis vector V_m being added
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
     int32_t *status, *m, *iter, *restart, *out_status; // [B]
     int32_t *cgs2;          // [B] correction takes two explicit Gram-Schmidt passes

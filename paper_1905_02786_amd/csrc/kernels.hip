@@ -561,9 +561,9 @@ __global__ __launch_bounds__(kPsp) void k_psp_guess(Batch b) {
 
 // After k_ritz: T on the P determinants <- (theta - H_PP)^-1 r_P, solved as
 // Q (theta - T)^-1 Q^T r_P (Thomas, pivots kept away from zero like the
-// diagonal preconditioner); the changes of |T|^2 and of the projections
-// V_i . T (x . T on restart) go to the extra partial block.  T is the vector
-// k_ritz wrote, V_m (V_1 on restart).
+// diagonal preconditioner); the changes of |T|^2, of the projections V_i . T
+// (x . T on restart) and of the dots S_i . T (Ax . T) go to the extra partial
+// block.  T is the vector k_ritz wrote, V_m (V_1 on restart).
 template <int MS>
 __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     const int t = blockIdx.x, i = threadIdx.x, n = b.psp;
@@ -576,12 +576,13 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     double *T = b.V + ((int64_t)t * b.max_space + (rs ? 1 : m)) * b.dim;
     const double *Q = b.pQ + (int64_t)t * kPsp * kPsp, *Qt = b.pQt + (int64_t)t * kPsp * kPsp;
     const double *dT = b.pT + (int64_t)t * 3 * kPsp, *eT = dT + kPsp;
-    __shared__ double r[kPsp], w[kPsp], cp[kPsp], red[2][MS + 2];
+    constexpr bool SD = MS <= kSdMax;
+    constexpr int NACC = SD ? kSdOff + MS : 2 + MS;
+    __shared__ double r[kPsp], w[kPsp], cp[kPsp], red[2][NACC];
     int64_t d = 0;
-    double x = 0.0, told = 0.0;
+    double x = 0.0, ax = 0.0, told = 0.0;
     if (i < n) {
         d = b.pidx[(int64_t)t * kPsp + i];
-        double ax = 0.0;
         if (rs) {
             x = V[d];
             ax = S[d];
@@ -617,9 +618,9 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
         for (int k = n - 2; k >= 0; --k) w[k] -= cp[k] * w[k + 1];
     }
     __syncthreads();
-    double acc[MS + 2];
+    double acc[NACC];
 #pragma unroll
-    for (int k = 0; k < MS + 2; ++k) acc[k] = 0.0;
+    for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
     if (i < n) {
         double tv = 0.0;
 #pragma unroll 8
@@ -629,15 +630,19 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
         acc[1] = tv * tv - told * told;
         if (rs) {
             acc[2] = x * dt;
+            if (SD) acc[kSdOff] = ax * dt;
         } else {
 #pragma unroll
             for (int k = 0; k < MS; ++k)
-                if (k < m) acc[2 + k] = V[(int64_t)k * b.dim + d] * dt;
+                if (k < m) {
+                    acc[2 + k] = V[(int64_t)k * b.dim + d] * dt;
+                    if (SD) acc[kSdOff + k] = S[(int64_t)k * b.dim + d] * dt;
+                }
         }
     }
-    const int nx = 2 + (rs ? 1 : m);
+    const int nx = (SD ? kSdOff : 2) + (rs ? 1 : m);
 #pragma unroll
-    for (int k = 0; k < MS + 2; ++k) {
+    for (int k = 0; k < NACC; ++k) {
         if (k < nx) {
             const double v = wave_sum(acc[k]);
             if ((i & 63) == 0) red[i >> 6][k] = v;
@@ -779,15 +784,19 @@ __global__ __launch_bounds__(256) void k_dots(Batch b, VecRef yref, int nx_extra
 }
 
 // G column m: G[i][m] = G[m][i] = V_i . S_m for i <= m (partial blocks
-// 0 .. nsum-1); then m += 1
-__global__ void k_update_G(Batch b, int nsum) {
+// 0 .. nsum-1); with `sd`, the entries i < gemm_dot_first of the GEMM's
+// epilogue come from the S-dots of k_ritz instead.  Then m += 1.
+__global__ void k_update_G(Batch b, int nsum, int sd) {
     const int t = blockIdx.x;
     if (b.status[t] != ST_RUNNING) return;
     const int m = b.m[t];
     double *G = b.G + (int64_t)t * kMaxSpace * kMaxSpace;
+    const int i0 = sd ? gemm_dot_first(b, t, m) : 0;
     if ((int)threadIdx.x <= m) {
         double v = 0.0;
-        for (int blk = 0; blk < nsum; ++blk) v += parts(b, t, blk)[threadIdx.x];
+        if ((int)threadIdx.x < i0) v = b.sdot[(int64_t)t * kMaxSpace + threadIdx.x];
+        else
+            for (int blk = 0; blk < nsum; ++blk) v += parts(b, t, blk)[threadIdx.x];
         G[threadIdx.x * kMaxSpace + m] = v;
         G[m * kMaxSpace + threadIdx.x] = v;
     }
@@ -798,12 +807,12 @@ __global__ void k_update_G(Batch b, int nsum) {
 hipError_t launch_dots(const Batch &b, VecRef y, int nx_extra, hipStream_t s) {
     if (b.max_space <= 12) hipLaunchKernelGGL(k_dots<12>, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra, 0);
     else hipLaunchKernelGGL(k_dots<kMaxSpace>, dim3(b.nblk, b.B), dim3(256), 0, s, b, y, nx_extra, 0);
-    if (nx_extra == 1) hipLaunchKernelGGL(k_update_G, dim3(b.B), dim3(64), 0, s, b, b.nblk);
+    if (nx_extra == 1) hipLaunchKernelGGL(k_update_G, dim3(b.B), dim3(64), 0, s, b, b.nblk, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_update_G(const Batch &b, int nsum, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_G, dim3(b.B), dim3(64), 0, s, b, nsum);
+    hipLaunchKernelGGL(k_update_G, dim3(b.B), dim3(64), 0, s, b, nsum, 1);
     return hipGetLastError();
 }
 
@@ -943,7 +952,8 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
 
 // x = V y, Ax = S y, r = Ax - theta x, T = r / (theta - Hd) (clamped);
 // partials |r|^2, |T|^2 and the projections V_i . T on the subspace the
-// correction is added to (V_i, i < m, or x alone on restart).  T is stored as
+// correction is added to (V_i, i < m, or x alone on restart), and for
+// MS <= kSdMax the dots S_i . T (Ax . T on restart) from partial kSdOff.  T is stored as
 // the next basis vector itself: V_m, or V_1 on restart, where V_0 <- x and
 // S_0 <- Ax in place (each thread owns its d and reads every vector there
 // before it writes).
@@ -961,12 +971,14 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     double *S = b.S + (int64_t)t * b.max_space * b.dim;
     const double *hd = b.Hd + (int64_t)t * b.dim;
     double *T = V + (int64_t)(rs ? 1 : m) * b.dim;
-    double acc[MS + 2];
+    constexpr bool SD = MS <= kSdMax;
+    constexpr int NACC = SD ? kSdOff + MS : 2 + MS;
+    double acc[NACC];
 #pragma unroll
-    for (int i = 0; i < MS + 2; ++i) acc[i] = 0.0;
-    // one determinant: Ritz vector, residual, preconditioned correction and
-    // its projections on the basis
-    auto one = [&](const double (&vd)[MS], double x, double ax, double h) -> double {
+    for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+    // one determinant: Ritz vector, residual, preconditioned correction, its
+    // projections on the basis and its dots with the basis' sigma vectors
+    auto one = [&](const double (&vd)[MS], const double (&sd)[MS], double x, double ax, double h) -> double {
         const double r = ax - th * x;
         acc[0] += r * r;
         double den = th - h;
@@ -975,10 +987,14 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
         acc[1] += tv * tv;
         if (rs) {
             acc[2] += x * tv;
+            if (SD) acc[kSdOff] += ax * tv;
         } else {
-            // (vd[i] = 0 for i >= m: those sums stay unused)
+            // (vd[i] = sd[i] = 0 for i >= m: those sums stay unused)
 #pragma unroll
-            for (int i = 0; i < MS; ++i) acc[2 + i] += vd[i] * tv;
+            for (int i = 0; i < MS; ++i) {
+                acc[2 + i] += vd[i] * tv;
+                if (SD) acc[kSdOff + i] += sd[i] * tv;
+            }
         }
         return tv;
     };
@@ -997,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
         for (int64_t d2 = (int64_t)blockIdx.x * 256 + threadIdx.x; d2 < n2; d2 += (int64_t)gridDim.x * 256) {
             const int64_t d = d2 << 1;
             const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
-            double v0[MS], v1[MS];
+            double v0[MS], v1[MS], s0[MS], s1[MS];
             double x0 = 0.0, x1 = 0.0, a0 = 0.0, a1 = 0.0;
             dbl2 vv[MS], ss[MS];
 #pragma unroll
@@ -1009,14 +1025,16 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
             for (int i = 0; i < MS; ++i) {
                 v0[i] = vv[i].x;
                 v1[i] = vv[i].y;
+                s0[i] = ss[i].x;
+                s1[i] = ss[i].y;
                 x0 += yy[i] * vv[i].x;
                 x1 += yy[i] * vv[i].y;
                 a0 += yy[i] * ss[i].x;
                 a1 += yy[i] * ss[i].y;
             }
             const dbl2 h = *reinterpret_cast<const dbl2 *>(hd + d);
-            const double t0 = one(v0, x0, a0, h.x);
-            const double t1 = one(v1, x1, a1, h.y);
+            const double t0 = one(v0, s0, x0, a0, h.x);
+            const double t1 = one(v1, s1, x1, a1, h.y);
             *reinterpret_cast<dbl2 *>(T + d) = dbl2{t0, t1};
             if (rs) {
                 *reinterpret_cast<dbl2 *>(V + d) = dbl2{x0, x1};
@@ -1037,14 +1055,14 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
                 x += yy[i] * vd[i];
                 ax += yy[i] * sd[i];
             }
-            T[d] = one(vd, x, ax, hd[d]);
+            T[d] = one(vd, sd, x, ax, hd[d]);
             if (rs) {
                 V[d] = x;
                 S[d] = ax;
             }
         }
     }
-    store_block_partials<MS + 2>(b, t, acc, 2 + (rs ? 1 : m));
+    store_block_partials<NACC>(b, t, acc, (SD ? kSdOff : 2) + (rs ? 1 : m));
 }
 
 // convergence test, restart bookkeeping, running count
@@ -1089,7 +1107,10 @@ __global__ void k_coef1(Batch b) {
     const int m = b.m[t], i = threadIdx.x;
     double *R = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
     __shared__ double dv[kMaxSpace], cv[kMaxSpace];
-    if (i < m) dv[i] = sum_parts_x(b, t, 2 + i);
+    if (i < m) {
+        dv[i] = sum_parts_x(b, t, 2 + i);
+        if (b.max_space <= kSdMax) b.sdot[(int64_t)t * kMaxSpace + i] = sum_parts_x(b, t, kSdOff + i);
+    }
     __syncthreads();
     double c = 0.0;
     if (i < m) {

@@ -368,7 +368,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
     if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP;  // RDM Gram partials and sum
-    pt += 8 * (size_t)(2 * kMaxSpace * kMaxSpace + 2 * kMaxSpace + 6) + 4 * 7;
+    pt += 8 * (size_t)(2 * kMaxSpace * kMaxSpace + 3 * kMaxSpace + 6) + 4 * 7;
     cp.per_tuple = pt + 256;
 }
 
@@ -467,6 +467,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.R = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.y = cv.take<double>((size_t)B * kMaxSpace);
     b.coef = cv.take<double>((size_t)B * kMaxSpace);
+    b.sdot = cv.take<double>((size_t)B * kMaxSpace);
     b.theta = cv.take<double>(B);
     b.theta_prev = cv.take<double>(B);
     b.rnorm = cv.take<double>(B);

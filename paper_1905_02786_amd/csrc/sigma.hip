@@ -204,8 +204,8 @@ constexpr int kGK = 16;
 // past the matrix (zero); they only meet zero rows of the other operand (K
 // past the end) or feed rows and columns that are not stored.
 // With `dots` (Davidson, sigma of V_m into S_m) the block also writes the
-// partial dots V_i . S_m, i <= m, of its finished tile to partial block
-// (its tile index) of the tuple.
+// partial dots V_i . S_m, gemm_dot_first <= i <= m, of its finished tile to
+// partial block (its tile index) of the tuple (the others come from k_ritz).
 // Grid: one block per (tuple, output tile), mapped so that every tile of
 // tuple t runs on XCD t % 8 and the tiles of one tuple are dispatched back to
 // back: the K-chunks they all read stay in that XCD's L2.
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
     // the vectors: zero) add nothing; offsets: per (i, q) a vector part, the
     // vector k and the row step 4 v scalar
     __shared__ double red[4][kMaxSpace];
-    const int m = b.m[t];
+    const int m = b.m[t], k0 = gemm_dot_first(b, t, m);
     const __amdgpu_buffer_rsrc_t rV = __builtin_amdgcn_make_buffer_rsrc(
         b.V + (int64_t)t * b.max_space * b.dim, (short)0, (int)(b.max_space * b.dim * sizeof(double)), 0x00020000);
     uint32_t vo[WM][WN];
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
 #pragma unroll
         for (int q = 0; q < WN; ++q)
             vo[i][q] = ((r0 + wy * 16 * WM + i * 16 + (lane >> 4)) * Nb + c0 + wx * 16 * WN + q * 16 + (lane & 15)) * 8u;
-    for (int k = 0; k <= m; ++k) {
+    for (int k = k0; k <= m; ++k) {
         const uint32_t sk = (uint32_t)(k * b.dim) * 8u;
         double a = 0.0;
 #pragma unroll
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
         if (lane == 0) red[wave][k] = a;
     }
     __syncthreads();
-    if (tid <= m) parts(b, t, tile)[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    if (tid >= k0 && tid <= m) parts(b, t, tile)[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // Tile choice: the smaller padded area of 96 x 96 and 64 x 64 tiles; on a tie
