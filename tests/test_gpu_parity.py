@@ -270,9 +270,11 @@ def test_pspace_settings_match_oracle(ws, pspace):
         assert second > 0
 
 
-@pytest.mark.parametrize("max_space", [4, 20, 32])
+@pytest.mark.parametrize("max_space", [2, 3, 4, 20, 32])
 def test_max_space_settings_match_oracle(ws, max_space):
-    """Subspace bounds other than the default: frequent restarts (4) and the
+    """Subspace bounds other than the default: a restart after every one or two
+    expansions (2, 3: the correction goes to basis slot 1 and the triangular
+    factor restarts from the Ritz vector), frequent restarts (4) and the
     32-vector kernel instantiations, on odd and even dimensions."""
     probs = {"hubbard8": synth.config_hubbard(8.0), "sweep": synth.config_sweep(0)}
     cases = [("hubbard8", (1, 2, 3, 6, 9)), ("hubbard8", (0, 1, 2, 6)), ("hubbard8", (0, 2, 6, 8)),
@@ -280,7 +282,7 @@ def test_max_space_settings_match_oracle(ws, max_space):
     worst = 0.0
     for name, S in cases:
         P = probs[name]
-        ctx = _ctx(P, max_space=max_space, max_iter=400)
+        ctx = _ctx(P, max_space=max_space, max_iter=1000)
         e, st = ctx.solve_tuples(len(S), [S], ws)
         e_ref = fci.casci_energy(P, S)
         assert st[0] == 0, (name, S, max_space, st[0])
