@@ -103,8 +103,9 @@ typedef struct {
                                (default) forms only the pair rows that link each alpha string
                                to another (1 + n_a (n_A - n_a) rows, at most 32; the diagonal
                                pairs summed first) where n_A >= 9 and they fit, with the A rows
-                               resident in LDS or gathered per string, whichever keeps the
-                               occupancy; 2 and 3 use linked rows wherever they fit (n_A >= 4),
+                               resident in LDS where that fits and there are at least as many
+                               alpha strings as pair rows, else gathered per string; 2 and 3
+                               use linked rows wherever they fit (n_A >= 4),
                                2 with the A rows gathered, 3 resident (each where it fits, else
                                the other).  Same result up to rounding. */
     int32_t reserved[4];

@@ -180,3 +180,22 @@ def test_tuple_shapes_match_partition():
         assert sh["dim"] == sp.dim
     sh = ctx.tuple_shape(5, (1, 2, 9, 10, 11))
     assert sh["dim"] == 213444 and sh["n_active"] == 11
+
+
+def _header_fields(hdr, name):
+    """Field names of `typedef struct { ... } name;` in declaration order."""
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r";", hdr).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return re.findall(r"\b(?:double|int32_t|int64_t)\s+(\w+)\s*(?:\[\d+\])?\s*;", body)
+
+
+def test_ctypes_structs_match_header():
+    """The Python mirrors of the option and statistics structs list the
+    header's fields in the header's order (the binding passes them by
+    pointer, so a field added to one side only would shift every later one)."""
+    with open(os.path.join(ROOT, "include", "mbefci.h")) as f:
+        hdr = f.read()
+    for cname, cls in (("mbefci_options", _lib.Options), ("mbefci_stats", _lib.Stats)):
+        fields = _header_fields(hdr, cname)
+        assert len(fields) >= 10, cname
+        assert fields == [n for n, _ in cls._fields_], cname
