@@ -820,9 +820,12 @@ hipError_t launch_update_G(const Batch &b, int nsum, hipStream_t s) {
 // parallel (round-robin) rotation order; one block of 64 threads per tuple.
 // The Jacobi matrix is the projection on the orthonormal basis Q = V R,
 // R^T G R (upper triangle computed, mirrored); its eigenvector y becomes the
-// coefficients R y on the stored basis.
+// coefficients R y on the stored basis.  Block 0 also clears the iteration's
+// counters (running tuples, explicit Gram-Schmidt passes), which k_converge
+// and k_coef1 count after it: no memset node in the iteration's launches.
 __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     const int t = blockIdx.x;
+    if (t == 0 && threadIdx.x < 2) b.counter[threadIdx.x] = 0;
     const int32_t st0 = b.status[t];
     if (st0 != ST_RUNNING && st0 != ST_RESTART) return;
     __syncthreads();

@@ -591,7 +591,6 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     int32_t cnt[2] = {b.B, 0};   // running tuples; those of them that need the explicit Gram-Schmidt passes
     int iters = 0;
     for (int it = 0; it <= b.max_iter; ++it) {
-        HIPCHK(hipMemsetAsync(b.counter, 0, 2 * sizeof(int32_t), s));
         if ((e = launch_iter_head(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
         HIPCHK(hipMemcpyAsync(cnt, b.counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
