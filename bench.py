@@ -24,7 +24,7 @@ METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |Î”E|â‰
 # HBM bytes per k_sigma_strip dispatch from the calibrated FETCH_SIZE / WRITE_SIZE
 # passes in profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md, valid only for
 # the strip kernel source they were taken on (kernels_sha1 below).
-TRAFFIC = {"kernels_sha1": "5c960025705ab582d2d780f81a395c7311e506bc", "bytes_per_launch": 797357996.3}
+TRAFFIC = {"kernels_sha1": "5c960025705ab582d2d780f81a395c7311e506bc", "bytes_per_launch": 797653441.9}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
