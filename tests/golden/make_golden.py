@@ -11,6 +11,12 @@ Outputs (JSON, one file per workload) next to this script:
   sweep_sample.json    sampled CASCI energies of the 24-orbital order sweep
   large_sample.json    sampled CASCI energies of the 60-orbital problem
   gradients.npz        MBE gradients (h, (pq|rs)) at orders 2, 4 and full
+  class_samples.json   CASCI energies and the gap to the second root of one or
+                       two tuples of every large shape class of the order sweep
+                       (also at integral scale std 0.1) and of the 60-orbital
+                       problem up to order 4 (dims up to 853776)
+  rdm_large.npz        CASCI energy and the active blocks of gamma and Gamma of
+                       tuples with 10, 11 and 12 active orbitals
 """
 from __future__ import annotations
 
@@ -137,6 +143,105 @@ def gradients():
             print(key, f"{time.time() - t:.1f}s", flush=True)
     np.savez_compressed(os.path.join(HERE, "gradients.npz"), **out)
     print("wrote gradients.npz", flush=True)
+
+
+def _eig2(P, S):
+    """Lowest two eigenvalues of the CAS of S (oracle Hamiltonian; dense up to
+    fci.DENSE_MAX, else ARPACK on the matrix-free product) and the dim."""
+    import scipy.sparse.linalg as sla
+    sp = fci.cas_space(P, S)
+    if sp.dim <= fci.DENSE_MAX:
+        w = np.linalg.eigvalsh(fci.hamiltonian_matrix(P, sp))
+        return float(w[0]), float(w[1]) if len(w) > 1 else None, sp.dim
+    op = sla.LinearOperator((sp.dim, sp.dim), matvec=lambda x: fci.matvec(P, sp, np.asarray(x).reshape(-1)),
+                            dtype=np.float64)
+    v0 = np.random.default_rng(20190507).standard_normal(sp.dim)
+    w = sla.eigsh(op, k=2, which="SA", v0=v0, tol=1e-14, ncv=min(sp.dim - 1, 40), maxiter=100000,
+                  return_eigenvectors=False)
+    w = np.sort(w)
+    return float(w[0]), float(w[1]), sp.dim
+
+
+# one or two tuples of every large shape class: (problem key, tuple)
+CLASS_PICKS = [
+    # order sweep, order 4: (8e,10o) 44100, (10e,10o) 63504
+    ("sweep", (1, 10, 15, 20)), ("sweep", (1, 2, 11, 19)),
+    # order sweep, order 5: (8e,11o) 108900 (4 alpha), (10e,11o) 213444 (5 alpha)
+    ("sweep", (1, 9, 14, 18, 23)), ("sweep", (2, 10, 13, 17, 21)),
+    ("sweep", (1, 2, 9, 16, 22)), ("sweep", (1, 2, 12, 15, 20)),
+    # order sweep with integral scale std 0.1 (20-vector plain scale x 3)
+    ("sweep01", ()), ("sweep01", (9,)), ("sweep01", (1,)), ("sweep01", (10, 17)), ("sweep01", (1, 12)),
+    ("sweep01", (1, 2)), ("sweep01", (9, 14, 20)), ("sweep01", (2, 11, 16)), ("sweep01", (1, 2, 13)),
+    ("sweep01", (11, 13, 18, 21)),
+    # 60 orbitals, order 2: (8e,10o) 44100, (10e,10o) 63504, (12e,10o) 44100
+    ("large", (10, 35)), ("large", (0, 22)), ("large", (0, 1)),
+    # order 4, the dominant classes: (8e,12o) 245025, (10e,12o) 627264, (12e,12o) 853776
+    ("large", (10, 25, 40, 55)),
+    # order 3: (8e,11o) 108900, (10e,11o) 213444, (12e,11o) 213444
+    ("large", (12, 30, 51)), ("large", (1, 20, 44)), ("large", (0, 1, 33)),
+    ("large", (0, 11, 29, 47)), ("large", (0, 1, 18, 52)),
+]
+
+
+def _problems():
+    return {"sweep": synth.config_sweep(0), "sweep01": synth.config_sweep(0, vec_std=0.1),
+            "large": synth.config_large(0)}
+
+
+def class_samples():
+    """Energies and gaps at the large shape classes, written after every tuple."""
+    probs = _problems()
+    path = os.path.join(HERE, "class_samples.json")
+    done = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for s in json.load(f)["samples"]:
+                done[(s["problem"], tuple(s["tuple"]))] = s
+    for key, S in CLASS_PICKS:
+        if (key, S) in done:
+            continue
+        t = time.time()
+        P = probs[key]
+        e0, e1, dim = _eig2(P, S)
+        sp = fci.cas_space(P, S)
+        done[(key, S)] = {"problem": key, "tuple": list(S), "eps": e0, "eps1": e1, "dim": dim,
+                          "n_active": len(sp.active), "na": sp.na, "nb": sp.nb, "seconds": time.time() - t}
+        print(key, S, dim, e0, e1, f"{time.time() - t:.1f}s", flush=True)
+        write("class_samples.json", {"source": "oracle (fci.cas_space, dense eigvalsh or ARPACK k=2)",
+                                     "samples": [done[k] for k in sorted(done, key=lambda k: (k[0], len(k[1]), k[1]))]})
+
+
+RDM_PICKS = [("sweep", (9, 12, 17, 22)), ("sweep", (13, 16, 20, 22, 23)), ("large", (10, 25, 40, 55))]
+
+
+def rdm_large():
+    """CASCI energy, gap and the active blocks gamma_A [nA, nA], Gamma_A
+    [nA, nA, nA, nA] (oracle rdm12 of the ARPACK eigenvector) of tuples with
+    10, 11 and 12 active orbitals."""
+    from oracle import rdm
+    import scipy.sparse.linalg as sla
+    probs = _problems()
+    out = {}
+    for key, S in RDM_PICKS:
+        t = time.time()
+        P = probs[key]
+        sp = fci.cas_space(P, S)
+        op = sla.LinearOperator((sp.dim, sp.dim), matvec=lambda x: fci.matvec(P, sp, np.asarray(x).reshape(-1)),
+                                dtype=np.float64)
+        v0 = np.random.default_rng(20190507).standard_normal(sp.dim)
+        w, v = sla.eigsh(op, k=2, which="SA", v0=v0, tol=1e-14, ncv=min(sp.dim - 1, 40), maxiter=100000)
+        o = np.argsort(w)
+        vec = v[:, o[0]] / np.linalg.norm(v[:, o[0]])
+        g1, g2 = rdm.rdm12(P, sp, vec)
+        A = np.array(sp.active)
+        tag = f"{key}_" + "_".join(map(str, S))
+        out[tag + "_eps"] = np.array([w[o[0]], w[o[1]]])
+        out[tag + "_active"] = A
+        out[tag + "_gamma"] = g1[np.ix_(A, A)]
+        out[tag + "_Gamma"] = g2[np.ix_(A, A, A, A)]
+        print(tag, sp.dim, w[o[0]], w[o[1]], f"{time.time() - t:.1f}s", flush=True)
+        np.savez_compressed(os.path.join(HERE, "rdm_large.npz"), **out)
+    print("wrote rdm_large.npz", flush=True)
 
 
 if __name__ == "__main__":

@@ -384,3 +384,56 @@ def test_full_order_gradient_is_fci_rdm():
     g1, g2 = rdm.rdm12(P, sp, v)
     np.testing.assert_allclose(gh, g1, atol=1e-10)
     np.testing.assert_allclose(ge, 0.5 * g2, atol=1e-10)
+
+
+def _fock_vector(sp, vec, n):
+    """The CAS vector (index ia * len(blist) + ib, creators ordered over the
+    full orbital space) as a Fock-space vector of tests.fockspace."""
+    out = np.zeros(2 ** (2 * n))
+    for ia, a in enumerate(sp.alist):
+        for ib, b in enumerate(sp.blist):
+            out[det_index(a, b, n)] = vec[ia * len(sp.blist) + ib]
+    return out
+
+
+@pytest.mark.parametrize("case", ["closed", "open", "core"])
+def test_rdm_elements_equal_fock_space_operators(case):
+    """Every element of the oracle's gamma and Gamma equals the Jordan-Wigner
+    construction gamma_pq = <c|E_pq|c>, Gamma_pqrs = <c|E_pq E_rs|c> -
+    delta_qr gamma_ps with E_pq = sum_spin a+_p a_q (no Slater-Condon rule, no
+    symmetry assumed): closed shell, open shell, and a CAS with a doubly
+    occupied core orbital and an empty virtual.  A p <-> q transposition of
+    Gamma would fail this test (checked on the same vector)."""
+    from tests.fockspace import mode_annihilators
+    if case == "closed":
+        n, na, nb, core, active = 4, 2, 2, [], [0, 1, 2, 3]
+    elif case == "open":
+        n, na, nb, core, active = 4, 3, 1, [], [0, 1, 2, 3]
+    else:
+        n, na, nb, core, active = 5, 2, 1, [1], [0, 2, 3]
+    h, eri = synth.random_hamiltonian(np.linspace(-1.1, 0.9, n), 0.15, 4, 0.3, seed=17)
+    P = _prob(h, eri, na + len(core), nb + len(core))
+    sp = _space(n, na, nb, core=core, active=active)
+    H = fci.hamiltonian_matrix(P, sp)
+    w, v = np.linalg.eigh(H)
+    vec = v[:, 0]
+    g1, g2 = rdm.rdm12(P, sp, vec)
+    a = mode_annihilators(2 * n)
+    ad = [x.T.tocsr() for x in a]
+    E = [[(ad[p] @ a[q] + ad[n + p] @ a[n + q]).tocsr() for q in range(n)] for p in range(n)]
+    c = _fock_vector(sp, vec, n)
+    Ec = [[E[p][q] @ c for q in range(n)] for p in range(n)]
+    r1 = np.array([[c @ Ec[p][q] for q in range(n)] for p in range(n)])
+    r2 = np.zeros((n, n, n, n))
+    for p in range(n):
+        for q in range(n):
+            left = E[q][p] @ c          # <c|E_pq = (E_qp |c>)^T
+            for r in range(n):
+                for s in range(n):
+                    r2[p, q, r, s] = left @ Ec[r][s] - (r1[p, s] if q == r else 0.0)
+    np.testing.assert_allclose(g1, r1, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g2, r2, rtol=0, atol=1e-12)
+    # sensitivity: the transposed convention differs from the operator form
+    assert np.abs(g2.transpose(1, 0, 2, 3) - r2).max() > 1e-3
+    # and the energy of the CAS follows from these elements
+    assert abs(rdm.energy_from_rdms(P, r1, r2) - w[0]) < 1e-11
