@@ -84,11 +84,19 @@ typedef struct {
     double e_tol;           /* Davidson: |theta - theta_prev| bound (default 1e-11) */
     double r_tol;           /* Davidson: residual 2-norm bound (default 1e-6; the Ritz value
                                then lies within about r_tol^2 / gap of the eigenvalue) */
-    int32_t max_iter;       /* Davidson iterations per tuple (default 200) */
+    int32_t max_iter;       /* Davidson iterations per tuple (default 1000) */
     int32_t max_space;      /* subspace vectors before restart, 2..32 (default 12) */
     int32_t batched;        /* 1: every tuple of a shape class in one batch of launches;
                                0: one tuple per launch sequence (the per-solve path) */
-    int32_t keep_vectors;   /* reserved for the backward pass; 0 */
+    int32_t gradient;       /* 1: mbefci_run also forms the gradient of the total with respect to
+                               h1 and (pq|rs) (density matrices of every tuple at convergence,
+                               weighted as at mbefci_backward, the last order's on the device as
+                               it converges), kept in the result, so that mbefci_backward solves
+                               nothing again.  Such a run, every backward pass and
+                               mbefci_tuple_rdm converge each tuple to r_tol <= 1e-9 and
+                               e_tol <= 1e-12 (max_iter >= 1000) whatever the options say:
+                               density matrices are first order in the residual.  Needs n^2 + n^4
+                               doubles of workspace beyond the batches. (default 0) */
     int32_t profile;        /* 1: time every sigma launch with HIP events (mbefci_get_stats) */
     int32_t sigma_variant;  /* 0: automatic; 1: column strip (W kept in LDS, beta-beta part as a
                                GEMM with the dense beta-string Hamiltonian); 2: W materialised
@@ -104,10 +112,14 @@ typedef struct {
                                to another (1 + n_a (n_A - n_a) rows, at most 32; the diagonal
                                pairs summed first) where n_A >= 9 and they fit, with the A rows
                                resident in LDS where that fits and there are at least as many
-                               alpha strings as pair rows, else gathered per string; 2 and 3
-                               use linked rows wherever they fit (n_A >= 4),
-                               2 with the A rows gathered, 3 resident (each where it fits, else
-                               the other).  Same result up to rounding. */
+                               alpha strings as pair rows, else gathered per string; where the
+                               n_a (n_A - n_a) off-diagonal rows alone fill the 32 slots (n_A =
+                               12 with 4 or 8 alpha electrons) the diagonal row goes to the
+                               vector ALU (A rows resident, two halves of four waves); 2 and 3
+                               use linked rows wherever they fit (n_A >= 4), 2 with the A rows
+                               gathered, 3 resident (each where it fits, else the other); 4 the
+                               vector-ALU diagonal form wherever it fits.  Same result up to
+                               rounding. */
     int32_t reserved[4];
 } mbefci_options;
 
@@ -158,6 +170,19 @@ mbefci_status mbefci_set_hamiltonian(mbefci_ctx *ctx, int32_t norb, const double
  * orbital is outside [Pi] or a frozen orbital is not doubly occupied. */
 mbefci_status mbefci_set_spaces(mbefci_ctx *ctx, int32_t nalpha, int32_t nbeta, int32_t nfrozen,
                                 const int32_t *ref_orbs, int32_t nref);
+
+/* Pi-pruning (Sec. 3; Sec. 4.1.2, Table 2): npairs pairs of expansion
+ * orbitals orbs[2i], orbs[2i+1] (the x and y components of a degenerate pi
+ * pair; no orbital twice); increments are then computed only for tuples that
+ * hold both components of every pair or neither.  Under screening an order-k
+ * tuple is computed iff it adds one unpaired orbital to an order-(k-1) tuple
+ * with |d_eps| >= tau_{k-1}, or one whole pair to an order-(k-2) tuple with
+ * |d_eps| >= tau_{k-2} (the empty tuple always counts; a reading, as the rule
+ * at mbefci_options.a); without screening every such tuple is computed.  An
+ * order without tuples then ends the expansion only if the order before it
+ * had none either.  npairs = 0 clears; mbefci_set_spaces clears too.  EINVAL
+ * for an orbital outside X or in two pairs; ESTATE before mbefci_set_spaces. */
+mbefci_status mbefci_set_pi_pairs(mbefci_ctx *ctx, const int32_t *orbs, int32_t npairs);
 
 mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *opt);
 
@@ -234,19 +259,26 @@ mbefci_status mbefci_string_tables(int32_t norb_active, int32_t nel, int64_t *n_
                                    int32_t *n_entries, uint32_t *strings, uint32_t *links);
 
 /* Gradient of the summed MBE energy of `res` (Eq. 1-3, tuple set held fixed)
- * with respect to every entry of h1 and of the full n^4 (pq|rs) array, each
- * treated as an independent variable, times gE:
+ * with respect to every entry of h1 and of (pq|rs), each treated as an
+ * independent variable, times gE:
  *   grad_h1[p*n+q]            = gE * sum_S w_S gamma_pq(S)
- *   grad_eri[((p*n+q)*n+r)*n+s] = gE * 1/2 sum_S w_S Gamma_pqrs(S)
+ *   full layout: grad_eri[((p*n+q)*n+r)*n+s] = gE * 1/2 sum_S w_S Gamma_pqrs(S)
+ *   packed layout (the integrals were set as MBEFCI_ERI_PACKED8): grad_eri[k]
+ *     for packed element k = the sum of the full-layout entries over the
+ *     distinct index quadruples of its orbit (the derivative with respect to
+ *     that one stored number); n(n+1)/2 (n(n+1)/2 + 1)/2 doubles
  * where w = (I + L^T)^-1 1 are the integer adjoint weights of the increment
  * recursion (L_ST = 1 iff T is a proper subtuple of S), and gamma(S), Gamma(S)
  * are the full-space one- and two-particle density matrices of tuple S's
  * CASCI ground state (gamma_pq = <E_pq>, Gamma_pqrs = <E_pq E_rs> - d_qr
- * gamma_ps, frozen core included).  Tuples with w_S != 0 are solved again
- * (same Davidson), and their density matrices come from a device Gram
- * contraction of <I|E_pq|c>.  Host outputs: n*n and n^4 doubles.  ETOOLARGE
- * for a CAS of more than 12 active orbitals.  The ground states must be
- * non-degenerate for the derivative to exist. */
+ * gamma_ps, frozen core included).  If `res` was computed with
+ * options.gradient = 1 the stored gradient is returned and the workspace is
+ * not used; otherwise the tuples with w_S != 0 are solved again (|r| <= 1e-9)
+ * and their density matrices come from a device Gram contraction of
+ * <I|E_pq|c>, embedded into the gradient on the device (n^2 + n^4 doubles of
+ * the workspace).  Host outputs: n*n doubles and grad_eri in the layout of
+ * the integrals.  ETOOLARGE for a CAS of more than 12 active orbitals.  The
+ * ground states must be non-degenerate for the derivative to exist. */
 mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double gE, void *d_workspace,
                               size_t ws_bytes, double *grad_h1, double *grad_eri);
 

@@ -23,6 +23,17 @@ which is not available).  Reading used on both sides:
     the sums of Eq. 3, as the paper says screened contributions are not
     accounted for).
 
+Pi-pruning (Sec. 3: increments are computed only for tuples that hold both
+components of a degenerate pair of pi orbitals, or neither; the counts of
+Table 2, 6, 21, 56, 120, 216, 336 for 6 sigma orbitals and 6 pairs, pin it).
+Reading for the candidates under screening: an order-k tuple is computed iff
+it is pi-complete and either adds one unpaired orbital to a computed order-(k-1)
+tuple T with |d_eps(T)| >= tau_{k-1}, or adds one whole pair to a computed
+order-(k-2) tuple T with |d_eps(T)| >= tau_{k-2} (the empty tuple always
+counts).  Without screening this gives every pi-complete tuple.  An order with
+no candidates ends the expansion unless the order before it had tuples (a pair
+added two orders back may still follow).
+
 Summation order (fixed so that two implementations agree bitwise on the same
 epsilons): subtuples T in (|T|, lexicographic) order, accumulated from 0.0,
 then d_eps(S) = eps(S) - acc.  Order sums accumulate in tuple-list order,
@@ -84,13 +95,42 @@ def children(parents, dinc, X, tau):
     return sorted(out)
 
 
-def candidates(problem, k, prev_order, dinc):
+def pi_complete(S, pairs):
+    s = set(S)
+    return all((x in s) == (y in s) for x, y in pairs)
+
+
+def pi_children(orders, dinc, X, pairs, a, k):
+    """Order-k candidates under pi-pruning (reading in the module docstring);
+    orders[j] is the computed order j."""
+    paired = {x for pr in pairs for x in pr}
+    out = set()
+    if k - 1 >= 1:
+        tau = screen_threshold(a, k - 1)
+        for T in orders[k - 1].tuples:
+            if abs(dinc[T]) >= tau:
+                for x in X:
+                    if x not in paired and x not in T:
+                        out.add(tuple(sorted(T + (x,))))
+    if k - 2 >= 0:
+        tau2 = screen_threshold(a, k - 2)
+        for T in orders[k - 2].tuples:
+            if k - 2 == 0 or abs(dinc[T]) >= tau2:
+                for x, y in pairs:
+                    if x not in T and y not in T:
+                        out.add(tuple(sorted(T + (x, y))))
+    return sorted(out)
+
+
+def candidates(problem, k, prev_order, dinc, orders=None):
     """Tuples to compute at order k (k >= 1)."""
     X = problem.expansion_space()
-    if k == 1:
-        return [(x,) for x in X]
-    if problem.a <= 0.0:
-        return list(itertools.combinations(X, k))
+    pairs = [tuple(p) for p in getattr(problem, "pi_pairs", [])]
+    if k == 1 or problem.a <= 0.0:
+        allk = [(x,) for x in X] if k == 1 else list(itertools.combinations(X, k))
+        return [S for S in allk if pi_complete(S, pairs)] if pairs else allk
+    if pairs:
+        return pi_children(orders, dinc, X, pairs, problem.a, k)
     return children(prev_order.tuples, dinc, X, screen_threshold(problem.a, k - 1))
 
 
@@ -137,9 +177,13 @@ def run(problem, energy=None, max_order=None) -> MBEResult:
     res = MBEResult()
     e0 = energy(())
     res.orders.append(assemble(0, [()], [e0], dinc))
+    pairs = getattr(problem, "pi_pairs", [])
     for k in range(1, kmax + 1):
-        cand = candidates(problem, k, res.orders[-1], dinc)
+        cand = candidates(problem, k, res.orders[-1], dinc, res.orders)
         if not cand:
+            if pairs and res.orders[-1].tuples:
+                res.orders.append(Order(k, [], [], [], 0.0))
+                continue
             break
         eps = [energy(S) for S in cand]
         res.orders.append(assemble(k, cand, eps, dinc))

@@ -18,7 +18,7 @@ c_int32, c_int64, c_double, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64
 class Options(ctypes.Structure):
     _fields_ = [("a", c_double), ("max_order", c_int32), ("e_tol", c_double), ("r_tol", c_double),
                 ("max_iter", c_int32), ("max_space", c_int32), ("batched", c_int32),
-                ("keep_vectors", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
+                ("gradient", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
                 ("pspace", c_int32), ("linked_rows", c_int32),
                 ("reserved", c_int32 * 4)]
 
@@ -44,6 +44,7 @@ SIGNATURES = [
     ("mbefci_set_hamiltonian", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_double]),
     ("mbefci_set_spaces", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_int32]),
     ("mbefci_set_options", c_int32, [c_void_p, ctypes.POINTER(Options)]),
+    ("mbefci_set_pi_pairs", c_int32, [c_void_p, c_void_p, c_int32]),
     ("mbefci_workspace_query", c_int32, [c_void_p, c_int32, c_int64, c_void_p,
                                          ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t)]),
     ("mbefci_solve_tuples", c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t,

@@ -66,6 +66,10 @@ def _read_result(L, res) -> Result:
         if rc != 0:
             raise MBEFCIError(rc, "result_order")
         m = nt.value
+        if m == 0:   # an empty order (pi-pruning)
+            out.orders.append(Order(k, np.zeros((0, k), dtype=np.int16), np.zeros(0), np.zeros(0),
+                                    np.zeros(0, dtype=np.int32), osum.value, wall.value))
+            continue
         if k > 0:
             tb = ctypes.string_at(tp.value, 2 * m * k)
             tuples = np.frombuffer(tb, dtype=np.int16).reshape(m, k).copy()
@@ -123,11 +127,17 @@ class Context:
             layout = 1
         self._check(self.L.mbefci_set_hamiltonian(self.ptr, n, _p(h), _p(eri), layout, float(e_const)))
         self.norb = n
+        self.eri_layout = layout
 
     def set_spaces(self, nalpha, nbeta, nfrozen, ref):
         r = np.ascontiguousarray(list(ref), dtype=np.int32)
         self._check(self.L.mbefci_set_spaces(self.ptr, int(nalpha), int(nbeta), int(nfrozen),
                                              _p(r) if r.size else None, int(r.size)))
+
+    def set_pi_pairs(self, pairs):
+        """Pi-pruning: pairs of expansion orbitals entering tuples together."""
+        a = np.ascontiguousarray(np.asarray(list(pairs), dtype=np.int32).reshape(-1))
+        self._check(self.L.mbefci_set_pi_pairs(self.ptr, _p(a) if a.size else None, int(a.size // 2)))
 
     def set_options(self, **kw):
         o = default_options()
@@ -143,6 +153,8 @@ class Context:
         ctx = cls(device, stream)
         ctx.set_hamiltonian(problem.h, problem.eri, problem.e_const)
         ctx.set_spaces(problem.nalpha, problem.nbeta, problem.nfrozen, problem.ref)
+        if getattr(problem, "pi_pairs", None):
+            ctx.set_pi_pairs(problem.pi_pairs)
         opts = dict(a=problem.a, max_order=problem.max_order)
         opts.update(options)
         ctx.set_options(**opts)
@@ -191,11 +203,16 @@ class Context:
         return out
 
     def backward(self, handle, workspace, gE=1.0):
-        """(dE/dh1 [n, n], dE/d(pq|rs) [n, n, n, n]) of the summed MBE energy,
-        times gE, with the tuple set of `handle` held fixed."""
+        """(dE/dh1 [n, n], dE/d(pq|rs)) of the summed MBE energy, times gE,
+        with the tuple set of `handle` held fixed; dE/d(pq|rs) is [n, n, n, n]
+        or, for packed integrals, the packed vector (orbit sums)."""
         n = self.norb
         gh = np.zeros((n, n))
-        ge = np.zeros((n, n, n, n))
+        if self.eri_layout == 0:
+            ge = np.zeros((n, n, n, n))
+        else:
+            npair = n * (n + 1) // 2
+            ge = np.zeros(npair * (npair + 1) // 2)
         self._check(self.L.mbefci_backward(self.ptr, handle.ptr, float(gE), ctypes.c_void_p(workspace.data_ptr()),
                                            workspace.numel(), _p(gh), _p(ge)))
         return gh, ge

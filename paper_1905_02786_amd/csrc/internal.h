@@ -34,8 +34,8 @@ enum : int32_t { SIGMA_AUTO = 0, SIGMA_STRIP = 1, SIGMA_WMAT = 2 };
 enum : int32_t { ST_RUNNING = 0, ST_DONE = 1, ST_MAXITER = 2, ST_NONFINITE = 3, ST_STALLED = 4,
                  ST_RESTART = 5 /* running; skips this expansion, restarts from its Ritz vector next */ };
 
-inline int pair_count(int n) { return n * (n + 1) / 2; }
-inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+__host__ __device__ inline int pair_count(int n) { return n * (n + 1) / 2; }
+__host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Offsets (in doubles) inside one tuple's parameter block.
 struct ParamLayout {
@@ -87,6 +87,7 @@ struct Batch {
     const int32_t *lperm;   // [2 (lpairs + 8)] alpha strings in pairs (N_a: dummy)
     int lpairs;
     int linked_mode;        // 1: variant by occupancy, 2: gathered A, 3: resident A (where it fits)
+    int linked_dv;          // slots hold the off-diagonal links only; diagonal sums on the vector ALU
     const int32_t *act;     // [B * nA] active orbitals (ascending)
     const int32_t *core;    // [B * nC] core orbitals
     double *params;         // [B * pl.stride]
@@ -122,6 +123,7 @@ struct Batch {
     int nblk_r;
     double *rdm_part;       // [B][nblk_r][NP*NP]
     double *rdm_G;          // [B][NP*NP]
+    double *rdm_w;          // [B] weights of the device embedding into the gradient
 };
 
 // kernels.hip, sigma.hip and strip.hip
@@ -146,6 +148,9 @@ __host__ __device__ inline int linked_row_len(int Kpad) { return (Kpad / 4 + 1) 
 // lanes kr in register v) in a string's scatter-entry row: 16 h + 4 kr + v.
 inline int linked_scat_pos(int s) { return (s & 16) | ((s & 3) << 2) | ((s >> 2) & 3); }
 bool linked_fits(const ParamLayout &pl, int64_t Na, int nel);
+// the form whose 32 slots hold only the n (n_A - n) off-diagonal links (the
+// diagonal sums on the vector ALU, A resident in LDS, two halves of four waves)
+bool linked_dv_fits(const ParamLayout &pl, int64_t Na, int nel);
 int64_t linked_a_stride(const ParamLayout &pl, int64_t Na);
 hipError_t launch_linked_a(const Batch &b, hipStream_t s);
 hipError_t launch_gather(const Batch &b, hipStream_t s);
@@ -175,5 +180,8 @@ hipError_t launch_pspace(const Batch &b, hipStream_t s);
 int rdm_np(int nA);
 size_t rdm_lds_bytes(int NP);
 hipError_t launch_rdm(const Batch &b, VecRef x, double *part, double *G, int nblk_r, hipStream_t s);
+// weighted embedding of the batch's density matrices (b.rdm_G) into the
+// full-space gradient gh [n^2], ge [n^4] (device), weights w [B] (device)
+hipError_t launch_rdm_embed(const Batch &b, const double *w, double *gh, double *ge, hipStream_t s);
 
 }  // namespace mbefci

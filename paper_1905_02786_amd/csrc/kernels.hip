@@ -1446,6 +1446,72 @@ hipError_t launch_rdm(const Batch &b, VecRef x, double *part, double *G, int nbl
     return hipGetLastError();
 }
 
+// Weighted embedding of the batch's density matrices into the full-space
+// gradient (n x n and n^4 doubles, row-major), w[t] the weight of tuple t:
+//   grad_h[o_p, o_q] += w gamma_pq,  grad_eri[o_p, o_q, o_r, o_s] += w/2 Gamma_pqrs
+// with gamma_pq = G[pq, x] and Gamma_pqrs = G[qp, rs] - d_qr gamma_ps over the
+// active orbitals o, and for the doubly occupied core c, d: gamma_cc = 2,
+// Gamma_cccc = 2, Gamma_ccdd = 4 and Gamma_cddc = -2 (c != d), Gamma_pqcc =
+// Gamma_ccpq = 2 gamma_pq, Gamma_pccq = Gamma_cqpc = -gamma_pq.  Tuples share
+// full-space entries, so the adds are atomic (their order, and the last bits
+// of the sums, are not fixed).
+__device__ __forceinline__ void grad_add(double *a, double v) { unsafeAtomicAdd(a, v); }
+
+__global__ __launch_bounds__(256) void k_rdm_embed_act(Batch b, const double *w, double *ge) {
+    const int t = blockIdx.y;
+    const double wt = w[t];
+    if (wt == 0.0) return;
+    const int nA = b.nA, nn = nA * nA, NP = round_up(nn + 1, 16), n = b.norb;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nn * nn) return;
+    const int p = idx / (nA * nn), q = (idx / nn) % nA, r = (idx / nA) % nA, s = idx % nA;
+    const double *G = b.rdm_G + (int64_t)t * NP * NP;
+    const int32_t *o = b.act + (int64_t)t * nA;
+    double v = G[(int64_t)(q * nA + p) * NP + r * nA + s];
+    if (q == r) v -= G[(int64_t)(p * nA + s) * NP + nn];
+    grad_add(ge + (((int64_t)o[p] * n + o[q]) * n + o[r]) * n + o[s], 0.5 * wt * v);
+}
+
+__global__ __launch_bounds__(256) void k_rdm_embed_core(Batch b, const double *w, double *gh, double *ge) {
+    const int t = blockIdx.x;
+    const double wt = w[t];
+    if (wt == 0.0) return;
+    const int nA = b.nA, nn = nA * nA, NP = round_up(nn + 1, 16), n = b.norb, nC = b.nC;
+    const double *G = b.rdm_G + (int64_t)t * NP * NP;
+    const int32_t *o = b.act + (int64_t)t * nA, *C = b.core + (int64_t)t * nC;
+    const double hw = 0.5 * wt;
+    auto E = [&](int p, int q, int r, int s) { return ge + (((int64_t)p * n + q) * n + r) * n + s; };
+    for (int i = threadIdx.x; i < nn; i += 256) {
+        const int p = i / nA, q = i % nA;
+        grad_add(gh + (int64_t)o[p] * n + o[q], wt * G[(int64_t)i * NP + nn]);
+    }
+    for (int i = threadIdx.x; i < nC * nC; i += 256) {
+        const int c = C[i / nC], d = C[i % nC];
+        if (c == d) {
+            grad_add(gh + (int64_t)c * n + c, 2.0 * wt);
+            grad_add(E(c, c, c, c), hw * 2.0);
+        } else {
+            grad_add(E(c, c, d, d), hw * 4.0);
+            grad_add(E(c, d, d, c), hw * -2.0);
+        }
+    }
+    for (int i = threadIdx.x; i < nC * nn; i += 256) {
+        const int c = C[i / nn], pq = i % nn, p = pq / nA, q = pq % nA;
+        const double g = G[(int64_t)pq * NP + nn];
+        grad_add(E(o[p], o[q], c, c), hw * 2.0 * g);
+        grad_add(E(c, c, o[p], o[q]), hw * 2.0 * g);
+        grad_add(E(o[p], c, c, o[q]), -hw * g);
+        grad_add(E(c, o[q], o[p], c), -hw * g);
+    }
+}
+
+hipError_t launch_rdm_embed(const Batch &b, const double *w, double *gh, double *ge, hipStream_t s) {
+    const int n4 = b.nA * b.nA * b.nA * b.nA;
+    hipLaunchKernelGGL(k_rdm_embed_act, dim3((n4 + 255) / 256, b.B), dim3(256), 0, s, b, w, ge);
+    hipLaunchKernelGGL(k_rdm_embed_core, dim3(b.B), dim3(256), 0, s, b, w, gh, ge);
+    return hipGetLastError();
+}
+
 __global__ void k_finalize(Batch b) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= b.B) return;

@@ -28,6 +28,7 @@ struct Tables {
     std::vector<uint32_t> pairs;     // [nstr][P]: link of each string per pair, strip pair order
     std::vector<uint32_t> scat;      // [nstr + 1][P + 1]: scatter form for the strip kernel
     std::vector<uint32_t> lrow, lscat;   // [nstr + 1][32]: linked-row form (empty if the links need more slots)
+    std::vector<uint32_t> lrow_v, lscat_v;   // the same without the diagonal slot (diagonal on the vector ALU)
     std::vector<int32_t> lperm;          // [2 (lpairs + 8)]: string order of the linked-row kernel
     int lpairs = 0;
 };
@@ -153,18 +154,28 @@ void build_tables(int nA, int nel, Tables &T) {
     // entries are one 16-byte load.
     T.lrow.clear();
     T.lscat.clear();
+    T.lrow_v.clear();
+    T.lscat_v.clear();
     T.lperm.clear();
     T.lpairs = 0;
-    if (1 + nel * (nA - nel) <= kLinkedRows) {
+    // both forms where they fit: with the diagonal sum in slot 0 (1 + n (n_A - n)
+    // rows) and, for the vector-ALU diagonal, the off-diagonal links alone
+    for (int form = 0; form < 2; ++form) {
+        const bool dv = form == 1;
+        if ((dv ? 0 : 1) + nel * (nA - nel) > kLinkedRows) continue;
         const uint32_t kp8 = (uint32_t)linked_row_len((np + 3) / 4 * 4) * 8u;
         const uint32_t dg = kLinkedSigned ? 2 * np : np;   // first diagonal-sum row
-        T.lrow.assign((size_t)(T.nstr + 1) * kLinkedRows, 0u);
-        T.lscat.assign((size_t)(T.nstr + 1) * kLinkedRows, discard);
+        std::vector<uint32_t> &LR = dv ? T.lrow_v : T.lrow, &LS = dv ? T.lscat_v : T.lscat;
+        LR.assign((size_t)(T.nstr + 1) * kLinkedRows, 0u);
+        LS.assign((size_t)(T.nstr + 1) * kLinkedRows, discard);
         for (int64_t I = 0; I < T.nstr; ++I) {
-            uint32_t *lr = &T.lrow[(size_t)I * kLinkedRows], *ls = &T.lscat[(size_t)I * kLinkedRows];
-            lr[0] = (uint32_t)(dg + I) * kp8;
-            ls[linked_scat_pos(0)] = (uint32_t)I * 128u;
-            int slot = 1;
+            uint32_t *lr = &LR[(size_t)I * kLinkedRows], *ls = &LS[(size_t)I * kLinkedRows];
+            int slot = 0;
+            if (!dv) {
+                lr[0] = (uint32_t)(dg + I) * kp8;
+                ls[linked_scat_pos(0)] = (uint32_t)I * 128u;
+                slot = 1;
+            }
             for (int e = 0; e < T.nent; ++e) {
                 const uint32_t L = T.links[(size_t)I * T.nent + e];
                 const int P = (int)((L >> 20) & 0x3FFu);
@@ -179,8 +190,8 @@ void build_tables(int nA, int nel, Tables &T) {
                 ++slot;
             }
         }
-        pair_strings(T);
     }
+    if (!T.lrow.empty() || !T.lrow_v.empty()) pair_strings(T);
 }
 
 struct ClassKey {
@@ -202,6 +213,10 @@ struct Result {
     };
     std::vector<Order> orders;
     double total = 0.0;
+    // gradient of the total formed by the forward run (options.gradient = 1):
+    // dE/dh [n^2] and dE/d(pq|rs) [n^4], entries as independent variables
+    bool has_grad = false;
+    std::vector<double> grad_h, grad_eri;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -229,11 +244,16 @@ struct mbefci_ctx {
     std::vector<double> h, eri;
     double e_const = 0.0;
     double *d_h = nullptr, *d_eri = nullptr;
+    mbefci_eri_layout eri_layout = MBEFCI_ERI_FULL;
+    // device gradient accumulators of the running gradient pass (in the
+    // caller's workspace, past the part the batches use)
+    double *d_gh = nullptr, *d_ge = nullptr;
     // spaces
     bool spaces_set = false;
     int nalpha = 0, nbeta = 0, nfrozen = 0;
     std::vector<int> ref, X;
     std::vector<char> inX;
+    std::vector<std::pair<int, int>> pi;   // degenerate pairs of the expansion space (pi-pruning)
     mbefci_options opt{};
     mbefci_stats stats{};
     bool sigma_pending = false;   // profile: events of the last sigma not read yet
@@ -315,6 +335,7 @@ struct ClassPlan {
     int variant;
     int psp;   // P-space size of the Davidson preconditioner (0: diagonal only)
     bool linked;   // linked-row strip kernel
+    bool linked_dv;   // its form without the diagonal slot (diagonal sums on the vector ALU)
     bool rdm;
     int nblk_r, NP;
     size_t fixed_bytes, per_tuple;
@@ -341,10 +362,16 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.variant = (want == SIGMA_WMAT || !fits) ? SIGMA_WMAT : SIGMA_STRIP;
     cp.psp = (davidson && cp.variant == SIGMA_STRIP && ctx->opt.pspace > 0)
                  ? (int)std::min<int64_t>(ctx->opt.pspace, cp.dim) : 0;
-    // linked rows pay off where they replace at least three MFMA row tiles
+    // linked rows pay off where they replace at least three MFMA row tiles;
+    // the form with the diagonal slot wherever it fits (linked_rows 1-3), else
+    // (or always with linked_rows 4) the form with the diagonal sums on the
+    // vector ALU
     const int lm = ctx->opt.linked_rows;
-    cp.linked = cp.variant == SIGMA_STRIP && lm != 0 && key.nA >= (lm == 1 ? kLinkedMinActive : 4) &&
-                !cp.ta->lrow.empty() && linked_fits(cp.pl, cp.ta->nstr, key.na);
+    const bool lin_ok = cp.variant == SIGMA_STRIP && lm != 0 && key.nA >= (lm == 1 ? kLinkedMinActive : 4);
+    const bool classic = lin_ok && !cp.ta->lrow.empty() && linked_fits(cp.pl, cp.ta->nstr, key.na);
+    const bool dvf = lin_ok && !cp.ta->lrow_v.empty() && linked_dv_fits(cp.pl, cp.ta->nstr, key.na);
+    cp.linked_dv = dvf && (lm == 4 || !classic);
+    cp.linked = classic || cp.linked_dv;
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
@@ -367,7 +394,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
-    if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP;  // RDM Gram partials and sum
+    if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP + 8 + 256;  // RDM Gram partials, sum, weight
     pt += 8 * (size_t)(2 * kMaxSpace * kMaxSpace + 3 * kMaxSpace + 6) + 4 * 7;
     cp.per_tuple = pt + 256;
 }
@@ -421,6 +448,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.lperm = cv.take<int32_t>(cp.ta->lperm.size());
         b.lpairs = cp.ta->lpairs;
         b.linked_mode = ctx->opt.linked_rows;
+        b.linked_dv = cp.linked_dv ? 1 : 0;
     } else {
         b.lrow = b.lscat = nullptr;
         b.la = nullptr;
@@ -484,8 +512,9 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     if (cp.rdm) {
         b.rdm_part = cv.take<double>((size_t)B * cp.nblk_r * cp.NP * cp.NP);
         b.rdm_G = cv.take<double>((size_t)B * cp.NP * cp.NP);
+        b.rdm_w = cv.take<double>(B);
     } else {
-        b.rdm_part = b.rdm_G = nullptr;
+        b.rdm_part = b.rdm_G = b.rdm_w = nullptr;
     }
     return cv.ok;
 }
@@ -502,9 +531,11 @@ mbefci_status upload_tables(mbefci_ctx *ctx, const ClassPlan &cp, const Batch &b
     HIPCHK(hipMemcpyAsync((void *)b.pairB, cp.tb->pairs.data(), 4 * (size_t)b.Nb * b.pl.P, hipMemcpyHostToDevice,
                           ctx->stream));
     if (b.la) {
-        HIPCHK(hipMemcpyAsync((void *)b.lrow, cp.ta->lrow.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
+        const std::vector<uint32_t> &lr = b.linked_dv ? cp.ta->lrow_v : cp.ta->lrow,
+                                    &ls = b.linked_dv ? cp.ta->lscat_v : cp.ta->lscat;
+        HIPCHK(hipMemcpyAsync((void *)b.lrow, lr.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
                               hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipMemcpyAsync((void *)b.lscat, cp.ta->lscat.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
+        HIPCHK(hipMemcpyAsync((void *)b.lscat, ls.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
                               hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync((void *)b.lperm, cp.ta->lperm.data(), 4 * cp.ta->lperm.size(), hipMemcpyHostToDevice,
                               ctx->stream));
@@ -562,11 +593,17 @@ mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, dou
     return MBEFCI_OK;
 }
 
+// What happens to the density matrices of a batch's converged vectors:
+// copied to the host as Gram matrices (gram), or embedded on the device into
+// the gradient accumulators ctx->d_gh, d_ge with the weights w (host, [B]).
+struct RdmOut {
+    std::vector<double> *gram = nullptr;
+    const double *w = nullptr;
+};
+
 // Davidson for one batch; energies/status (public codes) written at out[t].
-// With `gram` the RDM Gram matrices of the converged vectors (NP*NP each) are
-// copied to the host too.
 mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out,
-                             std::vector<double> *gram = nullptr) {
+                             const RdmOut *ro = nullptr) {
     hipStream_t s = ctx->stream;
     hipError_t e;
     if ((e = launch_gather(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
@@ -604,14 +641,21 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
         if (rc != MBEFCI_OK) return rc;
     }
     if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-    if (gram) {
+    if (ro) {
         const int NP = rdm_np(b.nA);
         if ((e = launch_form_x(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
         VecRef xr{b.T, b.dim, nullptr, 0};
         if ((e = launch_rdm(b, xr, b.rdm_part, b.rdm_G, b.nblk_r, s)) != hipSuccess)
             return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-        gram->resize((size_t)b.B * NP * NP);
-        HIPCHK(hipMemcpyAsync(gram->data(), b.rdm_G, 8 * gram->size(), hipMemcpyDeviceToHost, s));
+        if (ro->gram) {
+            ro->gram->resize((size_t)b.B * NP * NP);
+            HIPCHK(hipMemcpyAsync(ro->gram->data(), b.rdm_G, 8 * ro->gram->size(), hipMemcpyDeviceToHost, s));
+        }
+        if (ro->w) {
+            HIPCHK(hipMemcpyAsync(b.rdm_w, ro->w, 8 * (size_t)b.B, hipMemcpyHostToDevice, s));
+            if ((e = launch_rdm_embed(b, b.rdm_w, ctx->d_gh, ctx->d_ge, s)) != hipSuccess)
+                return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        }
     }
     std::vector<int32_t> dst(b.B), dit(b.B);
     HIPCHK(hipMemcpyAsync(e_out, b.out_e, 8 * (size_t)b.B, hipMemcpyDeviceToHost, s));
@@ -641,9 +685,13 @@ mbefci_status check_device(mbefci_ctx *ctx) {
     return MBEFCI_OK;
 }
 
-// Receives the RDM Gram matrix of one solved tuple (input index, its shape).
+// Density matrices of solved tuples: embedded on the device with a weight
+// per tuple (device() true; the caller has set ctx->d_gh, d_ge), or their Gram
+// matrices handed over on the host (input index, its shape).
 struct RdmSink {
-    virtual void take(int64_t index, const TupleShape &ts, const double *G, int NP) = 0;
+    virtual bool device() const { return false; }
+    virtual double weight(int64_t) const { return 1.0; }
+    virtual void take(int64_t, const TupleShape &, const double *, int) {}
     virtual ~RdmSink() = default;
 };
 
@@ -683,15 +731,23 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
             std::vector<const TupleShape *> sh(B);
             for (int t = 0; t < B; ++t) sh[t] = &shapes[idx[start + t]];
             if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) return rc;
-            std::vector<double> e(B), gram;
+            std::vector<double> e(B), gram, wts;
             std::vector<int32_t> st(B);
-            if ((rc = davidson_batch(ctx, b, e.data(), st.data(), sink ? &gram : nullptr)) != MBEFCI_OK) return rc;
+            RdmOut ro;
+            if (sink && sink->device()) {
+                wts.resize(B);
+                for (int t = 0; t < B; ++t) wts[t] = sink->weight(idx[start + t]);
+                ro.w = wts.data();
+            } else if (sink) {
+                ro.gram = &gram;
+            }
+            if ((rc = davidson_batch(ctx, b, e.data(), st.data(), sink ? &ro : nullptr)) != MBEFCI_OK) return rc;
             for (int t = 0; t < B; ++t) {
                 energies[idx[start + t]] = e[t];
                 status[idx[start + t]] = st[t];
                 failed |= st[t] != MBEFCI_TUPLE_OK;
-                if (sink) sink->take(idx[start + t], shapes[idx[start + t]], gram.data() + (size_t)t * cp.NP * cp.NP,
-                                     cp.NP);
+                if (sink && !sink->device())
+                    sink->take(idx[start + t], shapes[idx[start + t]], gram.data() + (size_t)t * cp.NP * cp.NP, cp.NP);
             }
         }
     }
@@ -757,6 +813,68 @@ void children(const Result::Order &prev, const std::vector<int> &X, double tau, 
                                                       out.begin() + i * k);
 }
 
+// Pi-pruning (Sec. 3, Table 2): a tuple holds both components of every
+// degenerate pair or neither.
+bool pi_complete(uint64_t m, const std::vector<std::pair<int, int>> &pi) {
+    for (const auto &pr : pi)
+        if (((m >> pr.first) & 1u) != ((m >> pr.second) & 1u)) return false;
+    return true;
+}
+
+// Lexicographic rows of k orbitals from sorted, unique masks.
+void rows_from_masks(std::vector<uint64_t> &masks, int k, std::vector<int16_t> &out) {
+    std::sort(masks.begin(), masks.end());
+    masks.erase(std::unique(masks.begin(), masks.end()), masks.end());
+    std::vector<int16_t> rows(masks.size() * k);
+    for (size_t i = 0; i < masks.size(); ++i) {
+        int j = 0;
+        for (uint64_t m = masks[i]; m; m &= m - 1) rows[i * k + j++] = (int16_t)__builtin_ctzll(m);
+    }
+    std::vector<size_t> ord(masks.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+        return std::lexicographical_compare(rows.begin() + a * k, rows.begin() + (a + 1) * k, rows.begin() + b * k,
+                                            rows.begin() + (b + 1) * k);
+    });
+    out.resize(rows.size());
+    for (size_t i = 0; i < ord.size(); ++i)
+        std::copy(rows.begin() + ord[i] * k, rows.begin() + (ord[i] + 1) * k, out.begin() + i * k);
+}
+
+// Order-k candidates under pi-pruning and screening: an unpaired orbital added
+// to an order-(k-1) tuple with |d_eps| >= tau_{k-1}, or a whole pair added to
+// an order-(k-2) tuple with |d_eps| >= tau_{k-2} (the empty tuple always
+// counts).  Without screening this reaches every pi-complete tuple.
+void pi_children(const std::vector<Result::Order> &orders, int k, const std::vector<int> &X,
+                 const std::vector<std::pair<int, int>> &pi, double a, std::vector<int16_t> &out) {
+    std::vector<char> paired(64, 0);
+    for (const auto &pr : pi) paired[pr.first] = paired[pr.second] = 1;
+    std::vector<uint64_t> masks;
+    if (k - 1 >= 1) {
+        const Result::Order &o = orders[k - 1];
+        const double tau = screen_threshold(a, k - 1);
+        for (size_t i = 0; i < o.dinc.size(); ++i) {
+            if (!(std::fabs(o.dinc[i]) >= tau)) continue;
+            const uint64_t mT = tuple_mask(o.tuples.data() + i * o.k, o.k);
+            for (int x : X)
+                if (!paired[x] && !(mT >> x & 1)) masks.push_back(mT | ((uint64_t)1 << x));
+        }
+    }
+    if (k - 2 >= 0) {
+        const Result::Order &o = orders[k - 2];
+        const double tau = screen_threshold(a, k - 2);
+        const size_t nt = k - 2 == 0 ? 1 : o.dinc.size();
+        for (size_t i = 0; i < nt; ++i) {
+            if (k - 2 > 0 && !(std::fabs(o.dinc[i]) >= tau)) continue;
+            const uint64_t mT = k - 2 == 0 ? 0 : tuple_mask(o.tuples.data() + i * o.k, o.k);
+            for (const auto &pr : pi)
+                if (!(mT >> pr.first & 1) && !(mT >> pr.second & 1))
+                    masks.push_back(mT | ((uint64_t)1 << pr.first) | ((uint64_t)1 << pr.second));
+        }
+    }
+    rows_from_masks(masks, k, out);
+}
+
 // Eq. 3 for one tuple: subtuples in (size, lexicographic) order from 0.0.
 double increment(const int16_t *S, int k, double eps, const std::unordered_map<uint64_t, double> &dinc) {
     double acc = 0.0;
@@ -789,15 +907,34 @@ mbefci_status run_planner(mbefci_ctx *ctx, EnergyFn energy, Result &R) {
     for (int k = 0; k <= kmax; ++k) {
         Result::Order o;
         o.k = k;
+        const bool pi = !ctx->pi.empty();
         if (k == 0) {
             o.tuples.clear();
         } else if (k == 1 || ctx->opt.a <= 0.0) {
             combinations(ctx->X, k, o.tuples);
+            if (pi) {   // keep the pi-complete tuples, in the same order
+                size_t w = 0;
+                for (size_t i = 0; i < o.tuples.size() / k; ++i)
+                    if (pi_complete(tuple_mask(o.tuples.data() + i * k, k), ctx->pi)) {
+                        std::copy(o.tuples.begin() + i * k, o.tuples.begin() + (i + 1) * k, o.tuples.begin() + w * k);
+                        ++w;
+                    }
+                o.tuples.resize(w * k);
+            }
+        } else if (pi) {
+            pi_children(R.orders, k, ctx->X, ctx->pi, ctx->opt.a, o.tuples);
         } else {
             children(R.orders.back(), ctx->X, screen_threshold(ctx->opt.a, k - 1), o.tuples);
         }
         const int64_t nt = k == 0 ? 1 : (int64_t)(o.tuples.size() / k);
-        if (nt == 0) break;
+        if (nt == 0) {
+            // under pi-pruning a pair added to the order before may still follow
+            if (pi && !R.orders.back().eps.empty()) {
+                R.orders.push_back(std::move(o));
+                continue;
+            }
+            break;
+        }
         const double t0 = now_ms();
         o.eps.assign(nt, 0.0);
         o.status.assign(nt, 0);
@@ -898,6 +1035,8 @@ std::vector<std::vector<int64_t>> adjoint_weights(const Result &R) {
     return w;
 }
 
+// Host accumulation of Gram matrices with integer weights (one tuple's
+// density matrices, mbefci_tuple_rdm).
 struct GradSink : RdmSink {
     int n;
     const std::vector<int64_t> *w;
@@ -907,6 +1046,94 @@ struct GradSink : RdmSink {
         if (wi != 0.0) accumulate_rdm(n, ts, G, NP, wi, gh, ge);
     }
 };
+
+// Device embedding with the weight of each tuple of the list being solved.
+struct WeightSink : RdmSink {
+    const std::vector<double> *w;
+    bool device() const override { return true; }
+    double weight(int64_t index) const override { return (*w)[index]; }
+};
+
+// Gram matrices of one order kept on the host until the weights are known.
+struct StoreSink : RdmSink {
+    std::vector<std::vector<double>> G;
+    std::vector<TupleShape> shape;
+    std::vector<int> NP;
+    void take(int64_t index, const TupleShape &ts, const double *g, int np) override {
+        G[index].assign(g, g + (size_t)np * np);
+        shape[index] = ts;
+        NP[index] = np;
+    }
+};
+
+// Davidson tolerances of a density-matrix pass: density matrices are first
+// order in the residual, so |r| <= 1e-9 (and |d theta| <= 1e-12) whatever the
+// energy-only settings are.
+struct TightTol {
+    mbefci_ctx *ctx;
+    mbefci_options saved;
+    explicit TightTol(mbefci_ctx *c) : ctx(c), saved(c->opt) {
+        ctx->opt.r_tol = std::min(ctx->opt.r_tol, 1e-9);
+        ctx->opt.e_tol = std::min(ctx->opt.e_tol, 1e-12);
+        ctx->opt.max_iter = std::max(ctx->opt.max_iter, 1000);
+    }
+    ~TightTol() { ctx->opt = saved; }
+};
+
+// The device gradient accumulators (n^2 + n^4 doubles) at the end of the
+// caller's workspace, cleared; *wsb shrinks to the part left for batches.
+mbefci_status grad_region(mbefci_ctx *ctx, void *ws, size_t *wsb) {
+    const size_t n2 = (size_t)ctx->norb * ctx->norb, n4 = n2 * n2;
+    const size_t bytes = align256(8 * n2) + align256(8 * n4);
+    if (!ws || *wsb < bytes + ((size_t)1 << 20))
+        return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the gradient accumulators (" +
+                                            std::to_string(bytes) + " bytes)");
+    const size_t off = (*wsb - bytes) / 256 * 256;
+    ctx->d_gh = reinterpret_cast<double *>(static_cast<char *>(ws) + off);
+    ctx->d_ge = reinterpret_cast<double *>(static_cast<char *>(ws) + off + align256(8 * n2));
+    HIPCHK(hipMemsetAsync(ctx->d_gh, 0, bytes, ctx->stream));
+    *wsb = off;
+    return MBEFCI_OK;
+}
+
+// Device accumulators added into host arrays gh [n^2], ge [n^4].
+mbefci_status grad_fetch(mbefci_ctx *ctx, std::vector<double> &gh, std::vector<double> &ge) {
+    const size_t n2 = (size_t)ctx->norb * ctx->norb, n4 = n2 * n2;
+    std::vector<double> dh(n2), de(n4);
+    HIPCHK(hipMemcpyAsync(dh.data(), ctx->d_gh, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(de.data(), ctx->d_ge, 8 * n4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->d_gh = ctx->d_ge = nullptr;
+    gh.resize(n2, 0.0);
+    ge.resize(n4, 0.0);
+    for (size_t i = 0; i < n2; ++i) gh[i] += dh[i];
+    for (size_t i = 0; i < n4; ++i) ge[i] += de[i];
+    return MBEFCI_OK;
+}
+
+// grad_eri in the layout the integrals were given in: the full array, or per
+// packed element the sum over its distinct equivalent index quadruples.
+void write_grad(const mbefci_ctx *ctx, const std::vector<double> &gh, const std::vector<double> &ge, double gE,
+                double *grad_h1, double *grad_eri) {
+    const int n = ctx->norb;
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    for (size_t i = 0; i < n2; ++i) grad_h1[i] = gE * gh[i];
+    if (ctx->eri_layout == MBEFCI_ERI_FULL) {
+        for (size_t i = 0; i < n4; ++i) grad_eri[i] = gE * ge[i];
+        return;
+    }
+    const size_t np = n2 / 2 + (size_t)n / 2 + (n % 2 ? 1 : 0);   // n (n + 1) / 2
+    std::fill(grad_eri, grad_eri + np * (np + 1) / 2, 0.0);
+    auto pr = [](int p, int q) -> size_t { return p >= q ? (size_t)p * (p + 1) / 2 + q : (size_t)q * (q + 1) / 2 + p; };
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r)
+                for (int s2 = 0; s2 < n; ++s2) {
+                    const size_t P = pr(p, q), R = pr(r, s2);
+                    const size_t k = P >= R ? P * (P + 1) / 2 + R : R * (R + 1) / 2 + P;
+                    grad_eri[k] += gE * ge[(((size_t)p * n + q) * n + r) * n + s2];
+                }
+}
 
 }  // namespace
 
@@ -923,12 +1150,12 @@ void mbefci_default_options(mbefci_options *o) {
     o->max_order = 0;
     o->e_tol = 1e-11;
     o->r_tol = 1e-6;
-    o->max_iter = 200;
+    o->max_iter = 1000;
     o->max_space = 12;
     o->pspace = kPsp;
     o->linked_rows = 1;
     o->batched = 1;
-    o->keep_vectors = 0;
+    o->gradient = 0;
     o->profile = 0;
 }
 
@@ -982,6 +1209,19 @@ mbefci_status mbefci_set_hamiltonian(mbefci_ctx *ctx, int32_t n, const double *h
     std::vector<double> full(n4);
     if (layout == MBEFCI_ERI_FULL) {
         std::memcpy(full.data(), eri, n4 * sizeof(double));
+        // 8-fold symmetry: the kernels read one element per orbit
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q)
+                for (int r = 0; r < n; ++r)
+                    for (int s2 = 0; s2 < n; ++s2) {
+                        auto at = [&](int a, int b, int c, int d) { return eri[(((size_t)a * n + b) * n + c) * n + d]; };
+                        const double v = at(p, q, r, s2);
+                        if (!std::isfinite(v)) return ctx->fail(MBEFCI_EINVAL, "non-finite eri");
+                        if (std::fabs(v - at(q, p, r, s2)) > 1e-12 || std::fabs(v - at(p, q, s2, r)) > 1e-12 ||
+                            std::fabs(v - at(r, s2, p, q)) > 1e-12)
+                            return ctx->fail(MBEFCI_EINVAL, "eri not 8-fold symmetric (pq|rs) = (qp|rs) = (pq|sr) = "
+                                                            "(rs|pq) within 1e-12");
+                    }
     } else if (layout == MBEFCI_ERI_PACKED8) {
         auto pr = [](int p, int q) { return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p; };
         for (int p = 0; p < n; ++p)
@@ -998,6 +1238,7 @@ mbefci_status mbefci_set_hamiltonian(mbefci_ctx *ctx, int32_t n, const double *h
     for (double v : full)
         if (!std::isfinite(v)) return ctx->fail(MBEFCI_EINVAL, "non-finite eri");
     ctx->norb = n;
+    ctx->eri_layout = layout;
     ctx->h.assign(h1, h1 + n2);
     ctx->eri.swap(full);
     ctx->e_const = e_const;
@@ -1049,7 +1290,29 @@ mbefci_status mbefci_set_spaces(mbefci_ctx *ctx, int32_t nalpha, int32_t nbeta, 
         }
     if ((int)ctx->ref.size() > kMaxActive)
         return ctx->fail(MBEFCI_ETOOLARGE, "reference space exceeds the active-orbital limit");
+    ctx->pi.clear();
     ctx->spaces_set = true;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_set_pi_pairs(mbefci_ctx *ctx, const int32_t *orbs, int32_t npairs) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (!ctx->spaces_set) return ctx->fail(MBEFCI_ESTATE, "set the spaces first");
+    if (npairs < 0 || (npairs > 0 && !orbs)) return ctx->fail(MBEFCI_EINVAL, "bad pair list");
+    std::vector<char> used(ctx->norb, 0);
+    std::vector<std::pair<int, int>> pi;
+    for (int i = 0; i < npairs; ++i) {
+        const int x = orbs[2 * i], y = orbs[2 * i + 1];
+        for (int p : {x, y}) {
+            if (p < 0 || p >= ctx->norb || !ctx->inX[p])
+                return ctx->fail(MBEFCI_EINVAL, "pair orbital " + std::to_string(p) + " is not an expansion orbital");
+            if (used[p]) return ctx->fail(MBEFCI_EINVAL, "orbital " + std::to_string(p) + " in two pairs");
+            used[p] = 1;
+        }
+        if (x == y) return ctx->fail(MBEFCI_EINVAL, "a pair needs two orbitals");
+        pi.emplace_back(std::min(x, y), std::max(x, y));
+    }
+    ctx->pi.swap(pi);
     return MBEFCI_OK;
 }
 
@@ -1061,7 +1324,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
     if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
     if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
-    if (o->linked_rows < 0 || o->linked_rows > 3) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..3");
+    if (o->linked_rows < 0 || o->linked_rows > 4) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..4");
     ctx->opt = *o;
     return MBEFCI_OK;
 }
@@ -1108,13 +1371,69 @@ mbefci_status mbefci_run(mbefci_ctx *ctx, void *ws, size_t wsb, mbefci_result **
     ctx->stats = mbefci_stats{};
     const double t0 = now_ms();
     auto res = std::make_unique<mbefci_result>();
+    const bool grad = ctx->opt.gradient != 0;
+    if (!grad) {
+        rc = run_planner(ctx,
+                         [&](int k, int64_t nt, const int16_t *tup, double *e, int32_t *st) {
+                             return solve_device(ctx, k, nt, tup, ws, wsb, e, st);
+                         },
+                         res->r);
+        ctx->stats.solve_ms = now_ms() - t0;
+        if (rc == MBEFCI_OK || rc == MBEFCI_ENOCONV) *out = res.release();
+        return rc;
+    }
+    // Forward run that also forms the gradient of the total (tuple set fixed).
+    // The adjoint weight of every tuple of the last order is 1 (no computed
+    // superset), so those density matrices are embedded on the device as they
+    // converge; the Gram matrices of the lower orders wait on the host until
+    // the tuple lists, and with them the weights w = (I + L^T)^-1 1, are known.
+    TightTol tight(ctx);
+    size_t wsb_run = wsb;
+    if ((rc = grad_region(ctx, ws, &wsb_run)) != MBEFCI_OK) return rc;
+    const int nX = (int)ctx->X.size();
+    const int kmax = ctx->opt.max_order > 0 ? std::min(ctx->opt.max_order, nX) : nX;
+    std::vector<std::unique_ptr<StoreSink>> stores;
     rc = run_planner(ctx,
                      [&](int k, int64_t nt, const int16_t *tup, double *e, int32_t *st) {
-                         return solve_device(ctx, k, nt, tup, ws, wsb, e, st);
+                         if (k == kmax) {
+                             std::vector<double> ones((size_t)nt, 1.0);
+                             WeightSink unit;
+                             unit.w = &ones;
+                             stores.emplace_back(nullptr);
+                             return solve_device(ctx, k, nt, tup, ws, wsb_run, e, st, &unit);
+                         }
+                         auto sk = std::make_unique<StoreSink>();
+                         sk->G.resize(nt);
+                         sk->shape.resize(nt);
+                         sk->NP.resize(nt, 0);
+                         mbefci_status r = solve_device(ctx, k, nt, tup, ws, wsb_run, e, st, sk.get());
+                         stores.push_back(std::move(sk));
+                         return r;
                      },
                      res->r);
+    if (rc != MBEFCI_OK && rc != MBEFCI_ENOCONV) {
+        ctx->d_gh = ctx->d_ge = nullptr;
+        return rc;
+    }
+    const auto w = adjoint_weights(res->r);
+    const int n = ctx->norb;
+    std::vector<double> gh((size_t)n * n, 0.0), ge((size_t)n * n * n * n, 0.0);
+    for (size_t oi = 0; oi < stores.size() && oi < w.size(); ++oi) {
+        if (!stores[oi]) continue;
+        StoreSink &sk = *stores[oi];
+        for (size_t i = 0; i < sk.G.size(); ++i) {
+            if (w[oi][i] != 0 && sk.NP[i] > 0) accumulate_rdm(n, sk.shape[i], sk.G[i].data(), sk.NP[i], (double)w[oi][i],
+                                                              gh.data(), ge.data());
+            std::vector<double>().swap(sk.G[i]);
+        }
+    }
+    mbefci_status rf = grad_fetch(ctx, gh, ge);
+    if (rf != MBEFCI_OK) return rf;
+    res->r.has_grad = true;
+    res->r.grad_h.swap(gh);
+    res->r.grad_eri.swap(ge);
     ctx->stats.solve_ms = now_ms() - t0;
-    if (rc == MBEFCI_OK || rc == MBEFCI_ENOCONV) *out = res.release();
+    *out = res.release();
     return rc;
 }
 
@@ -1243,37 +1562,48 @@ mbefci_status mbefci_string_tables(int32_t nA, int32_t nel, int64_t *n_strings, 
 mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double gE, void *ws, size_t wsb,
                               double *grad_h1, double *grad_eri) {
     if (!ctx || !res || !grad_h1 || !grad_eri) return MBEFCI_EINVAL;
-    mbefci_status rc = check_device(ctx);
-    if (rc != MBEFCI_OK) return rc;
+    if (!std::isfinite(gE)) return ctx->fail(MBEFCI_EINVAL, "non-finite gE");
+    if (!ctx->ham_set) return ctx->fail(MBEFCI_ESTATE, "no Hamiltonian set");
     const int n = ctx->norb;
     const size_t n2 = (size_t)n * n, n4 = n2 * n2;
-    std::vector<double> gh(n2, 0.0), ge(n4, 0.0);
-    const auto w = adjoint_weights(res->r);
+    if (res->r.has_grad) {   // formed by the forward run
+        if (res->r.grad_h.size() != n2 || res->r.grad_eri.size() != n4)
+            return ctx->fail(MBEFCI_ESTATE, "result was computed for another orbital count");
+        write_grad(ctx, res->r.grad_h, res->r.grad_eri, gE, grad_h1, grad_eri);
+        return MBEFCI_OK;
+    }
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
     const double t0 = now_ms();
     ctx->stats = mbefci_stats{};
+    TightTol tight(ctx);
+    size_t wsb_run = wsb;
+    if ((rc = grad_region(ctx, ws, &wsb_run)) != MBEFCI_OK) return rc;
+    const auto w = adjoint_weights(res->r);
     for (size_t oi = 0; oi < res->r.orders.size(); ++oi) {
         const auto &o = res->r.orders[oi];
-        // tuples with a non-zero weight only
+        // tuples with a non-zero weight only, solved again and embedded on the device
         std::vector<int16_t> tl;
-        std::vector<int64_t> wl;
+        std::vector<double> wl;
         for (size_t i = 0; i < o.eps.size(); ++i)
             if (w[oi][i] != 0) {
                 tl.insert(tl.end(), o.tuples.begin() + i * o.k, o.tuples.begin() + (i + 1) * o.k);
-                wl.push_back(w[oi][i]);
+                wl.push_back((double)w[oi][i]);
             }
         if (wl.empty()) continue;
         std::vector<double> e(wl.size());
         std::vector<int32_t> st(wl.size());
-        GradSink sink;
-        sink.n = n;
+        WeightSink sink;
         sink.w = &wl;
-        sink.gh = gh.data();
-        sink.ge = ge.data();
-        rc = solve_device(ctx, o.k, (int64_t)wl.size(), tl.data(), ws, wsb, e.data(), st.data(), &sink);
-        if (rc != MBEFCI_OK) return rc;
+        rc = solve_device(ctx, o.k, (int64_t)wl.size(), tl.data(), ws, wsb_run, e.data(), st.data(), &sink);
+        if (rc != MBEFCI_OK) {
+            ctx->d_gh = ctx->d_ge = nullptr;
+            return rc;
+        }
     }
-    for (size_t i = 0; i < n2; ++i) grad_h1[i] = gE * gh[i];
-    for (size_t i = 0; i < n4; ++i) grad_eri[i] = gE * ge[i];
+    std::vector<double> gh, ge;
+    if ((rc = grad_fetch(ctx, gh, ge)) != MBEFCI_OK) return rc;
+    write_grad(ctx, gh, ge, gE, grad_h1, grad_eri);
     ctx->stats.solve_ms = now_ms() - t0;
     return MBEFCI_OK;
 }
@@ -1285,6 +1615,7 @@ mbefci_status mbefci_tuple_rdm(mbefci_ctx *ctx, int32_t order, const int16_t *tu
     const size_t n2 = (size_t)n * n;
     std::memset(gamma, 0, 8 * n2);
     std::memset(Gamma, 0, 8 * n2 * n2);
+    TightTol tight(ctx);
     std::vector<int64_t> w1{1};
     GradSink sink;
     sink.n = n;

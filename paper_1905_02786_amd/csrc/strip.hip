@@ -454,6 +454,19 @@ bool linked_fits(const ParamLayout &pl, int64_t Na, int nel) {
            linked_lds_gat(pl, Na) <= 160 * 1024 && Na < (1 << 24);
 }
 
+// LDS of the diagonal-on-vector-ALU kernel: sigma strip [Na + 1][16], D of
+// the two halves' pairs [2][2][Kpad][16], the A rows [P][row length] and the
+// staged diagonal-sum rows [2][2][row length].
+static size_t linked_lds_dv(const ParamLayout &pl, int64_t Na) {
+    const size_t rl = (size_t)linked_row_len(pl.Kpad);
+    return sizeof(double) * ((size_t)(Na + 1) * kStrip + 4 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 4) * rl);
+}
+
+bool linked_dv_fits(const ParamLayout &pl, int64_t Na, int nel) {
+    return pl.nA >= 4 && pl.nA <= kMaxActive && nel * (pl.nA - nel) <= kLinkedRows &&
+           linked_lds_dv(pl, Na) <= 160 * 1024 && Na < (1 << 24);
+}
+
 // The per-tuple A table.  Row r holds twice the stored 1/2 (pq|rs) of pair
 // row r (strip pair order) against every pair column k, in the interleaved
 // column order: column k = 4 ks + kr sits at (ks / 2) * 8 + 2 kr + (ks & 1), so
@@ -919,6 +932,225 @@ __global__ __launch_bounds__(768) void k_sigma_linked_res(Batch b, VecRef cref, 
     }
 }
 
+// Diagonal-on-vector-ALU kernel: for strings with n (n_A - n) = 32
+// off-diagonal links (n_A = 12 at four or eight electrons of the spin) the
+// 32 row slots hold the off-diagonal links only, and the diagonal-sum row of
+// each string, (sum_{p in K} A_(pp)) D, is formed on the vector ALU from the
+// B operands the MFMA wave already holds: lane (kr, ar) sums the K steps
+// congruent to kr, and the four lane groups are added with row swaps.  The A
+// rows stay in LDS for the whole strip; for lack of room for a third set of
+// D tiles, eight waves run in two halves of four (one wave of each half per
+// SIMD) in ping-pong.  Pair q of the string order (lperm) belongs to half
+// q % 2, and in phase p (one barrier after each):
+//   * half p % 2 runs the MFMAs of pair p (wave 4z + 2g + h: row tile h of
+//     string g) and, in its h = 0 waves, the diagonal sum of string g;
+//   * the other half scatters its pair p - 1 from the MFMA registers and adds
+//     the two diagonal sums to their own strings' rows, writes D and the
+//     diagonal-sum row of its next pair p + 1 (values loaded two phases
+//     earlier), and loads the C values, diagonal-sum rows and A-row offsets of
+//     pair p + 3 and the scatter entries of pair p + 1.
+// One pair is scattered per phase, in pair order; the two strings of a pair
+// differ in at least three orbitals, so neither they nor any of their links
+// coincide, and every sigma entry gets its adds in a fixed order.  Host
+// tables per alpha string K, 32 slots each (row N_a: all discard): lrow =
+// byte offset of the slot's A row, lscat = byte offset of its target row in
+// the sigma strip (the linked string J, or the discard row N_a for unused
+// slots), bit 31 the alpha link sign, in the order of the MFMA output rows of
+// a lane (linked_scat_pos).
+template <int NA>
+__global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, VecRef sref, double shift,
+                                                         int skip_done) {
+    constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4;
+    constexpr int RL = (KS + 1) / 2 * 8;                      // A-table row length (linked_row_len)
+    constexpr uint32_t RLB = RL * sizeof(double);
+    constexpr uint32_t DB = KP * kStrip * sizeof(double);     // bytes of one string's D
+    constexpr int NDI = (2 * KP * kStrip + 255) / 256;        // D items per thread of a half
+    const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
+    int t, strip_id;
+    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int z = wu >> 2, lw = wu & 3, g = lw >> 1, h = lw & 1;   // half, wave in half, string, tile
+    const int th = tid & 255;                                      // thread in half
+    const int ar = lane & 15, kr = lane >> 4;
+    const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb;
+    const uint32_t B0 = (uint32_t)strip_id * kStrip;
+    const bool colok = B0 + ar < Nb;
+    extern __shared__ double lds[];
+    double *strip = lds;                                                // [Na + 1][16]
+    const uint32_t D0 = (Na + 1) * kStrip * (uint32_t)sizeof(double);   // D [2 halves][2][KP][16]
+    const uint32_t A0 = D0 + 4 * DB;                                    // A rows [P][RL]
+    const uint32_t G0 = A0 + P * RLB;                                   // diagonal-sum rows [2 halves][2][RL]
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const int32_t *perm = b.lperm;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
+                                                                        (int)(b.dim * sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+        b.la + (int64_t)t * b.la_stride, (short)0, (int)(linked_a_rows(P, Na) * RLB), 0x00020000);
+    const int tbytes = (int)((Na + 1) * kLinkedRows * sizeof(uint32_t));
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lrow), (short)0,
+                                                                        tbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(b.lscat), (short)0,
+                                                                        tbytes, 0x00020000);
+    // D items of a half: element j = th + 256 i of its D [2][KP][16] (string
+    // j / (16 KP), row (j / 16) % KP, column ar); wave-uniform string and
+    // presence, as in the resident-A kernel
+    uint32_t boff[NDI], bsg[NDI];
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) {
+        const int j = th + 256 * i, q = (j >> 4) % KP;
+        const uint32_t eb = (colok && j < 2 * KP * kStrip && q < P) ? b.pairB[(B0 + ar) * (uint32_t)P + q] : 0u;
+        const bool vb = (eb & kPairValid) != 0;
+        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
+        bsg[i] = vb ? (eb & kPairSign) : 0u;
+    }
+    auto item_on = [&](int i) { return 256 * (i + 1) <= 2 * KP * kStrip || 64 * lw + 256 * i < 2 * KP * kStrip; };
+    auto item_str = [&](int i) { return (64 * lw + 256 * i) / (KP * kStrip); };
+
+    const uint32_t rowC = Nb * (uint32_t)sizeof(double), rowT = kLinkedRows * (uint32_t)sizeof(uint32_t);
+    auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    auto str = [&](uint32_t q, int k) -> uint32_t { return (uint32_t)perm[2 * q + k]; };   // string k of pair q
+    auto crow = [&](uint32_t s) -> uint32_t { return s < Na ? s : 0u; };   // C row (dummy: any row)
+    auto trow = [&](uint32_t s) -> uint32_t { return s < Na ? s : Na; };   // table row (dummy: discard)
+    auto load_c = [&](uint32_t s, int i) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[i], crow(s) * rowC, 0));
+    };
+    auto load_row = [&](uint32_t s) -> uint32_t {   // A-row offset of this lane's slot 16 h + ar
+        return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u, trow(s) * rowT, 0);
+    };
+    auto load_scat = [&](uint32_t s, uint32_t (&e)[4]) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (uint32_t)(16 * h + 4 * kr) * 4u, trow(s) * rowT, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = v[k];
+    };
+    // diagonal-sum row of string s: 16 bytes per lane, lanes < RL / 2 of the
+    // h = 0 wave of each string
+    const bool dgl = h == 0 && lane < RL / 2;
+    auto load_dg = [&](uint32_t s) -> dbl2v {
+        const uint32_t r = (uint32_t)P + (s < Na ? s : 0u);
+        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, r * RLB, 0));
+    };
+    auto dval = [&](double v, int i) -> double {
+        return __hiloint2double(__double2hiint(v) ^ (int)bsg[i], __double2loint(v));
+    };
+    const uint32_t dw = D0 + (uint32_t)z * 2 * DB + (uint32_t)th * (uint32_t)sizeof(double);
+    const uint32_t dr = D0 + (uint32_t)(2 * z + g) * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
+    const uint32_t gd = G0 + (uint32_t)(2 * z + g) * RLB;                  // staged diagonal-sum row of string g
+    const uint32_t gw = gd + (uint32_t)lane * 16u;
+    const uint32_t ar8 = (uint32_t)ar * (uint32_t)sizeof(double);
+
+    for (uint32_t i = tid; i < (Na + 1) * kStrip; i += 512) strip[i] = 0.0;
+    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 512)
+        *reinterpret_cast<dbl2v *>(lds_at(A0 + 16u * i)) =
+            __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * i, 0, 0));
+    // prologue: half 0 stages pair 0 and holds the loads of pair 2; half 1
+    // holds the loads of pair 1 (staged in its first phase)
+    uint32_t ra = 0u, rap = 0u, e[4];
+    double cb[NDI];
+    dbl2v dg = {0.0, 0.0};
+    if (z == 0) {
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(load_c(str(0, item_str(i)), i), i);
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = load_dg(str(0, g));
+        ra = load_row(str(0, g));
+        load_scat(str(0, g), e);
+    } else {
+        load_scat(Na, e);
+    }
+    const uint32_t q0 = z == 0 ? 2u : 1u;
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) cb[i] = item_on(i) ? load_c(str(q0, item_str(i)), i) : 0.0;
+    if (dgl) dg = load_dg(str(q0, g));
+    rap = load_row(str(q0, g));
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    double dsum = 0.0;     // diagonal sum of this wave's string (h = 0 waves), column ar
+    uint32_t dtgt = Na;    // its target row (the string itself; the discard row before the first pair)
+    __syncthreads();
+
+    // MFMAs of pair q, and in the h = 0 waves the diagonal sum of string g
+    auto mphase = [&](uint32_t q) {
+        double bv[KS], af[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = *lds_at(dr + ks * 4u * kStrip * (uint32_t)sizeof(double));
+        const uint32_t arow = A0 + ra + (uint32_t)kr * 16u;
+#pragma unroll
+        for (int j = 0; j < KS / 2; ++j) {
+            const dbl2v v = *reinterpret_cast<const dbl2v *>(lds_at(arow + 64u * j));
+            af[2 * j] = v[0];
+            af[2 * j + 1] = v[1];
+        }
+        if (KS & 1) af[KS - 1] = *lds_at(arow + 64u * (KS / 2));
+        dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
+        acc = a;
+        if (h == 0) {
+            // lane (kr, ar): sum over k = 4 ks + kr of G_k D_k(ar), in ks order
+            const uint32_t grow = gd + (uint32_t)kr * 16u;
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < KS / 2; ++j) {
+                const dbl2v v = *reinterpret_cast<const dbl2v *>(lds_at(grow + 64u * j));
+                s = __builtin_fma(v[0], bv[2 * j], s);
+                s = __builtin_fma(v[1], bv[2 * j + 1], s);
+            }
+            if (KS & 1) s = __builtin_fma(*lds_at(grow + 64u * (KS / 2)), bv[KS - 1], s);
+            dsum = sum_over_kr(s);
+            dtgt = trow(str(q, g));
+        }
+    };
+    // phase p of the other half: scatter of pair p - 1 and its diagonal
+    // sums; D and diagonal-sum rows of pair p + 1; loads of pairs p + 1, p + 3
+    auto nphase = [&](uint32_t p) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            __builtin_amdgcn_ds_atomic_fadd_f64(
+                (__attribute__((address_space(3))) double *)(uintptr_t)((e[v] & 0x7FFFFFFFu) | ar8),
+                __hiloint2double(__double2hiint(acc[v]) ^ (int)(e[v] & kPairSign), __double2loint(acc[v])));
+        if (h == 0 && kr == 0)
+            __builtin_amdgcn_ds_atomic_fadd_f64(
+                (__attribute__((address_space(3))) double *)(uintptr_t)(dtgt * 128u | ar8), dsum);
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(cb[i], i);
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = dg;
+        ra = rap;
+        load_scat(str(p + 1, g), e);
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) cb[i] = load_c(str(p + 3, item_str(i)), i);
+        if (dgl) dg = load_dg(str(p + 3, g));
+        rap = load_row(str(p + 3, g));
+    };
+    // phases 0 .. 2k - 1 cover the last pair's scatter in phase lpairs
+    const uint32_t nph = (uint32_t)b.lpairs + 1;
+    if (z == 0) {
+        for (uint32_t p = 0; p < nph; p += 2) {
+            mphase(p);
+            __syncthreads();
+            nphase(p + 1);
+            __syncthreads();
+        }
+    } else {
+        for (uint32_t p = 0; p < nph; p += 2) {
+            nphase(p);
+            __syncthreads();
+            mphase(p + 1);
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = tid; i < Na * kStrip; i += 512) {
+        const uint32_t row = i / kStrip, col = i % kStrip;
+        if (B0 + col < Nb) {
+            const uint32_t d = row * Nb + B0 + col;
+            sg[d] = strip[i] + shift * c[d];
+        }
+    }
+}
+
 // The resident-A kernel (A rows in LDS, one twelve-wave workgroup in three
 // thirds) needs more LDS than the gathered-A kernel (four waves, A rows
 // loaded through the vector memory path, which they saturate).  It runs
@@ -937,7 +1169,10 @@ template <int NA>
 static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    if (use_resident(b))
+    if (b.linked_dv)
+        hipLaunchKernelGGL(k_sigma_linked_dv<NA>, grid, dim3(512), linked_lds_dv(b.pl, b.Na), s, b, c, sig, shift,
+                           skip);
+    else if (use_resident(b))
         hipLaunchKernelGGL(k_sigma_linked_res<NA>, grid, dim3(768), linked_lds_res(b.pl, b.Na), s, b, c, sig,
                            shift, skip);
     else
@@ -1007,7 +1242,12 @@ hipError_t init_strip_kernels() {
                             (const void *)k_sigma_linked_res<10>, (const void *)k_sigma_linked_gat<10>,
                             (const void *)k_sigma_linked_res<11>, (const void *)k_sigma_linked_gat<11>,
                             (const void *)k_sigma_linked_res<12>, (const void *)k_sigma_linked_gat<12>,
-                            (const void *)k_sigma_linked_res<13>, (const void *)k_sigma_linked_gat<13>};
+                            (const void *)k_sigma_linked_res<13>, (const void *)k_sigma_linked_gat<13>,
+                            (const void *)k_sigma_linked_dv<4>,  (const void *)k_sigma_linked_dv<5>,
+                            (const void *)k_sigma_linked_dv<6>,  (const void *)k_sigma_linked_dv<7>,
+                            (const void *)k_sigma_linked_dv<8>,  (const void *)k_sigma_linked_dv<9>,
+                            (const void *)k_sigma_linked_dv<10>, (const void *)k_sigma_linked_dv<11>,
+                            (const void *)k_sigma_linked_dv<12>, (const void *)k_sigma_linked_dv<13>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "random_hamiltonian", "config_plain", "config_sweep",
-    "config_hubbard", "config_large", "small_problem", "hubbard_site",
+    "config_hubbard", "config_large", "small_problem", "hubbard_site", "config_weak",
 ]
 
 
@@ -47,6 +47,9 @@ class Problem:
     max_order: int = 0       # <= 0 means full order |X|
     e_const: float = 0.0
     meta: dict = field(default_factory=dict)
+    # degenerate orbital pairs (x, y) of the expansion space whose components
+    # enter a tuple only together (pi-pruning); empty: no pruning
+    pi_pairs: list = field(default_factory=list)
 
     @property
     def norb(self) -> int:
@@ -193,3 +196,11 @@ def small_problem(n: int, nalpha: int, nbeta: int, ref, nfrozen: int = 0, nvec: 
     h, eri = random_hamiltonian(-1.0 + 0.3 * np.arange(n), offdiag_std, nvec, vec_std, seed)
     return Problem(f"small-n{n}-{nalpha}a{nbeta}b-s{seed}", h, eri, nalpha, nbeta, nfrozen,
                    sorted(ref), a=a, max_order=max_order, e_const=e_const, meta={"seed": seed})
+
+
+def config_weak(seed: int = 1) -> Problem:
+    """Weakly coupled 9-orbital problem (3a+3b, [Pi] = {2, 3}, off-diagonal h
+    N(0, 0.005), 6 vectors N(0, 0.01)) on which the screening of a = 5.0 removes
+    tuples from order 4 on; orders 1..5."""
+    return small_problem(9, 3, 3, [2, 3], nvec=6, seed=seed, a=5.0, vec_std=0.01, offdiag_std=0.005,
+                         max_order=5)

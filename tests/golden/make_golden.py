@@ -11,6 +11,9 @@ Outputs (JSON, one file per workload) next to this script:
   sweep_sample.json    sampled CASCI energies of the 24-orbital order sweep
   large_sample.json    sampled CASCI energies of the 60-orbital problem
   gradients.npz        MBE gradients (h, (pq|rs)) at orders 2, 4 and full
+  pi_pruned.json       MBE of the plain problem with pi-pruning (a = 0, 5.0)
+  screened_weak.json   MBE of a weakly coupled problem whose screening (a = 5.0)
+                       removes tuples from order 4 on
   class_samples.json   CASCI energies and the gap to the second root of one or
                        two tuples of every large shape class of the order sweep
                        (also at integral scale std 0.1) and of the 60-orbital
@@ -143,6 +146,39 @@ def gradients():
             print(key, f"{time.time() - t:.1f}s", flush=True)
     np.savez_compressed(os.path.join(HERE, "gradients.npz"), **out)
     print("wrote gradients.npz", flush=True)
+
+
+def pi_pruned():
+    """Full-order MBE of the plain 10-orbital problem with pi-pruning over the
+    expansion pairs (5, 6) and (7, 8), without screening and with a = 5.0."""
+    out = {}
+    cache = {}
+    for a in (0.0, 5.0):
+        P = synth.config_plain(0)
+        P.pi_pairs = [(5, 6), (7, 8)]
+        P.a = a
+
+        def energy(S):
+            if S not in cache:
+                cache[S] = fci.casci_energy(P, S)
+            return cache[S]
+        t = time.time()
+        res = mbe.run(P, energy=energy)
+        out["a%g" % a] = mbe_json(P, res, {"seconds": time.time() - t})
+    out["pairs"] = [[5, 6], [7, 8]]
+    out["fci"] = cache[tuple(synth.config_plain(0).expansion_space())]
+    write("pi_pruned.json", out)
+
+
+def screened():
+    P = synth.config_weak()
+    t = time.time()
+    res = mbe.run(P)
+    band = []
+    for o in res.orders[1:]:
+        tau = mbe.screen_threshold(P.a, o.k)
+        band += [[o.k, list(tt), d] for tt, d in zip(o.tuples, o.dinc) if abs(abs(d) - tau) < 1e-10]
+    write("screened_weak.json", mbe_json(P, res, {"guard_band": band, "seconds": time.time() - t}))
 
 
 def _eig2(P, S):

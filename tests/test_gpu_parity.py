@@ -74,42 +74,76 @@ SIGMA_CASES = [
     ("sweep", ()), ("sweep", (1,)), ("sweep", (9, 13)), ("sweep", (1, 2, 10)),
     ("sweep", (9, 10, 11, 12, 13)), ("large", (10, 11)),
     ("openshell", ()), ("openshell", (1, 5)), ("openshell", (1, 4, 5, 6, 7)),
+    # the order sweep's largest classes: n_A = 11 with 4 and 5 alpha electrons
+    ("sweep", (1, 9, 10, 11, 12)), ("sweep", (1, 2, 9, 10, 11)),
+    # the 60-orbital problem at n_A = 12: (8e,12o), (10e,12o), (12e,12o), and n_A = 13
+    ("large", (10, 11, 12, 13)), ("large", (0, 10, 11, 12)), ("large", (0, 1, 10, 11)),
+    ("large", (10, 11, 12, 13, 14)),
 ]
+
+_PROBLEM_CACHE = {}
+_REF_CACHE = {}
+
+
+def _problem(name):
+    if name not in _PROBLEM_CACHE:
+        _PROBLEM_CACHE[name] = PROBLEMS[name]()
+    return _PROBLEM_CACHE[name]
+
+
+def _sigma_reference(name, S):
+    """Oracle sigma of seeded vectors (one above 200000 determinants) in the
+    library's determinant signs, and the oracle diagonal where it is dense;
+    computed once per case and shared by the variants."""
+    key = (name, S)
+    if key not in _REF_CACHE:
+        P = _problem(name)
+        sp = fci.cas_space(P, S)
+        rng = np.random.default_rng(sum(S) + 7)
+        print(f"oracle sigma {name} {S} dim {sp.dim} ...", flush=True)
+        c = rng.standard_normal((2 if sp.dim <= 200000 else 1, sp.dim))
+        sg = core_order_signs(sp)
+        if sp.dim <= 2000:
+            H = fci.hamiltonian_matrix(P, sp)
+            ref = sg * ((sg * c) @ H.T)
+            ref_diag = np.diag(H)
+        else:
+            ref = np.stack([sg * fci.matvec(P, sp, sg * v) for v in c])
+            # sampled diagonal elements <I|H|I> (Slater-Condon, E_const included)
+            from oracle import native
+            L = native.lib()
+            h = np.ascontiguousarray(P.h)
+            eri = np.ascontiguousarray(P.eri)
+            ref_diag = {}
+            for I in rng.choice(sp.dim, size=6, replace=False):
+                a, b = int(sp.alist[I // len(sp.blist)]), int(sp.blist[I % len(sp.blist)])
+                ref_diag[int(I)] = P.e_const + L.sc_element(P.norb, native.ptr(h), native.ptr(eri), a, b, a, b)
+        _REF_CACHE[key] = (sp, c, ref, ref_diag)
+    return _REF_CACHE[key]
 
 
 # (sigma_variant, linked_rows): column strip with linked rows where n_A >= 9
 # (the default), column strip on all pair rows, linked rows wherever they fit
-# with the A rows gathered (2) or resident in LDS (3), materialised W
-@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (1, 2), (1, 3), (2, 1)])
+# with the A rows gathered (2) or resident in LDS (3), the form with the
+# diagonal sums on the vector ALU wherever it fits (4), materialised W
+@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (1, 2), (1, 3), (1, 4), (2, 1)])
 @pytest.mark.parametrize("name,S", SIGMA_CASES)
 def test_hdiag_and_sigma_match_oracle(ws, name, S, variant, linked):
-    P = PROBLEMS[name]()
+    P = _problem(name)
     ctx = _ctx(P, sigma_variant=variant, linked_rows=linked)
-    sp = fci.cas_space(P, S)
+    sp, c, ref, ref_diag = _sigma_reference(name, S)
     print(f"case {name} {S} dim {sp.dim} variant {variant} linked {linked}", flush=True)
-    rng = np.random.default_rng(sum(S) + 7)
-    c = rng.standard_normal((2, sp.dim))
-    sg = core_order_signs(sp)
-    if sp.dim <= 2000:
-        H = fci.hamiltonian_matrix(P, sp)
-        ref = sg * ((sg * c) @ H.T)
-        ref_diag = np.diag(H)
-    else:
-        ref = np.stack([sg * fci.matvec(P, sp, sg * v) for v in c])
-        ref_diag = None
     ct = torch.tensor(c, device="cuda:0")
     sig = ctx.tuple_sigma(len(S), S, ct, ws).cpu().numpy()
     scale = max(1.0, np.abs(ref).max())
     assert np.abs(sig - ref).max() <= 1e-12 * scale, np.abs(sig - ref).max()
     hd = ctx.tuple_hdiag(len(S), S, ws).cpu().numpy()
-    if ref_diag is not None:
-        assert np.abs(hd - ref_diag).max() <= 1e-12 * max(1.0, np.abs(ref_diag).max())
+    if isinstance(ref_diag, dict):
+        # sampled determinants
+        for I, v in ref_diag.items():
+            assert abs(hd[I] - v) <= 1e-12 * max(1.0, abs(v))
     else:
-        # diagonal element check on sampled determinants: <e_I|H|e_I>
-        for I in rng.choice(sp.dim, size=4, replace=False):
-            e = np.zeros(sp.dim)
-            e[I] = 1.0
-            assert abs(hd[I] - fci.matvec(P, sp, e)[I]) <= 1e-12 * max(1.0, abs(hd[I]))
+        assert np.abs(hd - ref_diag).max() <= 1e-12 * max(1.0, np.abs(ref_diag).max())
 
 
 def test_sigma_is_symmetric_full_space(ws):
@@ -336,3 +370,45 @@ def test_edge_cases(ws):
     P1 = synth.small_problem(5, 1, 0, [0], nvec=3, seed=1)
     e, st = _ctx(P1).solve_tuples(4, [(1, 2, 3, 4)], ws)
     assert abs(e[0] - fci.casci_energy(P1, (1, 2, 3, 4))) <= 1e-10
+
+
+def test_screening_removes_tuples_on_device(ws):
+    """A weakly coupled problem on which a = 5.0 screens out 5 of the 35
+    order-4 candidates and 11 of the 21 order-5 ones: the device run, with its
+    own energies, takes the same screening decisions as the oracle run with
+    the oracle's energies (identical lists), and every |d_eps| within 1e-10 of
+    its threshold (the guard band) is reported; the stored run has none."""
+    with open(os.path.join(GOLDEN, "screened_weak.json")) as f:
+        g = json.load(f)
+    P = synth.config_weak()
+    res = _ctx(P).run(ws)
+    counts = [len(o.tuples) for o in res.orders]
+    assert counts == [len(o["tuples"]) for o in g["orders"]] == [1, 7, 21, 35, 30, 10]
+    _check_against_golden(res, g)
+    band = []
+    for o in res.orders[1:]:
+        tau = ombe.screen_threshold(P.a, o.k)
+        band += [(o.k, tuple(int(x) for x in t), float(d)) for t, d in zip(o.tuples, o.dinc)
+                 if abs(abs(d) - tau) < 1e-10]
+    print(f"screened counts {counts}; device guard band {band}; stored guard band {g['guard_band']}")
+    assert not band and not g["guard_band"]
+
+
+@pytest.mark.parametrize("a", [0.0, 5.0])
+def test_pi_pruned_mbe_matches_oracle(ws, a):
+    """Pi-pruning on the device run (pairs (5, 6), (7, 8) of the plain problem):
+    the tuple lists, energies, increments and sums of the oracle's run, and at
+    full order still the FCI energy (Eq. 3 telescopes over any computed set
+    that contains the top tuple)."""
+    path = os.path.join(GOLDEN, "pi_pruned.json")
+    if not os.path.exists(path):
+        pytest.skip("pi_pruned.json not generated")
+    with open(path) as f:
+        g = json.load(f)
+    P = synth.config_plain(0)
+    P.pi_pairs = [tuple(p) for p in g["pairs"]]
+    P.a = a
+    res = _ctx(P).run(ws)
+    _check_against_golden(res, g["a%g" % a])
+    print(f"a = {a}: counts {[len(o.tuples) for o in res.orders]}")
+    assert abs(res.total - g["fci"]) <= 1e-9

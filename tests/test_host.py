@@ -4,6 +4,7 @@ planner (tuple generation, screening, Eq. 3 assembly) reproduces the oracle's
 bit for bit when both are fed the same tuple energies, and bad input is
 rejected."""
 import itertools
+import json
 import math
 import os
 import re
@@ -149,11 +150,22 @@ def test_invalid_inputs_rejected():
         with pytest.raises(M.MBEFCIError):
             ctx.set_options(pspace=bad_psp)
     ctx.set_options(pspace=0)
-    for bad_lr in (-1, 4):
+    for bad_lr in (-1, 5):
         with pytest.raises(M.MBEFCIError):
             ctx.set_options(linked_rows=bad_lr)
-    for lr in (0, 1, 2, 3):
+    for lr in (0, 1, 2, 3, 4):
         ctx.set_options(linked_rows=lr)
+    # full-layout integrals must be 8-fold symmetric
+    asym = np.zeros((4,) * 4)
+    asym[0, 1, 2, 3] = 0.3
+    with pytest.raises(M.MBEFCIError) as e:
+        ctx.set_hamiltonian(h, asym)
+    assert e.value.code == -1
+    sym = np.zeros((4,) * 4)
+    for o in {(0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0),
+              (3, 2, 1, 0)}:
+        sym[o] = 0.3
+    ctx.set_hamiltonian(h, sym)
 
 
 class _FakeTensor:
@@ -199,3 +211,45 @@ def test_ctypes_structs_match_header():
         fields = _header_fields(hdr, cname)
         assert len(fields) >= 10, cname
         assert fields == [n for n, _ in cls._fields_], cname
+
+
+@pytest.mark.parametrize("a,seed", [(5.0, 0), (2.5, 1), (0.0, 2)])
+def test_pi_pruned_planner_matches_oracle_bitwise(a, seed):
+    """The library planner under pi-pruning (and screening) takes the oracle
+    planner's decisions on the same energy table: lists, increments, sums."""
+    n = 12
+    pairs = [(5, 6), (8, 9)]
+    P = synth.Problem("plan-pi", np.eye(n), np.zeros((n,) * 4), 4, 4, 1, [3, 4], a=a, max_order=7, pi_pairs=pairs)
+    eps = _table_energy(seed)
+    ref = ombe.run(P, energy=eps)
+    ctx = M.Context(device=None)
+    ctx.set_hamiltonian(P.h, P.eri)
+    ctx.set_spaces(P.nalpha, P.nbeta, P.nfrozen, P.ref)
+    ctx.set_pi_pairs(pairs)
+    ctx.set_options(a=a, max_order=7)
+    got = ctx.run_host(lambda k, tup: [eps(t) for t in tup] if k > 0 else [eps(())])
+    assert len(got.orders) == len(ref.orders)
+    for go, ro in zip(got.orders, ref.orders):
+        assert [tuple(int(x) for x in t) for t in go.tuples] == list(ro.tuples)
+        assert np.array_equal(go.dinc, np.array(ro.dinc))
+        assert go.order_sum == ro.order_sum
+    assert got.total == ref.total
+
+
+def test_pi_pruned_counts_table2_library():
+    """The library planner reproduces Table 2's pi-pruned counts (orders 1-6:
+    6, 21, 56, 120, 216, 336) on N2-like spaces without screening."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_counts.json")) as f:
+        t2 = json.load(f)["table2_pi_pruned_orders_1_6"]
+    n = 28
+    ctx = M.Context(device=None)
+    ctx.set_hamiltonian(np.eye(n), np.zeros((n,) * 4))
+    ctx.set_spaces(7, 7, 2, list(range(2, 10)))
+    ctx.set_pi_pairs([(12, 13), (14, 15), (18, 19), (20, 21), (24, 25), (26, 27)])
+    ctx.set_options(a=0.0, max_order=6)
+    got = ctx.run_host(lambda k, tup: np.zeros(len(tup)))
+    assert [len(o.tuples) for o in got.orders[1:]] == t2["counts"]
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_pi_pairs([(12, 13), (13, 14)])     # orbital in two pairs
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_pi_pairs([(3, 12)])                # reference orbital

@@ -437,3 +437,50 @@ def test_rdm_elements_equal_fock_space_operators(case):
     assert np.abs(g2.transpose(1, 0, 2, 3) - r2).max() > 1e-3
     # and the energy of the CAS follows from these elements
     assert abs(rdm.energy_from_rdms(P, r1, r2) - w[0]) < 1e-11
+
+
+def _n2_like(a):
+    """N2-like spaces of Table 2: 28 orbitals, 2 frozen, CAS(10,8) reference,
+    18 expansion orbitals of which 6 sigma and 6 degenerate pi pairs."""
+    pairs = [(12, 13), (14, 15), (18, 19), (20, 21), (24, 25), (26, 27)]
+    return synth.Problem("n2-like", np.zeros((28, 28)), np.zeros((1,)), 7, 7, 2, list(range(2, 10)), a=a,
+                         max_order=6, pi_pairs=pairs)
+
+
+@pytest.mark.parametrize("a", [0.0, 5.0])
+def test_pi_pruned_counts_table2(a):
+    """Pi-pruning counts of Table 2 (6, 21, 56, 120, 216, 336 for orders 1-6),
+    by the oracle's planner without screening and with screening whose
+    increments all exceed the thresholds (then the child rule must reach
+    every pi-complete tuple); the unpruned order 1 is the standard 18."""
+    with open(os.path.join(GOLDEN, "paper_counts.json")) as f:
+        t2 = json.load(f)["table2_pi_pruned_orders_1_6"]
+    P = _n2_like(a)
+    assert len(P.expansion_space()) == t2["standard_order1"] == 18
+    res = mbe.run(P, energy=lambda S: float(2 ** len(S)))
+    assert [len(o.tuples) for o in res.orders[1:]] == t2["counts"]
+    for o in res.orders[1:]:
+        assert all(mbe.pi_complete(S, P.pi_pairs) for S in o.tuples)
+
+
+def test_pi_pruning_screening_rule_on_handmade_table():
+    """Children under pi-pruning: unpaired orbitals join significant
+    order-(k-1) parents, whole pairs join significant order-(k-2) parents (the
+    empty tuple always)."""
+    P = synth.Problem("pi", np.zeros((5, 5)), np.zeros((1,)), 0, 0, 0, [], a=5.0, pi_pairs=[(1, 2)])
+    X = P.expansion_space()
+    assert X == [0, 1, 2, 3, 4]
+    orders = [mbe.Order(0, [()], [0.0], [0.0], 0.0)]
+    dinc = {(): 0.0}
+    o1 = mbe.candidates(P, 1, orders[0], dinc, orders)
+    assert o1 == [(0,), (3,), (4,)]
+    dinc.update({(0,): 1.0, (3,): 1e-12, (4,): 1.0})
+    orders.append(mbe.Order(1, o1, [0.0] * 3, [1.0, 1e-12, 1.0], 0.0))
+    o2 = mbe.candidates(P, 2, orders[1], dinc, orders)
+    # (3,) is negligible: (0,3), (3,4) come from (0,), (4,); the pair from {}
+    assert o2 == [(0, 3), (0, 4), (1, 2), (3, 4)]
+    dinc.update({(0, 3): 1e-12, (0, 4): 1e-12, (1, 2): 1.0, (3, 4): 1e-12})
+    orders.append(mbe.Order(2, o2, [0.0] * 4, [1e-12, 1e-12, 1.0, 1e-12], 0.0))
+    o3 = mbe.candidates(P, 3, orders[2], dinc, orders)
+    # from (1,2) + unpaired; pairs onto significant order-1 tuples (0,), (4,)
+    assert o3 == [(0, 1, 2), (1, 2, 3), (1, 2, 4)]
