@@ -64,7 +64,8 @@ enum {
     MBEFCI_TUPLE_OK = 0,        /* converged */
     MBEFCI_TUPLE_MAXITER = 1,   /* iteration limit reached */
     MBEFCI_TUPLE_NONFINITE = 2, /* NaN/Inf met in the iteration */
-    MBEFCI_TUPLE_STALLED = 3    /* correction vector fell inside the subspace before convergence */
+    MBEFCI_TUPLE_STALLED = 3,   /* correction vector fell inside the subspace before convergence */
+    MBEFCI_TUPLE_PENDING = 4    /* listed in an open (streamed) order, not solved yet */
 };
 
 typedef enum {
@@ -84,7 +85,13 @@ typedef struct {
     double e_tol;           /* Davidson: |theta - theta_prev| bound (default 1e-11) */
     double r_tol;           /* Davidson: residual 2-norm bound (default 1e-6; the Ritz value
                                then lies within about r_tol^2 / gap of the eigenvalue) */
-    int32_t max_iter;       /* Davidson iterations per tuple (default 1000) */
+    int32_t max_iter;       /* Davidson iterations per tuple in the first pass (default 300); a
+                               tuple that does not converge (iteration limit or stalled) is
+                               solved again in a second pass with a subspace of 32, no P space
+                               and max(10 max_iter, 3000) iterations, and a shape class whose
+                               first batch sends a quarter or more of its tuples there runs its
+                               remaining batches with those settings.  The status is that of the
+                               second pass. */
     int32_t max_space;      /* subspace vectors before restart, 2..32 (default 12) */
     int32_t batched;        /* 1: every tuple of a shape class in one batch of launches;
                                0: one tuple per launch sequence (the per-solve path) */
@@ -94,7 +101,7 @@ typedef struct {
                                it converges), kept in the result, so that mbefci_backward solves
                                nothing again.  Such a run, every backward pass and
                                mbefci_tuple_rdm converge each tuple to r_tol <= 1e-9 and
-                               e_tol <= 1e-12 (max_iter >= 1000) whatever the options say:
+                               e_tol <= 1e-12 whatever the options say:
                                density matrices are first order in the residual.  Needs n^2 + n^4
                                doubles of workspace beyond the batches. (default 0) */
     int32_t profile;        /* 1: time every sigma launch with HIP events (mbefci_get_stats) */
@@ -120,7 +127,12 @@ typedef struct {
                                gathered, 3 resident (each where it fits, else the other); 4 the
                                vector-ALU diagonal form wherever it fits.  Same result up to
                                rounding. */
-    int32_t reserved[4];
+    int32_t stream_last;    /* 1: mbefci_run solves orders 0 .. K-1 and only lists the last order K
+                               (its tuples generated, status MBEFCI_TUPLE_PENDING), which the
+                               caller then solves in slices with mbefci_order_solve and ends with
+                               mbefci_order_close: the same result as one call, for orders too
+                               large to solve in one go (default 0) */
+    int32_t reserved[3];
 } mbefci_options;
 
 typedef struct {
@@ -137,7 +149,23 @@ typedef struct {
     double solve_ms;            /* host wall time inside solve/run */
     int64_t gs_second_pass;     /* Davidson corrections that took two explicit Gram-Schmidt passes (the
                                    rest join the subspace unchanged: it keeps V = Q U, U triangular) */
+    int64_t second_pass;        /* tuples solved again in the second pass (see max_iter) */
 } mbefci_stats;
+
+/* Counters of one shape class (active orbitals, active alpha and beta
+ * electrons) in the last solve/run call; times need profile = 1. */
+typedef struct {
+    int32_t n_active, n_alpha, n_beta;
+    int32_t kernel;             /* alpha-beta sigma kernel: 0 k_sigma_strip (all pair rows),
+                                   1 k_sigma_linked_gat, 2 k_sigma_linked_res, 3 k_sigma_linked_dv,
+                                   4 k_sigma_w + k_sigma_g (W materialised) */
+    int64_t dim;                /* determinants per tuple */
+    int64_t tuples, iterations, sigma_calls, sigma_launches;
+    double sigma_flops;         /* as mbefci_stats.sigma_flops */
+    double sigma_ms;            /* HIP-event time of the alpha-beta kernel */
+    double sigma_total_ms;      /* of all sigma kernels (with the string-Hamiltonian GEMMs) */
+    double wall_ms;             /* host wall time of the class's batches */
+} mbefci_class_stats;
 
 /* Library version string. */
 const char *mbefci_version(void);
@@ -219,6 +247,21 @@ typedef int (*mbefci_energy_fn)(void *user, int32_t order, int64_t ntup,
 mbefci_status mbefci_run_host(mbefci_ctx *ctx, mbefci_energy_fn energy, void *user,
                               mbefci_result **out);
 
+/* Streamed last order (options.stream_last = 1; the paper's task farm over one
+ * order, Sec. 4.2.3).  mbefci_order_solve solves the tuples first + i * stride,
+ * i < count, of the open order of `res` (indices into its lexicographic list):
+ * CASCI energies, increments against the completed lower orders (Eq. 3), and
+ * with options.gradient their density matrices, weight 1 (no computed
+ * superset), added to the result's gradient (n^2 + n^4 doubles of the
+ * workspace used on the way).  Each tuple is solved once: EINVAL for a slice
+ * outside the order or a tuple already solved; ESTATE without an open order;
+ * ENOCONV as at mbefci_solve_tuples.  mbefci_order_close checks that every
+ * tuple is solved (else ESTATE), forms the order sum and the total, and
+ * closes the order; mbefci_backward refuses a result with an open order. */
+mbefci_status mbefci_order_solve(mbefci_ctx *ctx, mbefci_result *res, int64_t first, int64_t stride,
+                                 int64_t count, void *d_workspace, size_t ws_bytes);
+mbefci_status mbefci_order_close(mbefci_ctx *ctx, mbefci_result *res);
+
 int32_t mbefci_result_norders(const mbefci_result *res);     /* orders 0..norders-1 */
 /* Views of order k (valid until mbefci_result_free): tuples [ntup*k] int16
  * lexicographic, eps, d_eps and status [ntup], order sum E^(k), and the host
@@ -289,6 +332,11 @@ mbefci_status mbefci_tuple_rdm(mbefci_ctx *ctx, int32_t order, const int16_t *tu
 
 /* Counters of the last solve/run call. */
 mbefci_status mbefci_get_stats(const mbefci_ctx *ctx, mbefci_stats *stats);
+
+/* Per-class counters of the last solve/run call: *nclass receives the number
+ * of classes; with out != NULL the first min(*nclass on entry, count) entries
+ * are written (ordered by n_active, n_alpha, n_beta). */
+mbefci_status mbefci_get_class_stats(const mbefci_ctx *ctx, int32_t *nclass, mbefci_class_stats *out);
 
 #ifdef __cplusplus
 }

@@ -19,8 +19,8 @@ class Options(ctypes.Structure):
     _fields_ = [("a", c_double), ("max_order", c_int32), ("e_tol", c_double), ("r_tol", c_double),
                 ("max_iter", c_int32), ("max_space", c_int32), ("batched", c_int32),
                 ("gradient", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
-                ("pspace", c_int32), ("linked_rows", c_int32),
-                ("reserved", c_int32 * 4)]
+                ("pspace", c_int32), ("linked_rows", c_int32), ("stream_last", c_int32),
+                ("reserved", c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -28,7 +28,14 @@ class Stats(ctypes.Structure):
                 ("sigma_flops", c_double), ("sigma_bytes", c_double), ("sigma_ms", c_double),
                 ("sigma_total_ms", c_double), ("iterations_total", c_int64),
                 ("iterations_max", c_int64), ("solve_ms", c_double),
-                ("gs_second_pass", c_int64)]
+                ("gs_second_pass", c_int64), ("second_pass", c_int64)]
+
+
+class ClassStats(ctypes.Structure):
+    _fields_ = [("n_active", c_int32), ("n_alpha", c_int32), ("n_beta", c_int32), ("kernel", c_int32),
+                ("dim", c_int64), ("tuples", c_int64), ("iterations", c_int64), ("sigma_calls", c_int64),
+                ("sigma_launches", c_int64), ("sigma_flops", c_double), ("sigma_ms", c_double),
+                ("sigma_total_ms", c_double), ("wall_ms", c_double)]
 
 
 ENERGY_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int64, ctypes.POINTER(ctypes.c_int16),
@@ -57,6 +64,8 @@ SIGNATURES = [
                                       ctypes.POINTER(c_void_p), ctypes.POINTER(c_double),
                                       ctypes.POINTER(c_double)]),
     ("mbefci_result_total", c_double, [c_void_p]),
+    ("mbefci_order_solve", c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_size_t]),
+    ("mbefci_order_close", c_int32, [c_void_p, c_void_p]),
     ("mbefci_result_free", None, [c_void_p]),
     ("mbefci_tuple_sigma", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,
                                      c_int32]),
@@ -67,6 +76,7 @@ SIGNATURES = [
     ("mbefci_string_tables", c_int32, [c_int32, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32),
                                        c_void_p, c_void_p]),
     ("mbefci_get_stats", c_int32, [c_void_p, ctypes.POINTER(Stats)]),
+    ("mbefci_get_class_stats", c_int32, [c_void_p, ctypes.POINTER(c_int32), c_void_p]),
     ("mbefci_backward", c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, c_void_p, c_void_p]),
     ("mbefci_tuple_rdm", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,
                                    c_void_p]),

@@ -15,7 +15,7 @@ from . import _lib
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "ESTATE",
                 -6: "ETOOLARGE"}
-TUPLE_OK, TUPLE_MAXITER, TUPLE_NONFINITE, TUPLE_STALLED = 0, 1, 2, 3
+TUPLE_OK, TUPLE_MAXITER, TUPLE_NONFINITE, TUPLE_STALLED, TUPLE_PENDING = 0, 1, 2, 3, 4
 
 
 class MBEFCIError(RuntimeError):
@@ -202,6 +202,22 @@ class Context:
         self.L.mbefci_result_free(res)
         return out
 
+    def order_solve(self, handle, first, stride, count, workspace, allow_noconv=False):
+        """Solve tuples first + i * stride (i < count) of the open (streamed)
+        last order of `handle` (a run with stream_last = 1)."""
+        rc = self.L.mbefci_order_solve(self.ptr, handle.ptr, int(first), int(stride), int(count),
+                                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel())
+        return self._check(rc, allow=(-4,) if allow_noconv else ())
+
+    def order_close(self, handle, allow_noconv=False):
+        """Close the streamed order (every tuple solved) and return the Result."""
+        rc = self.L.mbefci_order_close(self.ptr, handle.ptr)
+        self._check(rc, allow=(-4,) if allow_noconv else ())
+        return _read_result(self.L, handle.ptr)
+
+    def result(self, handle) -> Result:
+        return _read_result(self.L, handle.ptr)
+
     def backward(self, handle, workspace, gE=1.0):
         """(dE/dh1 [n, n], dE/d(pq|rs)) of the summed MBE energy, times gE,
         with the tuple set of `handle` held fixed; dE/d(pq|rs) is [n, n, n, n]
@@ -299,6 +315,14 @@ class Context:
                                               ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                               ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def class_stats(self) -> list:
+        """Per-shape-class counters of the last call (list of dicts)."""
+        n = ctypes.c_int32(0)
+        self._check(self.L.mbefci_get_class_stats(self.ptr, ctypes.byref(n), None))
+        arr = (_lib.ClassStats * max(1, n.value))()
+        self._check(self.L.mbefci_get_class_stats(self.ptr, ctypes.byref(n), ctypes.cast(arr, ctypes.c_void_p)))
+        return [{name: getattr(arr[i], name) for name, _ in _lib.ClassStats._fields_} for i in range(n.value)]
 
     def stats(self) -> dict:
         s = _lib.Stats()

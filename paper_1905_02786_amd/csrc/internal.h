@@ -132,6 +132,10 @@ hipError_t init_sigma_kernels();   // LDS limits of the sigma kernels (called by
 hipError_t init_strip_kernels();   // the same for the strip kernels (called by init_sigma_kernels)
 // alpha-beta term of sigma (column strip, strip.hip): sig = X + shift c
 hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s);
+// which alpha-beta kernel launch_sigma runs for the batch (0 all pair rows,
+// 1 linked gathered, 2 linked resident, 3 linked with the vector-ALU
+// diagonal, 4 W materialised)
+int alpha_beta_kernel(const Batch &b);
 // linked-row strip kernel: row slots per alpha string, fit check, per-tuple
 // A-table size (doubles) and its build (once per batch, after the gather)
 constexpr int kLinkedRows = 32;

@@ -1460,7 +1460,7 @@ __device__ __forceinline__ void grad_add(double *a, double v) { unsafeAtomicAdd(
 __global__ __launch_bounds__(256) void k_rdm_embed_act(Batch b, const double *w, double *ge) {
     const int t = blockIdx.y;
     const double wt = w[t];
-    if (wt == 0.0) return;
+    if (wt == 0.0 || b.status[t] != ST_DONE) return;   // unconverged: solved again, embedded then
     const int nA = b.nA, nn = nA * nA, NP = round_up(nn + 1, 16), n = b.norb;
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= nn * nn) return;
@@ -1475,7 +1475,7 @@ __global__ __launch_bounds__(256) void k_rdm_embed_act(Batch b, const double *w,
 __global__ __launch_bounds__(256) void k_rdm_embed_core(Batch b, const double *w, double *gh, double *ge) {
     const int t = blockIdx.x;
     const double wt = w[t];
-    if (wt == 0.0) return;
+    if (wt == 0.0 || b.status[t] != ST_DONE) return;
     const int nA = b.nA, nn = nA * nA, NP = round_up(nn + 1, 16), n = b.norb, nC = b.nC;
     const double *G = b.rdm_G + (int64_t)t * NP * NP;
     const int32_t *o = b.act + (int64_t)t * nA, *C = b.core + (int64_t)t * nC;

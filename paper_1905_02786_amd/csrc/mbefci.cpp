@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -217,6 +218,11 @@ struct Result {
     // dE/dh [n^2] and dE/d(pq|rs) [n^4], entries as independent variables
     bool has_grad = false;
     std::vector<double> grad_h, grad_eri;
+    // streamed last order (options.stream_last): listed but solved in slices
+    // by mbefci_order_solve; its increments need the lower orders' d_eps
+    bool open = false;
+    std::vector<char> solved;
+    std::unordered_map<uint64_t, double> dinc_map;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -256,6 +262,8 @@ struct mbefci_ctx {
     std::vector<std::pair<int, int>> pi;   // degenerate pairs of the expansion space (pi-pruning)
     mbefci_options opt{};
     mbefci_stats stats{};
+    std::map<std::tuple<int, int, int>, mbefci_class_stats> cstats;   // per shape class, last call
+    mbefci_class_stats *sigma_cls = nullptr;   // class of the sigma whose events are pending
     bool sigma_pending = false;   // profile: events of the last sigma not read yet
     std::map<std::pair<int, int>, Tables> tables;
 
@@ -572,7 +580,21 @@ void flush_sigma_time(mbefci_ctx *ctx) {
         hipEventElapsedTime(&ms_all, ctx->ev[0], ctx->ev[2]) == hipSuccess) {
         ctx->stats.sigma_ms += ms_w;
         ctx->stats.sigma_total_ms += ms_all;
+        if (ctx->sigma_cls) {
+            ctx->sigma_cls->sigma_ms += ms_w;
+            ctx->sigma_cls->sigma_total_ms += ms_all;
+        }
     }
+}
+
+mbefci_class_stats &class_stats(mbefci_ctx *ctx, const Batch &b) {
+    mbefci_class_stats &c = ctx->cstats[std::make_tuple(b.nA, b.na, b.nb)];
+    c.n_active = b.nA;
+    c.n_alpha = b.na;
+    c.n_beta = b.nb;
+    c.dim = b.dim;
+    c.kernel = alpha_beta_kernel(b);
+    return c;
 }
 
 mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, double shift, bool skip_done,
@@ -589,6 +611,11 @@ mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, dou
     ctx->stats.sigma_calls += napps;
     ctx->stats.sigma_flops += napps * sigma_flops(b);
     ctx->stats.sigma_bytes += napps * sigma_bytes(b);
+    mbefci_class_stats &cs = class_stats(ctx, b);
+    cs.sigma_launches += 1;
+    cs.sigma_calls += napps;
+    cs.sigma_flops += napps * sigma_flops(b);
+    ctx->sigma_cls = &cs;
     ctx->sigma_pending = prof;
     return MBEFCI_OK;
 }
@@ -663,6 +690,9 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     HIPCHK(hipMemcpyAsync(dit.data(), b.iter, 4 * (size_t)b.B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     flush_sigma_time(ctx);
+    mbefci_class_stats &cs = class_stats(ctx, b);
+    cs.tuples += b.B;
+    for (int t = 0; t < b.B; ++t) cs.iterations += dit[t];
     for (int t = 0; t < b.B; ++t) {
         const int32_t d = dst[t];
         st_out[t] = d == ST_DONE ? MBEFCI_TUPLE_OK
@@ -697,8 +727,29 @@ struct RdmSink {
 
 // Solve a list of tuples (device).  Groups by shape class, batches within
 // the workspace, writes energies/status in input order.
+// The same sink seen through a list of input indices (second pass).
+struct SubsetSink : RdmSink {
+    RdmSink *inner;
+    const std::vector<int64_t> *map;
+    bool device() const override { return inner->device(); }
+    double weight(int64_t i) const override { return inner->weight((*map)[i]); }
+    void take(int64_t i, const TupleShape &ts, const double *G, int NP) override { inner->take((*map)[i], ts, G, NP); }
+};
+
+// Davidson settings of the second pass: tuples that fail the first (iteration
+// limit, stalled) are solved again with the largest subspace and without the
+// P space.  In the strongly spin-coupled classes a small subspace with
+// restarts to the Ritz vector can stagnate above the lowest state, which 32
+// vectors resolve; a class whose first batch sends at least a quarter of its
+// tuples to the second pass runs the rest of its batches with these settings.
+void second_pass_options(mbefci_options &o) {
+    o.max_space = kMaxSpace;
+    o.pspace = 0;
+    o.max_iter = std::max(10 * o.max_iter, 3000);
+}
+
 mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16_t *tuples, void *ws, size_t wsb,
-                           double *energies, int32_t *status, RdmSink *sink = nullptr) {
+                           double *energies, int32_t *status, RdmSink *sink = nullptr, bool second = false) {
     mbefci_status rc = check_device(ctx);
     if (rc != MBEFCI_OK) return rc;
     if (ntup < 0 || (ntup > 0 && order > 0 && !tuples)) return ctx->fail(MBEFCI_EINVAL, "bad tuple list");
@@ -710,29 +761,39 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
         if (rc != MBEFCI_OK) return rc;
         groups[{shapes[i].key, shapes[i].nC}].push_back(i);
     }
-    bool failed = false;
+    const mbefci_options first_opt = ctx->opt;
+    std::vector<int64_t> retry;
     for (auto &g : groups) {
-        ClassPlan cp;
         if (sink && g.first.first.nA > kRdmMaxActive)
             return ctx->fail(MBEFCI_ETOOLARGE, "RDMs need at most 12 active orbitals");
-        plan_class(ctx, g.first.first, g.first.second, cp, true, sink != nullptr);
-        if (cp.fixed_bytes + cp.per_tuple > wsb)
-            return ctx->fail(MBEFCI_ENOMEM, "workspace of " + std::to_string(wsb) + " bytes cannot hold one tuple (" +
-                                                std::to_string(cp.fixed_bytes + cp.per_tuple) + " needed)");
-        int64_t Bmax = ctx->opt.batched ? (int64_t)((wsb - cp.fixed_bytes) / cp.per_tuple) : 1;
-        Bmax = std::max<int64_t>(1, std::min<int64_t>(Bmax, 65535));
+        bool hard = false;   // this class runs with the second-pass settings
         const std::vector<int64_t> &idx = g.second;
-        for (size_t start = 0; start < idx.size(); start += Bmax) {
+        for (size_t start = 0; start < idx.size();) {
+            ctx->opt = first_opt;
+            if (hard) second_pass_options(ctx->opt);
+            ClassPlan cp;
+            plan_class(ctx, g.first.first, g.first.second, cp, true, sink != nullptr);
+            if (cp.fixed_bytes + cp.per_tuple > wsb) {
+                ctx->opt = first_opt;
+                return ctx->fail(MBEFCI_ENOMEM, "workspace of " + std::to_string(wsb) + " bytes cannot hold one tuple (" +
+                                                    std::to_string(cp.fixed_bytes + cp.per_tuple) + " needed)");
+            }
+            int64_t Bmax = ctx->opt.batched ? (int64_t)((wsb - cp.fixed_bytes) / cp.per_tuple) : 1;
+            Bmax = std::max<int64_t>(1, std::min<int64_t>(Bmax, 65535));
             const int B = (int)std::min<size_t>(Bmax, idx.size() - start);
             Carver cv{(char *)ws, wsb};
             Batch b;
-            if (!carve_batch(ctx, cp, B, cv, b, true)) return ctx->fail(MBEFCI_ENOMEM, "workspace carve failed");
-            if ((rc = upload_tables(ctx, cp, b)) != MBEFCI_OK) return rc;
+            if (!carve_batch(ctx, cp, B, cv, b, true)) {
+                ctx->opt = first_opt;
+                return ctx->fail(MBEFCI_ENOMEM, "workspace carve failed");
+            }
+            if ((rc = upload_tables(ctx, cp, b)) != MBEFCI_OK) break;
             std::vector<const TupleShape *> sh(B);
             for (int t = 0; t < B; ++t) sh[t] = &shapes[idx[start + t]];
-            if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) return rc;
+            if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) break;
             std::vector<double> e(B), gram, wts;
             std::vector<int32_t> st(B);
+            const double tb0 = now_ms();
             RdmOut ro;
             if (sink && sink->device()) {
                 wts.resize(B);
@@ -741,18 +802,55 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
             } else if (sink) {
                 ro.gram = &gram;
             }
-            if ((rc = davidson_batch(ctx, b, e.data(), st.data(), sink ? &ro : nullptr)) != MBEFCI_OK) return rc;
+            if ((rc = davidson_batch(ctx, b, e.data(), st.data(), sink ? &ro : nullptr)) != MBEFCI_OK) break;
+            class_stats(ctx, b).wall_ms += now_ms() - tb0;
+            int nfail = 0;
             for (int t = 0; t < B; ++t) {
-                energies[idx[start + t]] = e[t];
-                status[idx[start + t]] = st[t];
-                failed |= st[t] != MBEFCI_TUPLE_OK;
-                if (sink && !sink->device())
-                    sink->take(idx[start + t], shapes[idx[start + t]], gram.data() + (size_t)t * cp.NP * cp.NP, cp.NP);
+                const int64_t i = idx[start + t];
+                energies[i] = e[t];
+                status[i] = st[t];
+                if (st[t] != MBEFCI_TUPLE_OK) {   // not embedded on the device (k_rdm_embed skips it)
+                    ++nfail;
+                    retry.push_back(i);
+                    continue;
+                }
+                if (sink && !sink->device()) sink->take(i, shapes[i], gram.data() + (size_t)t * cp.NP * cp.NP, cp.NP);
             }
+            if (start == 0 && !second && 4 * nfail >= B && B >= 4) hard = true;
+            start += B;
         }
+        ctx->opt = first_opt;
+        if (rc != MBEFCI_OK) return rc;
     }
     ctx->stats.ntuples += ntup;
-    return failed ? ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge") : MBEFCI_OK;
+    if (!retry.empty() && !second) {
+        std::sort(retry.begin(), retry.end());
+        ctx->stats.second_pass += (int64_t)retry.size();
+        std::vector<int16_t> tl(retry.size() * (size_t)order);
+        for (size_t j = 0; j < retry.size(); ++j)
+            std::copy(tuples + retry[j] * order, tuples + (retry[j] + 1) * order, tl.begin() + j * order);
+        std::vector<double> e2(retry.size());
+        std::vector<int32_t> st2(retry.size());
+        SubsetSink sub;
+        sub.inner = sink;
+        sub.map = &retry;
+        second_pass_options(ctx->opt);
+        rc = solve_device(ctx, order, (int64_t)retry.size(), tl.data(), ws, wsb, e2.data(), st2.data(),
+                          sink ? &sub : nullptr, true);
+        ctx->opt = first_opt;
+        ctx->stats.ntuples -= (int64_t)retry.size();
+        if (rc != MBEFCI_OK && rc != MBEFCI_ENOCONV) return rc;
+        for (size_t j = 0; j < retry.size(); ++j) {
+            energies[retry[j]] = e2[j];
+            status[retry[j]] = st2[j];
+        }
+        for (int32_t x : st2)
+            if (x != MBEFCI_TUPLE_OK) return ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge");
+        return MBEFCI_OK;
+    }
+    for (int64_t i = 0; i < ntup; ++i)
+        if (status[i] != MBEFCI_TUPLE_OK) return ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge");
+    return MBEFCI_OK;
 }
 
 // ----------------------------------------------------------------- planner --
@@ -935,6 +1033,17 @@ mbefci_status run_planner(mbefci_ctx *ctx, EnergyFn energy, Result &R) {
             }
             break;
         }
+        if (k == kmax && k >= 1 && ctx->opt.stream_last) {
+            // the last order is only listed; mbefci_order_solve fills it slice by slice
+            o.eps.assign(nt, std::nan(""));
+            o.dinc.assign(nt, std::nan(""));
+            o.status.assign(nt, MBEFCI_TUPLE_PENDING);
+            R.orders.push_back(std::move(o));
+            R.open = true;
+            R.solved.assign(nt, 0);
+            R.dinc_map = std::move(dinc);
+            break;
+        }
         const double t0 = now_ms();
         o.eps.assign(nt, 0.0);
         o.status.assign(nt, 0);
@@ -955,6 +1064,9 @@ mbefci_status run_planner(mbefci_ctx *ctx, EnergyFn energy, Result &R) {
     R.total = tot;
     return failed ? ctx->fail(MBEFCI_ENOCONV, "at least one tuple did not converge") : MBEFCI_OK;
 }
+
+// The status code of a listed tuple of a streamed order not solved yet.
+static_assert(MBEFCI_TUPLE_PENDING == 4, "status codes");
 
 // Full-space density matrices of one CASCI vector from its Gram matrix G
 // (columns p*nA+q: D_pq = <I|E_pq|x>, column nA^2: x), accumulated with
@@ -1075,7 +1187,7 @@ struct TightTol {
     explicit TightTol(mbefci_ctx *c) : ctx(c), saved(c->opt) {
         ctx->opt.r_tol = std::min(ctx->opt.r_tol, 1e-9);
         ctx->opt.e_tol = std::min(ctx->opt.e_tol, 1e-12);
-        ctx->opt.max_iter = std::max(ctx->opt.max_iter, 1000);
+        ctx->opt.max_iter = std::max(ctx->opt.max_iter, 300);
     }
     ~TightTol() { ctx->opt = saved; }
 };
@@ -1150,7 +1262,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->max_order = 0;
     o->e_tol = 1e-11;
     o->r_tol = 1e-6;
-    o->max_iter = 1000;
+    o->max_iter = 300;
     o->max_space = 12;
     o->pspace = kPsp;
     o->linked_rows = 1;
@@ -1357,6 +1469,8 @@ mbefci_status mbefci_solve_tuples(mbefci_ctx *ctx, int32_t order, int64_t ntup, 
     if (!ctx) return MBEFCI_EINVAL;
     if (!energies || !status || order < 0) return ctx->fail(MBEFCI_EINVAL, "null output");
     ctx->stats = mbefci_stats{};
+    ctx->cstats.clear();
+    ctx->sigma_cls = nullptr;
     const double t0 = now_ms();
     mbefci_status rc = solve_device(ctx, order, ntup, tuples, ws, wsb, energies, status);
     ctx->stats.solve_ms = now_ms() - t0;
@@ -1369,6 +1483,8 @@ mbefci_status mbefci_run(mbefci_ctx *ctx, void *ws, size_t wsb, mbefci_result **
     mbefci_status rc = check_device(ctx);
     if (rc != MBEFCI_OK) return rc;
     ctx->stats = mbefci_stats{};
+    ctx->cstats.clear();
+    ctx->sigma_cls = nullptr;
     const double t0 = now_ms();
     auto res = std::make_unique<mbefci_result>();
     const bool grad = ctx->opt.gradient != 0;
@@ -1566,6 +1682,7 @@ mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double 
     if (!ctx->ham_set) return ctx->fail(MBEFCI_ESTATE, "no Hamiltonian set");
     const int n = ctx->norb;
     const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    if (res->r.open) return ctx->fail(MBEFCI_ESTATE, "the last order is still open (mbefci_order_close)");
     if (res->r.has_grad) {   // formed by the forward run
         if (res->r.grad_h.size() != n2 || res->r.grad_eri.size() != n4)
             return ctx->fail(MBEFCI_ESTATE, "result was computed for another orbital count");
@@ -1576,6 +1693,8 @@ mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double 
     if (rc != MBEFCI_OK) return rc;
     const double t0 = now_ms();
     ctx->stats = mbefci_stats{};
+    ctx->cstats.clear();
+    ctx->sigma_cls = nullptr;
     TightTol tight(ctx);
     size_t wsb_run = wsb;
     if ((rc = grad_region(ctx, ws, &wsb_run)) != MBEFCI_OK) return rc;
@@ -1626,6 +1745,102 @@ mbefci_status mbefci_tuple_rdm(mbefci_ctx *ctx, int32_t order, const int16_t *tu
     mbefci_status rc = solve_device(ctx, order, 1, tuple, ws, wsb, energy, &st, &sink);
     if (rc != MBEFCI_OK) return rc;
     for (size_t i = 0; i < n2 * n2; ++i) Gamma[i] *= 2.0;   // the sink stores Gamma / 2
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_order_solve(mbefci_ctx *ctx, mbefci_result *res, int64_t first, int64_t stride, int64_t count,
+                                 void *ws, size_t wsb) {
+    if (!ctx || !res) return MBEFCI_EINVAL;
+    Result &R = res->r;
+    if (!R.open) return ctx->fail(MBEFCI_ESTATE, "no open order");
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    Result::Order &o = R.orders.back();
+    const int k = o.k;
+    const int64_t nt = (int64_t)o.eps.size();
+    if (first < 0 || stride < 1 || count < 0 || (count > 0 && first + (count - 1) * stride >= nt))
+        return ctx->fail(MBEFCI_EINVAL, "slice outside the open order");
+    if (count == 0) return MBEFCI_OK;
+    std::vector<int64_t> idx((size_t)count);
+    std::vector<int16_t> tl((size_t)count * k);
+    for (int64_t i = 0; i < count; ++i) {
+        idx[i] = first + i * stride;
+        if (R.solved[idx[i]]) return ctx->fail(MBEFCI_EINVAL, "tuple " + std::to_string(idx[i]) + " already solved");
+        std::copy(o.tuples.begin() + idx[i] * k, o.tuples.begin() + (idx[i] + 1) * k, tl.begin() + i * k);
+    }
+    ctx->stats = mbefci_stats{};
+    ctx->cstats.clear();
+    ctx->sigma_cls = nullptr;
+    const double t0 = now_ms();
+    std::vector<double> e((size_t)count);
+    std::vector<int32_t> st((size_t)count);
+    const bool grad = ctx->opt.gradient != 0 && R.has_grad;
+    if (grad) {
+        // the last order's adjoint weights are 1: density matrices embedded on
+        // the device as they converge, then added to the result's gradient
+        TightTol tight(ctx);
+        size_t wsb_run = wsb;
+        if ((rc = grad_region(ctx, ws, &wsb_run)) != MBEFCI_OK) return rc;
+        std::vector<double> ones((size_t)count, 1.0);
+        WeightSink unit;
+        unit.w = &ones;
+        rc = solve_device(ctx, k, count, tl.data(), ws, wsb_run, e.data(), st.data(), &unit);
+        if (rc != MBEFCI_OK && rc != MBEFCI_ENOCONV) {
+            ctx->d_gh = ctx->d_ge = nullptr;
+            return rc;
+        }
+        mbefci_status rf = grad_fetch(ctx, R.grad_h, R.grad_eri);
+        if (rf != MBEFCI_OK) return rf;
+    } else {
+        rc = solve_device(ctx, k, count, tl.data(), ws, wsb, e.data(), st.data());
+        if (rc != MBEFCI_OK && rc != MBEFCI_ENOCONV) return rc;
+    }
+    // Eq. 3 against the completed lower orders (no tuple of the open order is
+    // a subtuple of another)
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t j = idx[i];
+        o.eps[j] = e[i];
+        o.status[j] = st[i];
+        o.dinc[j] = increment(o.tuples.data() + (size_t)j * k, k, e[i], R.dinc_map);
+        R.solved[j] = 1;
+    }
+    o.wall_ms += now_ms() - t0;
+    ctx->stats.solve_ms = now_ms() - t0;
+    return rc;
+}
+
+mbefci_status mbefci_order_close(mbefci_ctx *ctx, mbefci_result *res) {
+    if (!ctx || !res) return MBEFCI_EINVAL;
+    Result &R = res->r;
+    if (!R.open) return ctx->fail(MBEFCI_ESTATE, "no open order");
+    Result::Order &o = R.orders.back();
+    for (size_t i = 0; i < R.solved.size(); ++i)
+        if (!R.solved[i]) return ctx->fail(MBEFCI_ESTATE, "tuple " + std::to_string(i) + " of the open order not solved");
+    double s = 0.0;
+    for (double d : o.dinc) s += d;
+    o.sum = s;
+    double tot = 0.0;
+    for (auto &oo : R.orders) tot += oo.sum;
+    R.total = tot;
+    R.open = false;
+    R.solved.clear();
+    std::unordered_map<uint64_t, double>().swap(R.dinc_map);
+    bool failed = false;
+    for (int32_t st : o.status) failed |= st != MBEFCI_TUPLE_OK;
+    return failed ? ctx->fail(MBEFCI_ENOCONV, "at least one tuple of the closed order did not converge") : MBEFCI_OK;
+}
+
+mbefci_status mbefci_get_class_stats(const mbefci_ctx *ctx, int32_t *nclass, mbefci_class_stats *out) {
+    if (!ctx || !nclass) return MBEFCI_EINVAL;
+    const int32_t cap = *nclass;
+    *nclass = (int32_t)ctx->cstats.size();
+    if (out) {
+        int32_t i = 0;
+        for (const auto &kv : ctx->cstats) {
+            if (i >= cap) break;
+            out[i++] = kv.second;
+        }
+    }
     return MBEFCI_OK;
 }
 

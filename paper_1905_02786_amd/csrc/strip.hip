@@ -1165,6 +1165,13 @@ static bool use_resident(const Batch &b) {
     return b.Na >= b.pl.P;
 }
 
+int alpha_beta_kernel(const Batch &b) {
+    if (b.sigma_variant != SIGMA_STRIP) return 4;
+    if (!b.la) return 0;
+    if (b.linked_dv) return 3;
+    return use_resident(b) ? 2 : 1;
+}
+
 template <int NA>
 static hipError_t launch_linked_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;

@@ -198,7 +198,10 @@ def _header_fields(hdr, name):
     """Field names of `typedef struct { ... } name;` in declaration order."""
     body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r";", hdr).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    return re.findall(r"\b(?:double|int32_t|int64_t)\s+(\w+)\s*(?:\[\d+\])?\s*;", body)
+    out = []
+    for decl in re.findall(r"\b(?:double|int32_t|int64_t)\s+([^;]+);", body):
+        out += [re.sub(r"\[\d+\]", "", v).strip() for v in decl.split(",")]
+    return out
 
 
 def test_ctypes_structs_match_header():
@@ -207,7 +210,8 @@ def test_ctypes_structs_match_header():
     pointer, so a field added to one side only would shift every later one)."""
     with open(os.path.join(ROOT, "include", "mbefci.h")) as f:
         hdr = f.read()
-    for cname, cls in (("mbefci_options", _lib.Options), ("mbefci_stats", _lib.Stats)):
+    for cname, cls in (("mbefci_options", _lib.Options), ("mbefci_stats", _lib.Stats),
+                       ("mbefci_class_stats", _lib.ClassStats)):
         fields = _header_fields(hdr, cname)
         assert len(fields) >= 10, cname
         assert fields == [n for n, _ in cls._fields_], cname
