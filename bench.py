@@ -36,7 +36,7 @@ METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |Î”E|â‰
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_sigma_strip", 1: "k_sigma_linked_gat", 2: "k_sigma_linked_res", 3: "k_sigma_linked_dv",
-                4: "k_sigma_w"}
+                4: "k_sigma_w", 5: "k_linked_wr"}
 # Calibrated HBM bytes per dispatch of the dominant kernel from the FETCH_SIZE /
 # WRITE_SIZE passes of profiles/, valid only while the kernel sources hash to
 # the value they were taken on.
@@ -93,13 +93,25 @@ def class_table(acc):
     for key in sorted(acc):
         c = acc[key]
         tf = c["sigma_flops"] / (c["sigma_ms"] / 1e3) / 1e12 if c["sigma_ms"] > 0 else 0.0
-        out.append({"cas": f"({c['n_alpha'] + c['n_beta']}e,{c['n_active']}o)", "dim": c["dim"],
-                    "kernel": KERNEL_NAMES[c["kernel"]], "tuples": c["tuples"],
-                    "iterations_mean": c["iterations"] / max(1, c["tuples"]), "sigma_applications": c["sigma_calls"],
-                    "sigma_launches": c["sigma_launches"], "alpha_beta_ms": c["sigma_ms"],
-                    "sigma_all_ms": c["sigma_total_ms"], "wall_ms": c["wall_ms"], "alpha_beta_tflops": tf,
-                    "frac": tf / FP64_MFMA_PEAK_TFLOPS, "flops": c["sigma_flops"]})
+        row = {"cas": f"({c['n_alpha'] + c['n_beta']}e,{c['n_active']}o)", "dim": c["dim"],
+               "kernel": KERNEL_NAMES[c["kernel"]], "tuples": c["tuples"],
+               "iterations_mean": c["iterations"] / max(1, c["tuples"]), "sigma_applications": c["sigma_calls"],
+               "sigma_launches": c["sigma_launches"], "alpha_beta_ms": c["sigma_ms"],
+               "sigma_all_ms": c["sigma_total_ms"], "wall_ms": c["wall_ms"], "alpha_beta_tflops": tf,
+               "frac": tf / FP64_MFMA_PEAK_TFLOPS, "flops": c["sigma_flops"]}
+        if c["kernel"] == 5 and c["gather_ms"] > 0:
+            row.update(gather_bytes_and_rate(c))
+        out.append(row)
     return out
+
+
+def gather_bytes_and_rate(c):
+    """The gather of the W-in-HBM form: per application it reads the 1 +
+    n_a (n_A - n_a) W rows of every determinant and c, and writes sigma."""
+    rows = 1 + c["n_alpha"] * (c["n_active"] - c["n_alpha"])
+    by = (rows + 2) * 8.0 * c["dim"] * c["sigma_calls"]
+    gbs = by / (c["gather_ms"] / 1e3) / 1e9
+    return {"gather_ms": c["gather_ms"], "gather_bytes": by, "gather_gbs": gbs, "gather_hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def roofline(acc, workload):

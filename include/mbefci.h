@@ -125,8 +125,11 @@ typedef struct {
                                vector ALU (A rows resident, two halves of four waves); 2 and 3
                                use linked rows wherever they fit (n_A >= 4), 2 with the A rows
                                gathered, 3 resident (each where it fits, else the other); 4 the
-                               vector-ALU diagonal form wherever it fits.  Same result up to
-                               rounding. */
+                               vector-ALU diagonal form wherever it fits.  Where neither LDS form
+                               fits (n_A = 12 at 5 or 6 electrons of the spin, whose sigma strips
+                               fill the LDS) the linked rows, up to 48, are written to the
+                               workspace and gathered back per target string; 5 uses that form
+                               wherever it fits.  Same result up to rounding. */
     int32_t stream_last;    /* 1: mbefci_run solves orders 0 .. K-1 and only lists the last order K
                                (its tuples generated, status MBEFCI_TUPLE_PENDING), which the
                                caller then solves in slices with mbefci_order_solve and ends with
@@ -150,6 +153,8 @@ typedef struct {
     int64_t gs_second_pass;     /* Davidson corrections that took two explicit Gram-Schmidt passes (the
                                    rest join the subspace unchanged: it keeps V = Q U, U triangular) */
     int64_t second_pass;        /* tuples solved again in the second pass (see max_iter) */
+    double gather_ms;           /* HIP-event time of the gather of the W-in-HBM linked form (profile = 1;
+                                   sigma_ms holds that form's MFMA kernel alone) */
 } mbefci_stats;
 
 /* Counters of one shape class (active orbitals, active alpha and beta
@@ -158,11 +163,13 @@ typedef struct {
     int32_t n_active, n_alpha, n_beta;
     int32_t kernel;             /* alpha-beta sigma kernel: 0 k_sigma_strip (all pair rows),
                                    1 k_sigma_linked_gat, 2 k_sigma_linked_res, 3 k_sigma_linked_dv,
-                                   4 k_sigma_w + k_sigma_g (W materialised) */
+                                   4 k_sigma_w + k_sigma_g (W materialised), 5 k_linked_wr +
+                                   k_linked_gw (linked rows through W in the workspace) */
     int64_t dim;                /* determinants per tuple */
     int64_t tuples, iterations, sigma_calls, sigma_launches;
     double sigma_flops;         /* as mbefci_stats.sigma_flops */
-    double sigma_ms;            /* HIP-event time of the alpha-beta kernel */
+    double sigma_ms;            /* HIP-event time of the alpha-beta kernel (the MFMA kernel of kernel 5) */
+    double gather_ms;           /* of the gather of kernel 5 */
     double sigma_total_ms;      /* of all sigma kernels (with the string-Hamiltonian GEMMs) */
     double wall_ms;             /* host wall time of the class's batches */
 } mbefci_class_stats;

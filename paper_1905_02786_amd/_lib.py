@@ -28,14 +28,14 @@ class Stats(ctypes.Structure):
                 ("sigma_flops", c_double), ("sigma_bytes", c_double), ("sigma_ms", c_double),
                 ("sigma_total_ms", c_double), ("iterations_total", c_int64),
                 ("iterations_max", c_int64), ("solve_ms", c_double),
-                ("gs_second_pass", c_int64), ("second_pass", c_int64)]
+                ("gs_second_pass", c_int64), ("second_pass", c_int64), ("gather_ms", c_double)]
 
 
 class ClassStats(ctypes.Structure):
     _fields_ = [("n_active", c_int32), ("n_alpha", c_int32), ("n_beta", c_int32), ("kernel", c_int32),
                 ("dim", c_int64), ("tuples", c_int64), ("iterations", c_int64), ("sigma_calls", c_int64),
                 ("sigma_launches", c_int64), ("sigma_flops", c_double), ("sigma_ms", c_double),
-                ("sigma_total_ms", c_double), ("wall_ms", c_double)]
+                ("gather_ms", c_double), ("sigma_total_ms", c_double), ("wall_ms", c_double)]
 
 
 ENERGY_FN = ctypes.CFUNCTYPE(c_int32, c_void_p, c_int32, c_int64, ctypes.POINTER(ctypes.c_int16),

@@ -88,6 +88,13 @@ struct Batch {
     int lpairs;
     int linked_mode;        // 1: variant by occupancy, 2: gathered A, 3: resident A (where it fits)
     int linked_dv;          // slots hold the off-diagonal links only; diagonal sums on the vector ALU
+    // linked rows through W in HBM (null lw: not this form): per alpha string
+    // the A-row offsets of its 48 slots [Na + 1][48], W [B][Na * lw_slots * Nb],
+    // and per target string its incoming W rows [Na][lw_ninc]
+    const uint32_t *lrow_w, *linc;
+    double *lw;
+    int64_t lw_stride;
+    int lw_slots, lw_ninc;
     const int32_t *act;     // [B * nA] active orbitals (ascending)
     const int32_t *core;    // [B * nC] core orbitals
     double *params;         // [B * pl.stride]
@@ -131,14 +138,18 @@ hipError_t init_kernels();
 hipError_t init_sigma_kernels();   // LDS limits of the sigma kernels (called by init_kernels)
 hipError_t init_strip_kernels();   // the same for the strip kernels (called by init_sigma_kernels)
 // alpha-beta term of sigma (column strip, strip.hip): sig = X + shift c
-hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s);
+// (ev_mid, if given, is recorded after the MFMA kernel, before the gather of
+// the W-in-HBM form)
+hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s,
+                        hipEvent_t ev_mid = nullptr);
 // which alpha-beta kernel launch_sigma runs for the batch (0 all pair rows,
 // 1 linked gathered, 2 linked resident, 3 linked with the vector-ALU
-// diagonal, 4 W materialised)
+// diagonal, 4 W materialised, 5 linked rows through W in HBM)
 int alpha_beta_kernel(const Batch &b);
 // linked-row strip kernel: row slots per alpha string, fit check, per-tuple
 // A-table size (doubles) and its build (once per batch, after the gather)
 constexpr int kLinkedRows = 32;
+constexpr int kLinkedRowsW = 48;       // slots of the form with W in HBM (three MFMA row tiles)
 constexpr int kLinkedMinActive = 9;    // smallest n_A that uses the linked-row kernel
 // Per-tuple A table of the linked-row kernel: with kLinkedSigned the rows are
 // A, -A (the alpha link sign picked by the row), then the diagonal sums;
@@ -155,6 +166,9 @@ bool linked_fits(const ParamLayout &pl, int64_t Na, int nel);
 // the form whose 32 slots hold only the n (n_A - n) off-diagonal links (the
 // diagonal sums on the vector ALU, A resident in LDS, two halves of four waves)
 bool linked_dv_fits(const ParamLayout &pl, int64_t Na, int nel);
+// the form that writes the linked rows of W to HBM and gathers them (no sigma
+// strip in LDS; 1 + n (n_A - n) <= 48 rows)
+bool linked_w_fits(const ParamLayout &pl, int64_t Na, int nel);
 int64_t linked_a_stride(const ParamLayout &pl, int64_t Na);
 hipError_t launch_linked_a(const Batch &b, hipStream_t s);
 hipError_t launch_gather(const Batch &b, hipStream_t s);
@@ -163,7 +177,7 @@ hipError_t launch_hdiag(const Batch &b, double *out, int64_t ostride, int add_ec
 // also leaves the partial dots V_i . sig, i <= m, in partial blocks
 // 0 .. gemm_blocks(b) - 1 (sigma_fuses_dots)
 hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done, bool dots,
-                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2);
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t evg, hipEvent_t ev2);
 inline bool sigma_fuses_dots(const Batch &b) { return b.sigma_variant == SIGMA_STRIP; }
 int gemm_blocks(const Batch &b);
 hipError_t launch_update_G(const Batch &b, int nsum, hipStream_t s);

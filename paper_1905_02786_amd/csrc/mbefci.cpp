@@ -30,6 +30,11 @@ struct Tables {
     std::vector<uint32_t> scat;      // [nstr + 1][P + 1]: scatter form for the strip kernel
     std::vector<uint32_t> lrow, lscat;   // [nstr + 1][32]: linked-row form (empty if the links need more slots)
     std::vector<uint32_t> lrow_v, lscat_v;   // the same without the diagonal slot (diagonal on the vector ALU)
+    // linked rows through W in HBM: A-row offsets of 48 slots per string
+    // [nstr + 1][48] (slot 0 the diagonal sum), and per target string its
+    // incoming W rows [nstr][1 + n (n_A - n)] (row K * slots + slot, bit 31 sign)
+    std::vector<uint32_t> lrow_w, linc;
+    int w_slots = 0;
     std::vector<int32_t> lperm;          // [2 (lpairs + 8)]: string order of the linked-row kernel
     int lpairs = 0;
 };
@@ -193,6 +198,38 @@ void build_tables(int nA, int nel, Tables &T) {
         }
     }
     if (!T.lrow.empty() || !T.lrow_v.empty()) pair_strings(T);
+    // the W-in-HBM form: slot 0 the diagonal sum, then the off-diagonal links
+    // in link order; the gather table lists for target J its own diagonal row
+    // first, then the rows (K, slot) of the links K -> J by ascending K
+    T.lrow_w.clear();
+    T.linc.clear();
+    T.w_slots = 0;
+    const int offd = nel * (nA - nel);
+    if (1 + offd <= kLinkedRowsW && T.nstr > 0) {
+        const int S = 1 + offd;
+        const uint32_t kp8 = (uint32_t)linked_row_len((np + 3) / 4 * 4) * 8u;
+        T.w_slots = S;
+        T.lrow_w.assign((size_t)(T.nstr + 1) * kLinkedRowsW, 0u);
+        std::vector<std::vector<uint32_t>> inc((size_t)T.nstr);
+        for (int64_t J = 0; J < T.nstr; ++J) inc[J].push_back((uint32_t)(J * S));
+        for (int64_t K = 0; K < T.nstr; ++K) {
+            int slot = 1;
+            for (int e = 0; e < T.nent; ++e) {
+                const uint32_t L = T.links[(size_t)K * T.nent + e];
+                const int P = (int)((L >> 20) & 0x3FFu);
+                int p = 0;
+                while ((p + 1) * (p + 2) / 2 <= P) ++p;
+                const int q = P - p * (p + 1) / 2;
+                if (p == q) continue;
+                T.lrow_w[(size_t)K * kLinkedRowsW + slot] = (uint32_t)(nA + P - p) * kp8;
+                const int64_t J = (int64_t)(L & 0xFFFFFu);
+                inc[J].push_back((uint32_t)(K * S + slot) | (L & 0x80000000u));
+                ++slot;
+            }
+        }
+        T.linc.reserve((size_t)T.nstr * S);
+        for (int64_t J = 0; J < T.nstr; ++J) T.linc.insert(T.linc.end(), inc[J].begin(), inc[J].end());
+    }
 }
 
 struct ClassKey {
@@ -242,7 +279,7 @@ struct mbefci_ctx {
     int device = -1;
     bool host_only = true;
     hipStream_t stream = nullptr;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sigma start, MFMA kernel end, gather end, end
     std::string err;
     // Hamiltonian
     int norb = 0;
@@ -344,6 +381,7 @@ struct ClassPlan {
     int psp;   // P-space size of the Davidson preconditioner (0: diagonal only)
     bool linked;   // linked-row strip kernel
     bool linked_dv;   // its form without the diagonal slot (diagonal sums on the vector ALU)
+    bool linked_w;    // linked rows through W in HBM (no sigma strip in LDS)
     bool rdm;
     int nblk_r, NP;
     size_t fixed_bytes, per_tuple;
@@ -379,7 +417,13 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     const bool classic = lin_ok && !cp.ta->lrow.empty() && linked_fits(cp.pl, cp.ta->nstr, key.na);
     const bool dvf = lin_ok && !cp.ta->lrow_v.empty() && linked_dv_fits(cp.pl, cp.ta->nstr, key.na);
     cp.linked_dv = dvf && (lm == 4 || !classic);
-    cp.linked = classic || cp.linked_dv;
+    // linked rows through W in HBM where neither LDS form fits (or always with
+    // linked_rows 5)
+    const bool wf = lin_ok && cp.ta->w_slots > 0 && linked_w_fits(cp.pl, cp.ta->nstr, key.na);
+    cp.linked_w = wf && (lm == 5 || (!classic && !cp.linked_dv));
+    if (lm == 5 && cp.linked_w) cp.linked_dv = false;
+    const bool cls = classic && !cp.linked_dv && !cp.linked_w;
+    cp.linked = cls || cp.linked_dv || cp.linked_w;
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
@@ -387,6 +431,8 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
                      align256(4 * (size_t)cp.tb->nstr * cp.pl.P) +
                      (cp.linked ? 2 * align256(4 * (size_t)(cp.ta->nstr + 1) * kLinkedRows) +
                                       align256(4 * cp.ta->lperm.size()) : 0) +
+                     (cp.linked_w ? align256(4 * (size_t)(cp.ta->nstr + 1) * kLinkedRowsW) +
+                                        align256(4 * cp.ta->linc.size()) : 0) +
                      64 * 256;
     const int ms = davidson ? ctx->opt.max_space : 0;
     size_t pt = 0;
@@ -398,6 +444,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
                (key.na != key.nb ? 8 * (size_t)cp.ta->nstr * cp.ta->nstr : 0);
     pt += 8 * (size_t)(cp.nblk + 1) * kParts;                // partials (+ P-space block)
     if (cp.linked) pt += 8 * (size_t)linked_a_stride(cp.pl, cp.ta->nstr);   // A table
+    if (cp.linked_w) pt += 8 * (size_t)cp.dim * cp.ta->w_slots + 256;          // W rows
     if (cp.psp > 0) pt += 4 * (size_t)kPsp + 16 * (size_t)kPsp * kPsp + 24 * (size_t)kPsp + 4 * 256;
     cp.rdm = rdm;
     cp.NP = rdm_np(key.nA);
@@ -453,10 +500,18 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.lscat = cv.take<uint32_t>((size_t)(b.Na + 1) * kLinkedRows);
         b.la_stride = linked_a_stride(cp.pl, b.Na);
         b.la = cv.take<double>((size_t)B * b.la_stride);
-        b.lperm = cv.take<int32_t>(cp.ta->lperm.size());
+        b.lperm = cv.take<int32_t>(cp.ta->lperm.size() + 1);
         b.lpairs = cp.ta->lpairs;
         b.linked_mode = ctx->opt.linked_rows;
         b.linked_dv = cp.linked_dv ? 1 : 0;
+        if (cp.linked_w) {
+            b.lrow_w = cv.take<uint32_t>((size_t)(b.Na + 1) * kLinkedRowsW);
+            b.linc = cv.take<uint32_t>(cp.ta->linc.size());
+            b.lw_slots = cp.ta->w_slots;
+            b.lw_ninc = cp.ta->w_slots;
+            b.lw_stride = (int64_t)b.dim * cp.ta->w_slots;
+            b.lw = cv.take<double>((size_t)B * b.lw_stride);
+        }
     } else {
         b.lrow = b.lscat = nullptr;
         b.la = nullptr;
@@ -539,14 +594,24 @@ mbefci_status upload_tables(mbefci_ctx *ctx, const ClassPlan &cp, const Batch &b
     HIPCHK(hipMemcpyAsync((void *)b.pairB, cp.tb->pairs.data(), 4 * (size_t)b.Nb * b.pl.P, hipMemcpyHostToDevice,
                           ctx->stream));
     if (b.la) {
+        // the slot tables of the LDS forms (not read by the W-in-HBM form,
+        // whose class may have none)
         const std::vector<uint32_t> &lr = b.linked_dv ? cp.ta->lrow_v : cp.ta->lrow,
                                     &ls = b.linked_dv ? cp.ta->lscat_v : cp.ta->lscat;
-        HIPCHK(hipMemcpyAsync((void *)b.lrow, lr.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
-                              hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipMemcpyAsync((void *)b.lscat, ls.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
-                              hipMemcpyHostToDevice, ctx->stream));
-        HIPCHK(hipMemcpyAsync((void *)b.lperm, cp.ta->lperm.data(), 4 * cp.ta->lperm.size(), hipMemcpyHostToDevice,
-                              ctx->stream));
+        if (!b.lw) {
+            HIPCHK(hipMemcpyAsync((void *)b.lrow, lr.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
+                                  hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync((void *)b.lscat, ls.data(), 4 * (size_t)(b.Na + 1) * kLinkedRows,
+                                  hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync((void *)b.lperm, cp.ta->lperm.data(), 4 * cp.ta->lperm.size(),
+                                  hipMemcpyHostToDevice, ctx->stream));
+        }
+        if (b.lw) {
+            HIPCHK(hipMemcpyAsync((void *)b.lrow_w, cp.ta->lrow_w.data(), 4 * cp.ta->lrow_w.size(),
+                                  hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync((void *)b.linc, cp.ta->linc.data(), 4 * cp.ta->linc.size(), hipMemcpyHostToDevice,
+                                  ctx->stream));
+        }
     }
     return MBEFCI_OK;
 }
@@ -575,13 +640,16 @@ double sigma_bytes(const Batch &b) { return 16.0 * (double)b.dim + 8.0 * (double
 void flush_sigma_time(mbefci_ctx *ctx) {
     if (!ctx->sigma_pending) return;
     ctx->sigma_pending = false;
-    float ms_w = 0.f, ms_all = 0.f;
+    float ms_w = 0.f, ms_g = 0.f, ms_all = 0.f;
     if (hipEventElapsedTime(&ms_w, ctx->ev[0], ctx->ev[1]) == hipSuccess &&
-        hipEventElapsedTime(&ms_all, ctx->ev[0], ctx->ev[2]) == hipSuccess) {
+        hipEventElapsedTime(&ms_g, ctx->ev[1], ctx->ev[2]) == hipSuccess &&
+        hipEventElapsedTime(&ms_all, ctx->ev[0], ctx->ev[3]) == hipSuccess) {
         ctx->stats.sigma_ms += ms_w;
+        ctx->stats.gather_ms += ms_g;
         ctx->stats.sigma_total_ms += ms_all;
         if (ctx->sigma_cls) {
             ctx->sigma_cls->sigma_ms += ms_w;
+            ctx->sigma_cls->gather_ms += ms_g;
             ctx->sigma_cls->sigma_total_ms += ms_all;
         }
     }
@@ -601,11 +669,12 @@ mbefci_status run_sigma(mbefci_ctx *ctx, const Batch &b, VecRef c, VecRef s, dou
                         int64_t napps, bool dots = false) {
     const bool prof = ctx->opt.profile != 0;
     if (prof && ctx->sigma_pending) {   // a sigma whose events were not read yet
-        HIPCHK(hipEventSynchronize(ctx->ev[2]));
+        HIPCHK(hipEventSynchronize(ctx->ev[3]));
         flush_sigma_time(ctx);
     }
     hipError_t e = launch_sigma(b, c, s, shift, skip_done, dots, ctx->stream, prof ? ctx->ev[0] : nullptr,
-                                prof ? ctx->ev[1] : nullptr, prof ? ctx->ev[2] : nullptr);
+                                prof ? ctx->ev[1] : nullptr, prof ? ctx->ev[2] : nullptr,
+                                prof ? ctx->ev[3] : nullptr);
     if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, std::string("sigma launch: ") + hipGetErrorString(e));
     ctx->stats.sigma_launches += 1;
     ctx->stats.sigma_calls += napps;
@@ -1436,7 +1505,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (!(o->e_tol > 0) || !(o->r_tol > 0)) return ctx->fail(MBEFCI_EINVAL, "tolerances must be positive");
     if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
     if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
-    if (o->linked_rows < 0 || o->linked_rows > 4) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..4");
+    if (o->linked_rows < 0 || o->linked_rows > 5) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..5");
     ctx->opt = *o;
     return MBEFCI_OK;
 }
@@ -1626,7 +1695,7 @@ mbefci_status mbefci_tuple_sigma(mbefci_ctx *ctx, int32_t order, const int16_t *
     for (int v = 0; v < nvec; ++v) {
         VecRef c{const_cast<double *>(d_c), 0, nullptr, v};
         VecRef s{d_sigma, 0, nullptr, v};
-        hipError_t e = launch_sigma(b, c, s, ecore, false, false, ctx->stream, nullptr, nullptr, nullptr);
+        hipError_t e = launch_sigma(b, c, s, ecore, false, false, ctx->stream, nullptr, nullptr, nullptr, nullptr);
         if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));

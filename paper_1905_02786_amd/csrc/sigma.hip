@@ -370,12 +370,12 @@ static hipError_t launch_gemm_h(const Batch &b, VecRef c, VecRef sig, int skip, 
 
 
 hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done, bool dots,
-                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t evg, hipEvent_t ev2) {
     if (b.sigma_variant == SIGMA_STRIP) {
         if (ev0) (void)hipEventRecord(ev0, s);
-        hipError_t e = launch_strip(b, c, sig, shift, skip_done ? 1 : 0, s);
+        hipError_t e = launch_strip(b, c, sig, shift, skip_done ? 1 : 0, s, ev1);
         if (e != hipSuccess) return e;
-        if (ev1) (void)hipEventRecord(ev1, s);
+        if (evg) (void)hipEventRecord(evg, s);
         e = launch_gemm_h(b, c, sig, skip_done ? 1 : 0, dots ? 1 : 0, s);
         if (ev2) (void)hipEventRecord(ev2, s);
         return e;
@@ -393,6 +393,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1) (void)hipEventRecord(ev1, s);
+    if (evg) (void)hipEventRecord(evg, s);
     dim3 grid(grid_for(b.dim, 256, 4096), b.B);
     hipLaunchKernelGGL(k_sigma_g, grid, dim3(256), 0, s, b, c, sig, shift, skip_done ? 1 : 0);
     e = hipGetLastError();

@@ -1151,6 +1151,271 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
     }
 }
 
+// ---------------------------------------------- linked rows, W in HBM --
+// For alpha-string counts whose sigma strip leaves no LDS for the A rows
+// (n_A = 12 at 5 or 6 electrons of the spin: 792 and 924 strings) the linked
+// rows of W = A D are written to HBM instead of being scattered into an LDS
+// strip, and a second kernel gathers them: for target string J and column
+// I_b, sigma(J, I_b) = sum over the links K -> J of the link sign times
+// W(K, slot of the link)(I_b), plus its own diagonal-sum row.  Each W element
+// is written once and read once; the sum over the incoming links of J runs in
+// a fixed order.  Slots per string: 0 the diagonal sum, then the off-diagonal
+// links in link order, up to 48 (three MFMA row tiles).
+//
+// W kernel: one workgroup of eight waves per (tuple, 16-column strip), in two
+// halves of four; the alpha strings are taken in groups of four (one per
+// wave), group q belonging to half q % 2.  In phase p (one barrier after
+// each) half p % 2 runs the MFMAs of group p (each wave all three row tiles
+// of its string, B operands from the string's D tile, A rows resident in
+// LDS, slot 0 from the staged diagonal-sum row), while the other half writes
+// the W rows of its group p - 1 from the MFMA registers to HBM, writes D and
+// the diagonal-sum rows of its group p + 1 (values loaded two phases
+// earlier) and loads those of group p + 3.
+template <int NA>
+__global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int skip_done) {
+    constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4;
+    constexpr int RL = (KS + 1) / 2 * 8;
+    constexpr uint32_t RLB = RL * sizeof(double);
+    constexpr uint32_t DB = KP * kStrip * sizeof(double);     // one string's D
+    constexpr int NDI = (4 * KP * kStrip + 255) / 256;        // D items per thread of a half
+    const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
+    int t, strip_id;
+    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int z = wu >> 2, g = wu & 3;     // half, string of the group
+    const int th = tid & 255;
+    const int ar = lane & 15, kr = lane >> 4;
+    const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb, SW = (uint32_t)b.lw_slots;
+    const uint32_t B0 = (uint32_t)strip_id * kStrip;
+    const bool colok = B0 + ar < Nb;
+    extern __shared__ double lds[];
+    const uint32_t A0 = 8 * DB;                  // D [2 halves][4][KP][16] at 0, then A rows [P][RL]
+    const uint32_t G0 = A0 + P * RLB;            // diagonal-sum rows [2 halves][4][RL]
+    const double *c = vref(cref, t, b.dim);
+    double *W = b.lw + (int64_t)t * b.lw_stride;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
+                                                                        (int)(b.dim * sizeof(double)), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+        b.la + (int64_t)t * b.la_stride, (short)0, (int)(linked_a_rows(P, Na) * RLB), 0x00020000);
+    const uint32_t rowT = kLinkedRowsW * (uint32_t)sizeof(uint32_t);
+    const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(b.lrow_w), (short)0, (int)((Na + 1) * rowT), 0x00020000);
+    // D items of a half: element j = th + 256 i of its D [4][KP][16]
+    uint32_t boff[NDI], bsg[NDI];
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) {
+        const int j = th + 256 * i, q = (j >> 4) % KP;
+        const uint32_t eb = (colok && j < 4 * KP * kStrip && q < P) ? b.pairB[(B0 + ar) * (uint32_t)P + q] : 0u;
+        const bool vb = (eb & kPairValid) != 0;
+        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
+        bsg[i] = vb ? (eb & kPairSign) : 0u;
+    }
+    auto item_on = [&](int i) { return 256 * (i + 1) <= 4 * KP * kStrip || 64 * g + 256 * i < 4 * KP * kStrip; };
+    auto item_str = [&](int i) { return (64 * g + 256 * i) / (KP * kStrip); };
+    const uint32_t rowC = Nb * (uint32_t)sizeof(double);
+    auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    auto crow = [&](uint32_t s) -> uint32_t { return s < Na ? s : 0u; };
+    auto trow = [&](uint32_t s) -> uint32_t { return s < Na ? s : Na; };
+    auto load_c = [&](uint32_t s, int i) -> double {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[i], crow(s) * rowC, 0));
+    };
+    auto load_row = [&](uint32_t s, int h) -> uint32_t {   // A-row offset of this lane's slot 16 h + ar
+        return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u, trow(s) * rowT, 0);
+    };
+    const bool dgl = lane < RL / 2;
+    auto load_dg = [&](uint32_t s) -> dbl2v {
+        const uint32_t r = (uint32_t)P + (s < Na ? s : 0u);
+        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, r * RLB, 0));
+    };
+    auto dval = [&](double v, int i) -> double {
+        return __hiloint2double(__double2hiint(v) ^ (int)bsg[i], __double2loint(v));
+    };
+    const uint32_t dw = (uint32_t)z * 4 * DB + (uint32_t)th * (uint32_t)sizeof(double);
+    const uint32_t dr = (uint32_t)(4 * z + g) * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
+    const uint32_t gd = G0 + (uint32_t)(4 * z + g) * RLB;
+    const uint32_t gw = gd + (uint32_t)lane * 16u;
+
+    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 512)
+        *reinterpret_cast<dbl2v *>(lds_at(A0 + 16u * i)) =
+            __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * i, 0, 0));
+    // prologue: half 0 stages group 0 and holds the loads of group 2; half 1
+    // holds the loads of group 1
+    uint32_t ra[3] = {0u, 0u, 0u}, rap[3];
+    double cb[NDI];
+    dbl2v dg = {0.0, 0.0};
+    if (z == 0) {
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(load_c((uint32_t)item_str(i), i), i);
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = load_dg((uint32_t)g);
+#pragma unroll
+        for (int h = 0; h < 3; ++h) ra[h] = load_row((uint32_t)g, h);
+    }
+    const uint32_t q0 = z == 0 ? 2u : 1u;
+#pragma unroll
+    for (int i = 0; i < NDI; ++i) cb[i] = item_on(i) ? load_c(4 * q0 + item_str(i), i) : 0.0;
+    if (dgl) dg = load_dg(4 * q0 + g);
+#pragma unroll
+    for (int h = 0; h < 3; ++h) rap[h] = load_row(4 * q0 + g, h);
+    dbl4 acc[3];
+#pragma unroll
+    for (int h = 0; h < 3; ++h) acc[h] = dbl4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+
+    // MFMAs of group q: this wave's string, all three row tiles
+    auto mphase = [&]() {
+        double bv[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = *lds_at(dr + ks * 4u * kStrip * (uint32_t)sizeof(double));
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            double af[KS];
+            const uint32_t arow = ((h == 0 && ar == 0) ? gd : A0 + ra[h]) + (uint32_t)kr * 16u;
+#pragma unroll
+            for (int j = 0; j < KS / 2; ++j) {
+                const dbl2v v = *reinterpret_cast<const dbl2v *>(lds_at(arow + 64u * j));
+                af[2 * j] = v[0];
+                af[2 * j + 1] = v[1];
+            }
+            if (KS & 1) af[KS - 1] = *lds_at(arow + 64u * (KS / 2));
+            dbl4 a = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
+            acc[h] = a;
+        }
+    };
+    // phase p of the other half: W rows of its group p - 1; D and
+    // diagonal-sum rows of group p + 1; loads of group p + 3
+    auto nphase = [&](uint32_t p) {
+        const uint32_t sw = 4 * (p - 1) + g;   // wraps past Na for p = 0
+        if (sw < Na && colok) {
+            double *wrow = W + ((int64_t)sw * SW) * Nb + B0 + ar;
+#pragma unroll
+            for (int h = 0; h < 3; ++h)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t slot = 16 * h + kr + 4 * v;
+                    if (slot < SW) wrow[(int64_t)slot * Nb] = acc[h][v];
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(cb[i], i);
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = dg;
+#pragma unroll
+        for (int h = 0; h < 3; ++h) ra[h] = rap[h];
+#pragma unroll
+        for (int i = 0; i < NDI; ++i)
+            if (item_on(i)) cb[i] = load_c(4 * (p + 3) + item_str(i), i);
+        if (dgl) dg = load_dg(4 * (p + 3) + g);
+#pragma unroll
+        for (int h = 0; h < 3; ++h) rap[h] = load_row(4 * (p + 3) + g, h);
+    };
+    const uint32_t nph = (Na + 3) / 4 + 1;   // groups, and the last group's W in the phase after
+    if (z == 0) {
+        for (uint32_t p = 0; p < nph; p += 2) {
+            mphase();
+            __syncthreads();
+            nphase(p + 1);
+            __syncthreads();
+        }
+    } else {
+        for (uint32_t p = 0; p < nph; p += 2) {
+            nphase(p);
+            __syncthreads();
+            mphase();
+            __syncthreads();
+        }
+    }
+}
+
+// Gather: sigma(J, I_b) = sum_i sign_i W(row_i)(I_b) + shift c(J, I_b) over the
+// incoming rows of J (table linc [N_a][ninc]: W row index K * SW + slot, bit
+// 31 the link sign; entry 0 is J's own diagonal-sum row), in table order.
+// One block per (512 columns, target string, tuple), two columns per thread
+// (16-byte loads when N_b is even, so that every W row starts 16-byte
+// aligned); the table row is staged in LDS and all loads of a column pair
+// are issued before the ordered sum.
+template <bool V2>
+__global__ __launch_bounds__(256) void k_linked_gw(Batch b, VecRef cref, VecRef sref, double shift, int skip_done) {
+    const int t = blockIdx.z;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const uint32_t J = blockIdx.y, Nb = (uint32_t)b.Nb;
+    const int ninc = b.lw_ninc;
+    __shared__ uint32_t sinc[kLinkedRowsW];
+    if ((int)threadIdx.x < ninc) sinc[threadIdx.x] = b.linc[(size_t)J * ninc + threadIdx.x];
+    __syncthreads();
+    const uint32_t ib = blockIdx.x * 512u + 2u * threadIdx.x;
+    if (ib >= Nb) return;
+    const double *W = b.lw + (int64_t)t * b.lw_stride;
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const int64_t d = (int64_t)J * Nb + ib;
+    if (V2) {
+        dbl2v w[kLinkedRowsW];
+#pragma unroll
+        for (int i = 0; i < kLinkedRowsW; ++i)
+            if (i < ninc) w[i] = *reinterpret_cast<const dbl2v *>(W + (int64_t)(sinc[i] & 0x7FFFFFFFu) * Nb + ib);
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < kLinkedRowsW; ++i)
+            if (i < ninc) {
+                const bool neg = sinc[i] >> 31;
+                a0 += neg ? -w[i][0] : w[i][0];
+                a1 += neg ? -w[i][1] : w[i][1];
+            }
+        const dbl2v cv = *reinterpret_cast<const dbl2v *>(c + d);
+        *reinterpret_cast<dbl2v *>(sg + d) = dbl2v{a0 + shift * cv[0], a1 + shift * cv[1]};
+    } else {
+        const bool two = ib + 1 < Nb;
+        double w0[kLinkedRowsW], w1[kLinkedRowsW];
+#pragma unroll
+        for (int i = 0; i < kLinkedRowsW; ++i)
+            if (i < ninc) {
+                const double *r = W + (int64_t)(sinc[i] & 0x7FFFFFFFu) * Nb + ib;
+                w0[i] = r[0];
+                w1[i] = two ? r[1] : 0.0;
+            }
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < kLinkedRowsW; ++i)
+            if (i < ninc) {
+                const bool neg = sinc[i] >> 31;
+                a0 += neg ? -w0[i] : w0[i];
+                a1 += neg ? -w1[i] : w1[i];
+            }
+        sg[d] = a0 + shift * c[d];
+        if (two) sg[d + 1] = a1 + shift * c[d + 1];
+    }
+}
+
+static size_t linked_lds_w(const ParamLayout &pl) {
+    const size_t rl = (size_t)linked_row_len(pl.Kpad);
+    return sizeof(double) * (8 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 8) * rl);
+}
+
+bool linked_w_fits(const ParamLayout &pl, int64_t Na, int nel) {
+    return pl.nA >= 4 && pl.nA <= kMaxActive && 1 + nel * (pl.nA - nel) <= kLinkedRowsW &&
+           linked_lds_w(pl) <= 160 * 1024 && Na < (1 << 24);
+}
+
+template <int NA>
+static hipError_t launch_linked_w_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s,
+                                     hipEvent_t ev_mid) {
+    const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
+    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
+    hipLaunchKernelGGL(k_linked_wr<NA>, grid, dim3(512), linked_lds_w(b.pl), s, b, c, skip);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_mid) (void)hipEventRecord(ev_mid, s);
+    const dim3 gg((unsigned)((b.Nb + 511) / 512), (unsigned)b.Na, (unsigned)b.B);
+    if ((b.Nb & 1) == 0) hipLaunchKernelGGL(k_linked_gw<true>, gg, dim3(256), 0, s, b, c, sig, shift, skip);
+    else hipLaunchKernelGGL(k_linked_gw<false>, gg, dim3(256), 0, s, b, c, sig, shift, skip);
+    return hipGetLastError();
+}
+
 // The resident-A kernel (A rows in LDS, one twelve-wave workgroup in three
 // thirds) needs more LDS than the gathered-A kernel (four waves, A rows
 // loaded through the vector memory path, which they saturate).  It runs
@@ -1168,6 +1433,7 @@ static bool use_resident(const Batch &b) {
 int alpha_beta_kernel(const Batch &b) {
     if (b.sigma_variant != SIGMA_STRIP) return 4;
     if (!b.la) return 0;
+    if (b.lw) return 5;
     if (b.linked_dv) return 3;
     return use_resident(b) ? 2 : 1;
 }
@@ -1197,7 +1463,30 @@ static hipError_t launch_strip_na(const Batch &b, VecRef c, VecRef sig, double s
     return hipGetLastError();
 }
 
-hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
+static hipError_t launch_strip_one(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s);
+
+hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s,
+                        hipEvent_t ev_mid) {
+    if (b.lw) {   // linked rows through W in HBM (the planner checked linked_w_fits)
+        switch (b.nA) {
+            case 4: return launch_linked_w_na<4>(b, c, sig, shift, skip, s, ev_mid);
+            case 5: return launch_linked_w_na<5>(b, c, sig, shift, skip, s, ev_mid);
+            case 6: return launch_linked_w_na<6>(b, c, sig, shift, skip, s, ev_mid);
+            case 7: return launch_linked_w_na<7>(b, c, sig, shift, skip, s, ev_mid);
+            case 8: return launch_linked_w_na<8>(b, c, sig, shift, skip, s, ev_mid);
+            case 9: return launch_linked_w_na<9>(b, c, sig, shift, skip, s, ev_mid);
+            case 10: return launch_linked_w_na<10>(b, c, sig, shift, skip, s, ev_mid);
+            case 11: return launch_linked_w_na<11>(b, c, sig, shift, skip, s, ev_mid);
+            case 12: return launch_linked_w_na<12>(b, c, sig, shift, skip, s, ev_mid);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    hipError_t e = launch_strip_one(b, c, sig, shift, skip, s);
+    if (e == hipSuccess && ev_mid) (void)hipEventRecord(ev_mid, s);
+    return e;
+}
+
+static hipError_t launch_strip_one(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s) {
     if (b.la) {   // linked-row variant (the planner checked linked_fits)
         switch (b.nA) {
             case 4: return launch_linked_na<4>(b, c, sig, shift, skip, s);
@@ -1254,7 +1543,12 @@ hipError_t init_strip_kernels() {
                             (const void *)k_sigma_linked_dv<6>,  (const void *)k_sigma_linked_dv<7>,
                             (const void *)k_sigma_linked_dv<8>,  (const void *)k_sigma_linked_dv<9>,
                             (const void *)k_sigma_linked_dv<10>, (const void *)k_sigma_linked_dv<11>,
-                            (const void *)k_sigma_linked_dv<12>, (const void *)k_sigma_linked_dv<13>};
+                            (const void *)k_sigma_linked_dv<12>, (const void *)k_sigma_linked_dv<13>,
+                            (const void *)k_linked_wr<4>,  (const void *)k_linked_wr<5>,
+                            (const void *)k_linked_wr<6>,  (const void *)k_linked_wr<7>,
+                            (const void *)k_linked_wr<8>,  (const void *)k_linked_wr<9>,
+                            (const void *)k_linked_wr<10>, (const void *)k_linked_wr<11>,
+                            (const void *)k_linked_wr<12>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

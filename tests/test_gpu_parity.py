@@ -125,8 +125,9 @@ def _sigma_reference(name, S):
 # (sigma_variant, linked_rows): column strip with linked rows where n_A >= 9
 # (the default), column strip on all pair rows, linked rows wherever they fit
 # with the A rows gathered (2) or resident in LDS (3), the form with the
-# diagonal sums on the vector ALU wherever it fits (4), materialised W
-@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (1, 2), (1, 3), (1, 4), (2, 1)])
+# diagonal sums on the vector ALU wherever it fits (4), the linked rows
+# through W in the workspace wherever it fits (5), materialised W
+@pytest.mark.parametrize("variant,linked", [(1, 1), (1, 0), (1, 2), (1, 3), (1, 4), (1, 5), (2, 1)])
 @pytest.mark.parametrize("name,S", SIGMA_CASES)
 def test_hdiag_and_sigma_match_oracle(ws, name, S, variant, linked):
     P = _problem(name)

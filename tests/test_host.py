@@ -150,10 +150,10 @@ def test_invalid_inputs_rejected():
         with pytest.raises(M.MBEFCIError):
             ctx.set_options(pspace=bad_psp)
     ctx.set_options(pspace=0)
-    for bad_lr in (-1, 5):
+    for bad_lr in (-1, 6):
         with pytest.raises(M.MBEFCIError):
             ctx.set_options(linked_rows=bad_lr)
-    for lr in (0, 1, 2, 3, 4):
+    for lr in (0, 1, 2, 3, 4, 5):
         ctx.set_options(linked_rows=lr)
     # full-layout integrals must be 8-fold symmetric
     asym = np.zeros((4,) * 4)
