@@ -1172,16 +1172,20 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
 // the diagonal-sum rows of its group p + 1 (values loaded two phases
 // earlier) and loads those of group p + 3.
 template <int NA>
-__global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int skip_done) {
+__global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int skip_done, int aparts) {
     constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4;
     constexpr int RL = (KS + 1) / 2 * 8;
     constexpr uint32_t RLB = RL * sizeof(double);
     constexpr uint32_t DB = KP * kStrip * sizeof(double);     // one string's D
     constexpr int NDI = (4 * KP * kStrip + 255) / 256;        // D items per thread of a half
     const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
-    int t, strip_id;
-    if (!xcd_map(blockIdx.x, nstrips, b.B, t, strip_id)) return;
+    int t, sp;
+    if (!xcd_map(blockIdx.x, nstrips * aparts, b.B, t, sp)) return;
     if (skip_done && b.status[t] != ST_RUNNING) return;
+    // a workgroup owns a 16-column strip and one of `aparts` consecutive
+    // ranges of the string groups (small batches split the strings to fill
+    // the chip; the W rows do not depend on the split)
+    const int strip_id = sp / aparts, part = sp % aparts;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int z = wu >> 2, g = wu & 3;     // half, string of the group
@@ -1190,6 +1194,10 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
     const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb, SW = (uint32_t)b.lw_slots;
     const uint32_t B0 = (uint32_t)strip_id * kStrip;
     const bool colok = B0 + ar < Nb;
+    const uint32_t ngr = (Na + 3) / 4, gpp = (ngr + aparts - 1) / aparts;
+    const uint32_t qb = (uint32_t)part * gpp, qe = qb + gpp < ngr ? qb + gpp : ngr;
+    if (qb >= ngr) return;   // an empty part (the whole workgroup)
+    const uint32_t S0 = 4 * qb, Nend = 4 * qe < Na ? 4 * qe : Na;   // strings [S0, Nend) of this part
     extern __shared__ double lds[];
     const uint32_t A0 = 8 * DB;                  // D [2 halves][4][KP][16] at 0, then A rows [P][RL]
     const uint32_t G0 = A0 + P * RLB;            // diagonal-sum rows [2 halves][4][RL]
@@ -1216,8 +1224,10 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
     auto item_str = [&](int i) { return (64 * g + 256 * i) / (KP * kStrip); };
     const uint32_t rowC = Nb * (uint32_t)sizeof(double);
     auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
-    auto crow = [&](uint32_t s) -> uint32_t { return s < Na ? s : 0u; };
-    auto trow = [&](uint32_t s) -> uint32_t { return s < Na ? s : Na; };
+    // strings of the part, local index s (string S0 + s); past the part's end:
+    // any C row, the discard table row, no W written
+    auto crow = [&](uint32_t s) -> uint32_t { return S0 + s < Nend ? S0 + s : 0u; };
+    auto trow = [&](uint32_t s) -> uint32_t { return S0 + s < Nend ? S0 + s : Na; };
     auto load_c = [&](uint32_t s, int i) -> double {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[i], crow(s) * rowC, 0));
     };
@@ -1226,7 +1236,7 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
     };
     const bool dgl = lane < RL / 2;
     auto load_dg = [&](uint32_t s) -> dbl2v {
-        const uint32_t r = (uint32_t)P + (s < Na ? s : 0u);
+        const uint32_t r = (uint32_t)P + crow(s);
         return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, r * RLB, 0));
     };
     auto dval = [&](double v, int i) -> double {
@@ -1289,8 +1299,8 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
     // phase p of the other half: W rows of its group p - 1; D and
     // diagonal-sum rows of group p + 1; loads of group p + 3
     auto nphase = [&](uint32_t p) {
-        const uint32_t sw = 4 * (p - 1) + g;   // wraps past Na for p = 0
-        if (sw < Na && colok) {
+        const uint32_t sw = S0 + 4 * (p - 1) + g;   // wraps past Nend for p = 0
+        if (4 * (p - 1) + g < Nend - S0 && colok) {
             double *wrow = W + ((int64_t)sw * SW) * Nb + B0 + ar;
 #pragma unroll
             for (int h = 0; h < 3; ++h)
@@ -1313,7 +1323,7 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
 #pragma unroll
         for (int h = 0; h < 3; ++h) rap[h] = load_row(4 * (p + 3) + g, h);
     };
-    const uint32_t nph = (Na + 3) / 4 + 1;   // groups, and the last group's W in the phase after
+    const uint32_t nph = (qe > qb ? qe - qb : 0) + 1;   // groups, and the last group's W in the phase after
     if (z == 0) {
         for (uint32_t p = 0; p < nph; p += 2) {
             mphase();
@@ -1405,8 +1415,13 @@ template <int NA>
 static hipError_t launch_linked_w_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s,
                                      hipEvent_t ev_mid) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
-    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips));
-    hipLaunchKernelGGL(k_linked_wr<NA>, grid, dim3(512), linked_lds_w(b.pl), s, b, c, skip);
+    // at least two workgroups per CU: split the string groups of a strip
+    // over up to four workgroups when the batch alone does not give that
+    const int64_t ngr = (b.Na + 3) / 4;
+    int aparts = 1;
+    while (aparts < 4 && (int64_t)b.B * nstrips * aparts < 512 && ngr >= 8 * (aparts + 1)) ++aparts;
+    const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips * aparts));
+    hipLaunchKernelGGL(k_linked_wr<NA>, grid, dim3(512), linked_lds_w(b.pl), s, b, c, skip, aparts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid) (void)hipEventRecord(ev_mid, s);
