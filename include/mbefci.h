@@ -239,6 +239,21 @@ mbefci_status mbefci_solve_tuples(mbefci_ctx *ctx, int32_t order, int64_t ntup,
                                   const int16_t *tuples, void *d_workspace, size_t ws_bytes,
                                   double *energies, int32_t *status);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mbefci_solve_tuples with the workspace taken from a static device array of
+ * 128 MiB that the library holds on every GPU it runs on until the process
+ * ends (allocated with the code object, never by this call; the call itself
+ * makes no hipMalloc, hipFree or other allocating device call).  Same
+ * arguments, results and errors as mbefci_solve_tuples, plus ENOMEM when one
+ * tuple needs more than 128 MiB (see mbefci_workspace_query); batches are cut
+ * to fit.  Every call on one GPU shares that GPU's array, and the array keeps
+ * the last call's contents (nothing in it is read before it is written):
+ * calls that overlap on one GPU -- two contexts on one device, or two host
+ * threads -- race and must be serialised by the caller. */
+mbefci_status mbefci_solve_tuples_noalloc(mbefci_ctx *ctx, int32_t order, int64_t ntup,
+                                          const int16_t *tuples, double *energies, int32_t *status);
+
 /* The whole expansion (Eq. 1-3): order 0 ([Pi] alone), then orders 1.. up to
  * max_order, |X| or until screening leaves no tuple.  *out receives a result
  * owned by the caller (mbefci_result_free).  ENOCONV leaves *out valid. */

@@ -56,6 +56,7 @@ SIGNATURES = [
                                          ctypes.POINTER(c_size_t), ctypes.POINTER(c_size_t)]),
     ("mbefci_solve_tuples", c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t,
                                       c_void_p, c_void_p]),
+    ("mbefci_solve_tuples_noalloc", c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
     ("mbefci_run", c_int32, [c_void_p, c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),
     ("mbefci_run_host", c_int32, [c_void_p, ENERGY_FN, c_void_p, ctypes.POINTER(c_void_p)]),
     ("mbefci_result_norders", c_int32, [c_void_p]),

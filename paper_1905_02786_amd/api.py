@@ -187,6 +187,17 @@ class Context:
         self._check(rc, allow=(-4,) if allow_noconv else ())
         return e, st
 
+    def solve_tuples_noalloc(self, order, tuples, allow_noconv=False):
+        """eps(S) for each tuple row with the library's static device workspace
+        (no device allocation; calls on one GPU must not overlap)."""
+        t = self._tuples(order, tuples)
+        n = t.shape[0]
+        e = np.zeros(n)
+        st = np.zeros(n, dtype=np.int32)
+        rc = self.L.mbefci_solve_tuples_noalloc(self.ptr, order, n, _p(t) if t.size else None, _p(e), _p(st))
+        self._check(rc, allow=(-4,) if allow_noconv else ())
+        return e, st
+
     def run(self, workspace, allow_noconv=False, keep=False):
         """The whole expansion.  keep=True returns (Result, ResultHandle) so
         that backward() can use the library's copy of the tuple set."""

@@ -135,6 +135,10 @@ struct Batch {
 
 // kernels.hip, sigma.hip and strip.hip
 hipError_t init_kernels();
+// Static device workspace of mbefci_solve_tuples_noalloc: 128 MiB per device.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+// Its device address on the current device (hipGetSymbolAddress).
+hipError_t scratch_address(void **ptr);
 hipError_t init_sigma_kernels();   // LDS limits of the sigma kernels (called by init_kernels)
 hipError_t init_strip_kernels();   // the same for the strip kernels (called by init_sigma_kernels)
 // alpha-beta term of sigma (column strip, strip.hip): sig = X + shift c

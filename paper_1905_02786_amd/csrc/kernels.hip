@@ -1524,6 +1524,18 @@ hipError_t launch_finalize(const Batch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The workspace of the allocation-free entry point: a file-scope device array
+// that the code object brings (each GPU the library runs on holds its own
+// copy until the process ends).  Host code never passes its name to a kernel
+// or a copy: scratch_address() resolves it once per device, with that device
+// current, and callers use the returned pointer.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **ptr) {
+    *ptr = nullptr;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 hipError_t init_kernels() {
     hipError_t e = init_sigma_kernels();
     if (e != hipSuccess) return e;

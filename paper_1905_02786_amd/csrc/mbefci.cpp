@@ -291,6 +291,8 @@ struct mbefci_ctx {
     // device gradient accumulators of the running gradient pass (in the
     // caller's workspace, past the part the batches use)
     double *d_gh = nullptr, *d_ge = nullptr;
+    // the static device workspace of this context's device (resolved at creation)
+    void *scratch = nullptr;
     // spaces
     bool spaces_set = false;
     int nalpha = 0, nbeta = 0, nfrozen = 0;
@@ -1355,6 +1357,7 @@ mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
         for (auto &e : ctx->ev)
             if (hipEventCreate(&e) != hipSuccess) return MBEFCI_EDEVICE;
         if (init_kernels() != hipSuccess) return MBEFCI_EDEVICE;
+        if (scratch_address(&ctx->scratch) != hipSuccess || !ctx->scratch) return MBEFCI_EDEVICE;
     }
     *out = ctx.release();
     return MBEFCI_OK;
@@ -1542,6 +1545,29 @@ mbefci_status mbefci_solve_tuples(mbefci_ctx *ctx, int32_t order, int64_t ntup, 
     ctx->sigma_cls = nullptr;
     const double t0 = now_ms();
     mbefci_status rc = solve_device(ctx, order, ntup, tuples, ws, wsb, energies, status);
+    ctx->stats.solve_ms = now_ms() - t0;
+    return rc;
+}
+
+mbefci_status mbefci_solve_tuples_noalloc(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples,
+                                          double *energies, int32_t *status) {
+    if (!ctx) return MBEFCI_EINVAL;
+    if (ctx->host_only || !ctx->scratch) return ctx->fail(MBEFCI_ESTATE, "host-only context");
+    if (!energies || !status || order < 0) return ctx->fail(MBEFCI_EINVAL, "null output");
+    if (!ctx->spaces_set) return ctx->fail(MBEFCI_ESTATE, "no spaces set");
+    if (ntup > 0) {
+        size_t mn = 0, want = 0;
+        mbefci_status rq = mbefci_workspace_query(ctx, order, ntup, tuples, &mn, &want);
+        if (rq != MBEFCI_OK) return rq;
+        if (mn > kScratchBytes)
+            return ctx->fail(MBEFCI_ENOMEM, "a tuple needs " + std::to_string(mn) + " bytes of workspace; the static "
+                                            "workspace holds " + std::to_string(kScratchBytes));
+    }
+    ctx->stats = mbefci_stats{};
+    ctx->cstats.clear();
+    ctx->sigma_cls = nullptr;
+    const double t0 = now_ms();
+    mbefci_status rc = solve_device(ctx, order, ntup, tuples, ctx->scratch, kScratchBytes, energies, status);
     ctx->stats.solve_ms = now_ms() - t0;
     return rc;
 }
