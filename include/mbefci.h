@@ -135,7 +135,20 @@ typedef struct {
                                caller then solves in slices with mbefci_order_solve and ends with
                                mbefci_order_close: the same result as one call, for orders too
                                large to solve in one go (default 0) */
-    int32_t reserved[3];
+    int32_t graph;          /* with profile = 0 the Davidson iterations of a batch run in blocks of
+                               4-8 launched back to back (the running count is read once per
+                               block; finished tuples are skipped by every kernel), and with
+                               graph = 1 (default) one iteration's launches are captured once per
+                               batch in a hipGraph on a private stream and replayed on the
+                               context's stream.  profile = 1 keeps one host round trip per
+                               iteration (every sigma launch timed).  Same results. */
+    int32_t autotune;       /* 1 (default): with the automatic settings (linked_rows 1,
+                               sigma_variant 0) the alpha-beta sigma form and the GEMM tile of
+                               every shape class of at least 10^4 determinants are chosen by
+                               timing one sigma of each candidate on up to 16 of its tuples, once
+                               per process and device (the choice is kept, so repeated runs are
+                               bitwise identical; processes can differ in the last bits) */
+    int32_t reserved[1];
 } mbefci_options;
 
 typedef struct {
@@ -155,6 +168,8 @@ typedef struct {
     int64_t second_pass;        /* tuples solved again in the second pass (see max_iter) */
     double gather_ms;           /* HIP-event time of the gather of the W-in-HBM linked form (profile = 1;
                                    sigma_ms holds that form's MFMA kernel alone) */
+    int64_t graph_batches;      /* batches whose iteration ran as a captured hipGraph */
+    int64_t tuned_classes;      /* shape classes timed by the autotuner in this call */
 } mbefci_stats;
 
 /* Counters of one shape class (active orbitals, active alpha and beta

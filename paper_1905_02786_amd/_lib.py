@@ -20,7 +20,7 @@ class Options(ctypes.Structure):
                 ("max_iter", c_int32), ("max_space", c_int32), ("batched", c_int32),
                 ("gradient", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
                 ("pspace", c_int32), ("linked_rows", c_int32), ("stream_last", c_int32),
-                ("reserved", c_int32 * 3)]
+                ("graph", c_int32), ("autotune", c_int32), ("reserved", c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -28,7 +28,8 @@ class Stats(ctypes.Structure):
                 ("sigma_flops", c_double), ("sigma_bytes", c_double), ("sigma_ms", c_double),
                 ("sigma_total_ms", c_double), ("iterations_total", c_int64),
                 ("iterations_max", c_int64), ("solve_ms", c_double),
-                ("gs_second_pass", c_int64), ("second_pass", c_int64), ("gather_ms", c_double)]
+                ("gs_second_pass", c_int64), ("second_pass", c_int64), ("gather_ms", c_double),
+                ("graph_batches", c_int64), ("tuned_classes", c_int64)]
 
 
 class ClassStats(ctypes.Structure):

@@ -88,6 +88,7 @@ struct Batch {
     int lpairs;
     int linked_mode;        // 1: variant by occupancy, 2: gathered A, 3: resident A (where it fits)
     int linked_dv;          // slots hold the off-diagonal links only; diagonal sums on the vector ALU
+    int gemm_tile;          // string-Hamiltonian GEMM output tile (64, 96; 0: by padding)
     // linked rows through W in HBM (null lw: not this form): per alpha string
     // the A-row offsets of its 48 slots [Na + 1][48], W [B][Na * lw_slots * Nb],
     // and per target string its incoming W rows [Na][lw_ninc]

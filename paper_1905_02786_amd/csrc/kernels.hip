@@ -755,6 +755,7 @@ __global__ void k_init_state(Batch b) {
     b.theta[t] = 0.0;
     b.theta_prev[t] = 1e300;
     b.R[(int64_t)t * kMaxSpace * kMaxSpace] = 1.0;   // V_0 is normalised: Q_0 = V_0
+    if (t == 0) b.counter[2] = 0;   // explicit Gram-Schmidt passes of the batch
 }
 
 hipError_t launch_init_state(const Batch &b, hipStream_t s) {
@@ -1131,7 +1132,10 @@ __global__ void k_coef1(Batch b) {
     if (i == 0) b.cgs2[t] = two;
     if (two) {
         if (i < m) b.coef[(int64_t)t * kMaxSpace + i] = a;
-        if (i == 0) atomicAdd(b.counter + 1, 1);   // the host launches the explicit passes only if some tuple needs them
+        if (i == 0) {
+            atomicAdd(b.counter + 1, 1);   // this iteration (the profiled loop launches the passes only then)
+            atomicAdd(b.counter + 2, 1);   // the whole batch
+        }
         return;
     }
     if (!(kept > 1e-300) || m >= b.max_space) {

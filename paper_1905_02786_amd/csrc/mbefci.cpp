@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <unordered_map>
@@ -279,6 +280,7 @@ struct mbefci_ctx {
     int device = -1;
     bool host_only = true;
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream the Davidson iteration is captured on (graph mode)
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // sigma start, MFMA kernel end, gather end, end
     std::string err;
     // Hamiltonian
@@ -293,6 +295,7 @@ struct mbefci_ctx {
     double *d_gh = nullptr, *d_ge = nullptr;
     // the static device workspace of this context's device (resolved at creation)
     void *scratch = nullptr;
+    int gemm_tile = 0;   // GEMM tile of the batches being carved (autotuner choice; 0: by padding)
     // spaces
     bool spaces_set = false;
     int nalpha = 0, nbeta = 0, nfrozen = 0;
@@ -545,6 +548,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
         b.Ha = b.na == b.nb ? b.Hb : cv.take<double>((size_t)B * b.Na * b.Na);
     }
     b.nblk = cp.nblk;
+    b.gemm_tile = ctx->gemm_tile;
     b.part = cv.take<double>((size_t)B * (b.nblk + 1) * kParts);
     b.psp = cp.psp;
     if (cp.psp > 0) {
@@ -572,7 +576,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.restart = cv.take<int32_t>(B);
     b.out_status = cv.take<int32_t>(B);
     b.cgs2 = cv.take<int32_t>(B);
-    b.counter = cv.take<int32_t>(2);
+    b.counter = cv.take<int32_t>(3);
     b.nblk_r = cp.nblk_r;
     if (cp.rdm) {
         b.rdm_part = cv.take<double>((size_t)B * cp.nblk_r * cp.NP * cp.NP);
@@ -723,20 +727,68 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     };
     mbefci_status rc = sigma_and_G(b.B);
     if (rc != MBEFCI_OK) return rc;
-    int32_t cnt[2] = {b.B, 0};   // running tuples; those of them that need the explicit Gram-Schmidt passes
-    int iters = 0;
-    for (int it = 0; it <= b.max_iter; ++it) {
-        if ((e = launch_iter_head(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-        HIPCHK(hipMemcpyAsync(cnt, b.counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        flush_sigma_time(ctx);
-        ++iters;
-        if (cnt[0] == 0) break;
-        ctx->stats.gs_second_pass += cnt[1];
-        if (cnt[1] > 0 && (e = launch_orthonormalize(b, s)) != hipSuccess)
-            return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
-        rc = sigma_and_G(cnt[0]);
-        if (rc != MBEFCI_OK) return rc;
+    int32_t cnt[3] = {b.B, 0, 0};   // running tuples; of them those that need the explicit Gram-Schmidt
+                                    // passes; explicit passes of the whole batch
+    const bool prof = ctx->opt.profile != 0;
+    if (prof) {
+        // one iteration per host round trip: the sigma launch of every
+        // iteration is timed with events, and the explicit Gram-Schmidt
+        // passes are launched only when some tuple needs them
+        for (int it = 0; it <= b.max_iter; ++it) {
+            if ((e = launch_iter_head(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+            HIPCHK(hipMemcpyAsync(cnt, b.counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            flush_sigma_time(ctx);
+            if (cnt[0] == 0) break;
+            if (cnt[1] > 0 && (e = launch_orthonormalize(b, s)) != hipSuccess)
+                return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+            rc = sigma_and_G(cnt[0]);
+            if (rc != MBEFCI_OK) return rc;
+        }
+    } else {
+        // Iterations in blocks launched back to back, the running count read
+        // once per block: every kernel skips the tuples that are no longer
+        // running (the explicit Gram-Schmidt kernels also those whose
+        // correction does not need them), so the result is that of one
+        // iteration per round trip.  With options.graph the iteration's
+        // launches are captured once per batch in a hipGraph (on a private
+        // stream) and the graph is replayed on the context's stream.
+        const bool fused = sigma_fuses_dots(b);
+        auto one_iter = [&](hipStream_t st) -> hipError_t {
+            hipError_t e1 = launch_iter_head(b, st);
+            if (e1 != hipSuccess) return e1;
+            if ((e1 = launch_orthonormalize(b, st)) != hipSuccess) return e1;
+            if ((e1 = launch_sigma(b, vm, sm, 0.0, true, fused, st, nullptr, nullptr, nullptr, nullptr)) != hipSuccess)
+                return e1;
+            return fused ? launch_update_G(b, gemm_blocks(b), st) : launch_dots(b, sm, 1, st);
+        };
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (ctx->opt.graph && ctx->cap_stream) {
+            if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess) {
+                const hipError_t ec = one_iter(ctx->cap_stream);
+                const hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &graph);
+                if (ec == hipSuccess && ee == hipSuccess && graph &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                    exec = nullptr;
+            }
+            (void)hipGetLastError();   // a capture that did not work leaves the direct launches
+            if (exec) ++ctx->stats.graph_batches;
+        }
+        int block = 4;
+        for (int it = 0; it <= b.max_iter + block; it += block) {
+            for (int j = 0; j < block; ++j) {
+                e = exec ? hipGraphLaunch(exec, s) : one_iter(s);
+                if (e != hipSuccess) break;
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(cnt, b.counter, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess || cnt[0] == 0) break;
+            block = std::min(block + 2, 8);
+        }
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, std::string("Davidson iterations: ") + hipGetErrorString(e));
     }
     if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if (ro) {
@@ -764,6 +816,22 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     mbefci_class_stats &cs = class_stats(ctx, b);
     cs.tuples += b.B;
     for (int t = 0; t < b.B; ++t) cs.iterations += dit[t];
+    {
+        int32_t gs = 0;
+        HIPCHK(hipMemcpy(&gs, b.counter + 2, sizeof(int32_t), hipMemcpyDeviceToHost));
+        ctx->stats.gs_second_pass += gs;
+    }
+    if (!prof) {
+        // sigma applications: the first, then one per iteration that a tuple
+        // leaves still running (counted by run_sigma in the profiled loop)
+        int64_t apps = 0;
+        for (int t = 0; t < b.B; ++t) apps += std::max(0, dit[t] - 1);
+        ctx->stats.sigma_calls += apps;
+        ctx->stats.sigma_flops += (double)apps * sigma_flops(b);
+        ctx->stats.sigma_bytes += (double)apps * sigma_bytes(b);
+        cs.sigma_calls += apps;
+        cs.sigma_flops += (double)apps * sigma_flops(b);
+    }
     for (int t = 0; t < b.B; ++t) {
         const int32_t d = dst[t];
         st_out[t] = d == ST_DONE ? MBEFCI_TUPLE_OK
@@ -773,7 +841,6 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
         ctx->stats.iterations_total += dit[t];
         ctx->stats.iterations_max = std::max<int64_t>(ctx->stats.iterations_max, dit[t]);
     }
-    (void)iters;
     return MBEFCI_OK;
 }
 
@@ -798,6 +865,93 @@ struct RdmSink {
 
 // Solve a list of tuples (device).  Groups by shape class, batches within
 // the workspace, writes energies/status in input order.
+// ------------------------------------------------------------ autotuner --
+// Per shape class, once per process and device: the alpha-beta sigma form
+// (all pair rows, linked rows with the A rows gathered or resident, the
+// vector-ALU diagonal, W in HBM) and the string-Hamiltonian GEMM tile (64 or
+// 96) are chosen by timing one sigma of every candidate that fits on up to 16
+// tuples of the class (HIP events, the second of two launches), the fastest
+// whole sigma winning.  The choice is kept for the process, so that repeated
+// runs stay bitwise identical; processes whose measurements differ can differ
+// in the last bits (the forms sum in different orders).
+struct TuneChoice {
+    int linked_rows;   // the linked_rows setting that selects the form
+    int gemm_tile;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, TuneChoice> g_tune;   // (device, n_A, n_a, n_b)
+
+mbefci_status autotune_class(mbefci_ctx *ctx, const ClassKey &key, int nC, const std::vector<const TupleShape *> &sample,
+                             void *ws, size_t wsb, TuneChoice &out) {
+    const auto gk = std::make_tuple(ctx->device, key.nA, key.na, key.nb);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(gk);
+        if (it != g_tune.end()) {
+            out = it->second;
+            return MBEFCI_OK;
+        }
+    }
+    const mbefci_options saved = ctx->opt;
+    const int saved_tile = ctx->gemm_tile;
+    hipStream_t s = ctx->stream;
+    float best = 1e30f;
+    TuneChoice bestc{saved.linked_rows, 0};
+    std::vector<int> seen;
+    mbefci_status rc = MBEFCI_OK;
+    for (int lm : {1, 0, 2, 3, 4, 5}) {
+        for (int tile : {64, 96}) {
+            ctx->opt = saved;
+            ctx->opt.linked_rows = lm;
+            ctx->gemm_tile = tile;
+            ClassPlan cp;
+            plan_class(ctx, key, nC, cp, true, false);
+            const int B = (int)std::min<size_t>(sample.size(), 16);
+            if (cp.fixed_bytes + cp.per_tuple * (size_t)B > wsb) continue;
+            Carver cv{(char *)ws, wsb};
+            Batch b;
+            if (!carve_batch(ctx, cp, B, cv, b, true)) continue;
+            const int kid = alpha_beta_kernel(b) * 1000 + tile;
+            if (std::find(seen.begin(), seen.end(), kid) != seen.end()) continue;
+            seen.push_back(kid);
+            if ((rc = upload_tables(ctx, cp, b)) != MBEFCI_OK) break;
+            std::vector<const TupleShape *> sh(sample.begin(), sample.begin() + B);
+            if ((rc = upload_shapes(ctx, b, sh)) != MBEFCI_OK) break;
+            hipError_t e = launch_gather(b, s);
+            if (e == hipSuccess) e = launch_build_hb(b, s);
+            if (e == hipSuccess) e = launch_hdiag(b, b.Hd, b.dim, 0, s);
+            VecRef cin{b.Hd, b.dim, nullptr, 0}, sout{b.S, (int64_t)b.max_space * b.dim, nullptr, 0};
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(ctx->ev[0], s);
+                if (e == hipSuccess) e = launch_sigma(b, cin, sout, 0.0, false, false, s, nullptr, nullptr, nullptr, nullptr);
+                if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], s);
+                if (e == hipSuccess) e = hipEventSynchronize(ctx->ev[3]);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[3]);
+            }
+            if (e != hipSuccess) {
+                rc = ctx->fail(MBEFCI_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                bestc = TuneChoice{lm, tile};
+            }
+        }
+        if (rc != MBEFCI_OK) break;
+    }
+    ctx->opt = saved;
+    ctx->gemm_tile = saved_tile;
+    if (rc != MBEFCI_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto ins = g_tune.emplace(gk, bestc);
+        out = ins.first->second;   // another thread may have tuned the class first
+    }
+    ctx->stats.tuned_classes += 1;
+    return MBEFCI_OK;
+}
+
 // The same sink seen through a list of input indices (second pass).
 struct SubsetSink : RdmSink {
     RdmSink *inner;
@@ -839,9 +993,30 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
             return ctx->fail(MBEFCI_ETOOLARGE, "RDMs need at most 12 active orbitals");
         bool hard = false;   // this class runs with the second-pass settings
         const std::vector<int64_t> &idx = g.second;
+        // the sigma form and GEMM tile of the class: automatic settings only
+        // (linked_rows 1, sigma_variant 0), classes of at least 10^4 determinants
+        TuneChoice tc{first_opt.linked_rows, 0};
+        bool tuned = false;
+        if (first_opt.autotune && first_opt.linked_rows == 1 && first_opt.sigma_variant == SIGMA_AUTO) {
+            const Tables &ta = ctx->table(g.first.first.nA, g.first.first.na),
+                         &tb = ctx->table(g.first.first.nA, g.first.first.nb);
+            if (ta.nstr * tb.nstr >= 10000) {
+                std::vector<const TupleShape *> sample;
+                for (size_t j = 0; j < idx.size() && j < 16; ++j) sample.push_back(&shapes[idx[j]]);
+                if ((rc = autotune_class(ctx, g.first.first, g.first.second, sample, ws, wsb, tc)) != MBEFCI_OK) {
+                    ctx->opt = first_opt;
+                    return rc;
+                }
+                tuned = true;
+            }
+        }
         for (size_t start = 0; start < idx.size();) {
             ctx->opt = first_opt;
             if (hard) second_pass_options(ctx->opt);
+            if (tuned) {
+                ctx->opt.linked_rows = tc.linked_rows;
+                ctx->gemm_tile = tc.gemm_tile;
+            }
             ClassPlan cp;
             plan_class(ctx, g.first.first, g.first.second, cp, true, sink != nullptr);
             if (cp.fixed_bytes + cp.per_tuple > wsb) {
@@ -891,6 +1066,7 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
             start += B;
         }
         ctx->opt = first_opt;
+        ctx->gemm_tile = 0;
         if (rc != MBEFCI_OK) return rc;
     }
     ctx->stats.ntuples += ntup;
@@ -1340,6 +1516,8 @@ void mbefci_default_options(mbefci_options *o) {
     o->batched = 1;
     o->gradient = 0;
     o->profile = 0;
+    o->graph = 1;
+    o->autotune = 1;
 }
 
 mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
@@ -1358,6 +1536,7 @@ mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
             if (hipEventCreate(&e) != hipSuccess) return MBEFCI_EDEVICE;
         if (init_kernels() != hipSuccess) return MBEFCI_EDEVICE;
         if (scratch_address(&ctx->scratch) != hipSuccess || !ctx->scratch) return MBEFCI_EDEVICE;
+        if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) return MBEFCI_EDEVICE;
     }
     *out = ctx.release();
     return MBEFCI_OK;
@@ -1371,6 +1550,7 @@ void mbefci_destroy(mbefci_ctx *ctx) {
         if (ctx->d_eri) (void)hipFree(ctx->d_eri);
         for (auto e : ctx->ev)
             if (e) (void)hipEventDestroy(e);
+        if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     }
     delete ctx;
 }

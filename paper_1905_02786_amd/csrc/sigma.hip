@@ -343,6 +343,7 @@ __global__ __launch_bounds__(256) void k_gemm_hx(Batch b, VecRef cref, VecRef sr
 // 96 for matrices of at least 256 x 256 strings, else 64 (measured with the
 // Davidson dots: 96 faster for 462 and 330 strings, 64 for 252, 210 and 165).
 static int gemm_tile(const Batch &b) {
+    if (b.gemm_tile == 64 || b.gemm_tile == 96) return b.gemm_tile;   // chosen by the autotuner
     auto padded = [&](int64_t t) { return ((b.Na + t - 1) / t * t) * ((b.Nb + t - 1) / t * t); };
     const int64_t p96 = padded(96), p64 = padded(64);
     if (p96 != p64) return p96 < p64 ? 96 : 64;

@@ -413,3 +413,39 @@ def test_pi_pruned_mbe_matches_oracle(ws, a):
     _check_against_golden(res, g["a%g" % a])
     print(f"a = {a}: counts {[len(o.tuples) for o in res.orders]}")
     assert abs(res.total - g["fci"]) <= 1e-9
+
+
+def test_iteration_blocks_and_graphs_give_the_same_energies(ws):
+    """Davidson iterations launched one per host round trip (profile = 1), in
+    blocks (graph = 0) and as a replayed hipGraph (graph = 1): the same
+    arithmetic, so bitwise the same energies, on tuples that take the
+    explicit Gram-Schmidt passes too (Hubbard U/t = 8, P space 7)."""
+    P = synth.config_hubbard(8.0)
+    tuples = _tuples_with_dims(P, 4, 10 ** 9)
+    out = []
+    for opts in (dict(profile=1), dict(profile=0, graph=0), dict(profile=0, graph=1)):
+        ctx = _ctx(P, pspace=7, **opts)
+        e, st = ctx.solve_tuples(4, tuples, ws)
+        assert (st == 0).all()
+        out.append(e)
+        if opts.get("graph") == 1:
+            assert ctx.stats()["graph_batches"] > 0
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    ref = np.array([fci.casci_energy(P, S) for S in tuples[:6]])
+    assert np.abs(out[2][:6] - ref).max() <= 1e-10
+
+
+def test_autotuned_forms_match_oracle(ws):
+    """The autotuner's choice of sigma form and GEMM tile (order-4 tuples of
+    the order sweep, 14400-63504 determinants) gives the energies of the fixed
+    default forms within 1e-10 and of the oracle's stored samples."""
+    P = synth.config_sweep(0)
+    import itertools
+    tuples = list(itertools.combinations(P.expansion_space(), 4))[::97]
+    ctx = _ctx(P, autotune=1)
+    e1, s1 = ctx.solve_tuples(4, tuples, ws)
+    e0, s0 = _ctx(P, autotune=0).solve_tuples(4, tuples, ws)
+    assert (s1 == 0).all() and (s0 == 0).all()
+    assert np.abs(e1 - e0).max() <= 1e-10
+    e2, _ = ctx.solve_tuples(4, tuples, ws)       # the choice is kept: bitwise repeat
+    assert np.array_equal(e1, e2)
