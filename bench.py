@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--no-per-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="large workload without the gradient")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="large workload: energies of stratified order-4 slices of all C(52, 4) tuples (the list "
+                         "screening leaves at a = 5.0), no lower orders, increments or gradient -- for profiler "
+                         "runs of the order-4 kernels, not a headline figure")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a plain device-to-device copy run 3 times first (HBM counter calibration)")
     return ap.parse_args()
@@ -158,9 +162,40 @@ def oracle_threads():
 
 # ------------------------------------------------------------- large --------
 
+def bench_order4_kernels(args, M, torch, out):
+    """Profiler mode: the order-4 kernels on stratified slices of the order-4
+    list, each step's progress printed (no set-up phase without output)."""
+    import itertools
+    import numpy as np
+    import synth
+    P = synth.config_large(0)
+    ws = M.workspace(int(args.ws_gib * (1 << 30)))
+    allt = np.array(list(itertools.combinations(P.expansion_space(), 4)), dtype=np.int16)
+    ctx = M.Context.from_problem(P, device=0, profile=1, batched=1)
+    B, acc, times = args.slices, {}, []
+    for s in range(args.warmup + args.steps):
+        tl = allt[s::B]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e, st = ctx.solve_tuples(4, tl, ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        log(f"slice {s}: {len(tl)} tuples in {dt:.2f} s")
+        if s >= args.warmup:
+            times.append(dt)
+            merge_classes(acc, ctx.class_stats())
+    out.update({"value": sum(len(allt[s::B]) for s in range(args.warmup, args.warmup + args.steps)) / sum(times),
+                "ms_per_step": 1e3 * sum(times) / len(times), "kernels_only": True,
+                "config": {"workload": "order-4 energies only (profiler mode)"},
+                "classes": class_table(acc), "roofline": roofline(acc, "large")})
+    return out
+
+
 def bench_large(args, M, torch, out):
     import numpy as np
     import synth
+    if args.kernels_only:
+        return bench_order4_kernels(args, M, torch, out)
     P = synth.config_large(0)
     ws = M.workspace(int(args.ws_gib * (1 << 30)))
     grad = 0 if args.no_grad else 1
