@@ -41,8 +41,10 @@ KERNEL_NAMES = {0: "k_sigma_strip", 1: "k_sigma_linked_gat", 2: "k_sigma_linked_
 # WRITE_SIZE passes of profiles/, valid only while the kernel sources hash to
 # the value they were taken on.
 TRAFFIC = {
-    "large": {"kernel": 3, "sources_sha1": None, "bytes_per_launch": None},
-    "sweep": {"kernel": 2, "sources_sha1": None, "bytes_per_launch": None},
+    # kernel id -> (sources sha1, calibrated bytes per dispatch), from
+    # profiles/hbm-traffic-large-n60-order4.md
+    "large": {5: ("6ca2228f92fbaf6b2da3054c4b3b69bc0c137e34", 2570092339.2),
+              3: ("6ca2228f92fbaf6b2da3054c4b3b69bc0c137e34", 831363072.0)},
 }
 
 
@@ -123,23 +125,35 @@ def roofline(acc, workload):
     steps: its FLOPs (rows formed) over that time."""
     by_k = {}
     for c in acc.values():
-        b = by_k.setdefault(c["kernel"], {"ms": 0.0, "flops": 0.0, "launches": 0})
+        b = by_k.setdefault(c["kernel"], {"ms": 0.0, "flops": 0.0, "launches": 0, "bytes": 0.0})
         b["ms"] += c["sigma_ms"]
         b["flops"] += c["sigma_flops"]
         b["launches"] += c["sigma_launches"]
+        b["bytes"] += c["sigma_calls"] * algorithmic_bytes(c)
     kid = max(by_k, key=lambda k: by_k[k]["ms"])
     b = by_k[kid]
     achieved = b["flops"] / (b["ms"] / 1e3) / 1e12 if b["ms"] > 0 else 0.0
-    tr = TRAFFIC.get(workload, {})
-    traffic = tr.get("bytes_per_launch") if (tr.get("kernel") == kid and tr.get("sources_sha1") == sources_sha1()) \
-        else None
+    tr = TRAFFIC.get(workload, {}).get(kid)
+    traffic = tr[1] if (tr and tr[0] == sources_sha1()) else None
     return {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": traffic, "kernel": KERNEL_NAMES[kid],
             "launches": b["launches"], "avg_launch_ms": b["ms"] / max(1, b["launches"]),
             "per_launch_flops": b["flops"] / max(1, b["launches"]),
+            "algorithmic_bytes_per_launch": b["bytes"] / max(1, b["launches"]),
             "time_share_of_alpha_beta": b["ms"] / max(1e-9, sum(x["ms"] for x in by_k.values())),
             "flops_counted": "2 x rows formed x P_A x dim per sigma application (rows: 1 + n_a (n_A - n_a) for the "
                              "linked-row kernels, P_A for the all-pairs kernel)"}
+
+
+def algorithmic_bytes(c):
+    """HBM bytes one sigma application of the class's alpha-beta kernel must
+    move: read c and write sigma (16 dim) plus the pair matrix (8 P_A^2); for
+    the W-in-HBM form read c and write its 1 + n_a (n_A - n_a) W rows."""
+    nA, na = c["n_active"], c["n_alpha"]
+    P = nA * (nA + 1) // 2
+    if c["kernel"] == 5:
+        return 8.0 * c["dim"] * (2 + na * (nA - na))
+    return 16.0 * c["dim"] + 8.0 * P * P
 
 
 def host_info():
