@@ -45,6 +45,8 @@ TRAFFIC = {
     # profiles/hbm-traffic-large-n60-order4.md
     "large": {5: ("6ca2228f92fbaf6b2da3054c4b3b69bc0c137e34", 2570092339.2),
               3: ("6ca2228f92fbaf6b2da3054c4b3b69bc0c137e34", 831363072.0)},
+    # profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md
+    "sweep": {2: ("6ca2228f92fbaf6b2da3054c4b3b69bc0c137e34", 1060520103.3)},
 }
 
 
