@@ -148,7 +148,12 @@ typedef struct {
                                timing one sigma of each candidate on up to 16 of its tuples, once
                                per process and device (the choice is kept, so repeated runs are
                                bitwise identical; processes can differ in the last bits) */
-    int32_t reserved[1];
+    int32_t restart_keep;   /* vectors a Davidson restart keeps: 1 the Ritz vector alone; 2
+                               (default) also the previous iteration's Ritz vector made
+                               orthogonal to it (where that direction is not negligible), as in
+                               the locally optimal restarts of Murray, Racine and Davidson and of
+                               Stathopoulos, Saad and Wu.  Same eigenvalue within the tolerances;
+                               fewer iterations where restarts are frequent. */
 } mbefci_options;
 
 typedef struct {

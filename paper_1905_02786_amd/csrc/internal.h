@@ -115,9 +115,17 @@ struct Batch {
     // entries j >= i used), so Q = V R
     double *R;              // [B][kMaxSpace*kMaxSpace]
     double *y, *coef;       // [B][kMaxSpace]; y: Ritz coefficients on the stored basis V
+    // restarts that keep the previous Ritz vector (restart_keep 2): zp the
+    // previous iteration's Ritz vector in the coordinates of Q (zero past its
+    // length), y2 the coefficients on V of the kept direction, mu its Rayleigh
+    // quotient
+    int restart_keep;
+    double *y2, *zp;        // [B][kMaxSpace]
+    double *mu;             // [B]
     double *sdot;           // [B][kMaxSpace] S_i . V_m, i < m, of the basis vector V_m being added
     double *theta, *theta_prev, *rnorm, *tnorm0, *out_e;   // [B]; tnorm0 = |T| before projection
-    int32_t *status, *m, *iter, *restart, *out_status; // [B]
+    int32_t *status, *m, *iter, *out_status; // [B]
+    int32_t *restart;       // [B] 0, or the vectors this iteration's restart keeps (1 or 2)
     int32_t *cgs2;          // [B] correction takes two explicit Gram-Schmidt passes
     // P-space preconditioner: the psp determinants of lowest diagonal energy
     // (0: diagonal preconditioner only); H_PP = Q T Q^T with T tridiagonal

@@ -562,8 +562,9 @@ __global__ __launch_bounds__(kPsp) void k_psp_guess(Batch b) {
 // After k_ritz: T on the P determinants <- (theta - H_PP)^-1 r_P, solved as
 // Q (theta - T)^-1 Q^T r_P (Thomas, pivots kept away from zero like the
 // diagonal preconditioner); the changes of |T|^2, of the projections V_i . T
-// (x . T on restart) and of the dots S_i . T (Ax . T) go to the extra partial
-// block.  T is the vector k_ritz wrote, V_m (V_1 on restart).
+// (on restart the kept vectors' x . T and x2 . T) and of the dots S_i . T
+// (Ax . T, A x2 . T) go to the extra partial block.  T is the vector k_ritz
+// wrote, V_m (V_restart on restart).
 template <int MS>
 __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     const int t = blockIdx.x, i = threadIdx.x, n = b.psp;
@@ -573,19 +574,23 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
     const double *yy = b.y + (int64_t)t * kMaxSpace;
     const double *V = b.V + (int64_t)t * b.max_space * b.dim;
     const double *S = b.S + (int64_t)t * b.max_space * b.dim;
-    double *T = b.V + ((int64_t)t * b.max_space + (rs ? 1 : m)) * b.dim;
+    double *T = b.V + ((int64_t)t * b.max_space + (rs ? rs : m)) * b.dim;
     const double *Q = b.pQ + (int64_t)t * kPsp * kPsp, *Qt = b.pQt + (int64_t)t * kPsp * kPsp;
     const double *dT = b.pT + (int64_t)t * 3 * kPsp, *eT = dT + kPsp;
     constexpr bool SD = MS <= kSdMax;
     constexpr int NACC = SD ? kSdOff + MS : 2 + MS;
     __shared__ double r[kPsp], w[kPsp], cp[kPsp], red[2][NACC];
     int64_t d = 0;
-    double x = 0.0, ax = 0.0, told = 0.0;
+    double x = 0.0, ax = 0.0, x2 = 0.0, a2 = 0.0, told = 0.0;
     if (i < n) {
         d = b.pidx[(int64_t)t * kPsp + i];
         if (rs) {
             x = V[d];
             ax = S[d];
+            if (rs == 2) {
+                x2 = V[b.dim + d];
+                a2 = S[b.dim + d];
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < MS; ++k)
@@ -631,6 +636,10 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
         if (rs) {
             acc[2] = x * dt;
             if (SD) acc[kSdOff] = ax * dt;
+            if (rs == 2) {
+                acc[3] = x2 * dt;
+                if (SD) acc[kSdOff + 1] = a2 * dt;
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < MS; ++k)
@@ -640,7 +649,7 @@ __global__ __launch_bounds__(kPsp) void k_psp_fix(Batch b) {
                 }
         }
     }
-    const int nx = (SD ? kSdOff : 2) + (rs ? 1 : m);
+    const int nx = (SD ? kSdOff : 2) + (rs ? rs : m);
 #pragma unroll
     for (int k = 0; k < NACC; ++k) {
         if (k < nx) {
@@ -755,6 +764,8 @@ __global__ void k_init_state(Batch b) {
     b.theta[t] = 0.0;
     b.theta_prev[t] = 1e300;
     b.R[(int64_t)t * kMaxSpace * kMaxSpace] = 1.0;   // V_0 is normalised: Q_0 = V_0
+    double *zp = b.zp + (int64_t)t * kMaxSpace;
+    for (int i = 0; i < kMaxSpace; ++i) zp[i] = i == 0 ? 1.0 : 0.0;
     if (t == 0) b.counter[2] = 0;   // explicit Gram-Schmidt passes of the batch
 }
 
@@ -839,6 +850,7 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
     __shared__ double cs[(kMaxSpace + 2) / 2], sn[(kMaxSpace + 2) / 2];
     __shared__ int pa[(kMaxSpace + 2) / 2], pb[(kMaxSpace + 2) / 2];
     __shared__ int done;
+    __shared__ double wv[kMaxSpace];
     const int tid = threadIdx.x;
     const double *G = b.G + (int64_t)t * kMaxSpace * kMaxSpace;
     const double *Rg = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
@@ -950,31 +962,65 @@ __global__ __launch_bounds__(64) void k_small_eig(Batch b) {
             for (int j = i; j < m; ++j) v += Rs[i][j] * Vv[j][k];
             y[i] = v;
         }
-        b.restart[t] = (m >= b.max_space || st0 == ST_RESTART) ? 1 : 0;
+        // A restart keeps the Ritz vector and, with restart_keep 2, the
+        // previous iteration's Ritz vector (zp, coordinates of Q, zero past
+        // its length) made orthogonal to it by two passes in these
+        // coordinates; kept when that leaves a norm above 1e-6.  Its
+        // Rayleigh quotient comes from the eigen-decomposition of the
+        // projected matrix (A's diagonal, eigenvectors Vv), its coefficients
+        // on the stored basis are R w.  The two are orthonormal and the
+        // projected matrix on them is diag(theta, mu).
+        const bool rs = m >= b.max_space || st0 == ST_RESTART;
+        double *zp = b.zp + (int64_t)t * kMaxSpace;
+        int keep = rs ? 1 : 0;
+        if (rs && b.restart_keep > 1) {
+            for (int i = 0; i < m; ++i) wv[i] = zp[i];
+            for (int pass = 0; pass < 2; ++pass) {
+                double d = 0.0;
+                for (int i = 0; i < m; ++i) d += Vv[i][k] * wv[i];
+                for (int i = 0; i < m; ++i) wv[i] -= d * Vv[i][k];
+            }
+            double nw = 0.0;
+            for (int i = 0; i < m; ++i) nw += wv[i] * wv[i];
+            if (nw > 1e-12) {
+                const double sc = 1.0 / sqrt(nw);
+                for (int i = 0; i < m; ++i) wv[i] *= sc;
+                double mu = 0.0;
+                for (int j = 0; j < m; ++j) {
+                    double cj = 0.0;
+                    for (int i = 0; i < m; ++i) cj += Vv[i][j] * wv[i];
+                    mu += cj * cj * A[j][j];
+                }
+                b.mu[t] = mu;
+                double *y2 = b.y2 + (int64_t)t * kMaxSpace;
+                for (int i = 0; i < m; ++i) {
+                    double v = 0.0;
+                    for (int j = i; j < m; ++j) v += Rs[i][j] * wv[j];
+                    y2[i] = v;
+                }
+                keep = 2;
+            }
+        }
+        if (!rs)
+            for (int i = 0; i < kMaxSpace; ++i) zp[i] = i < m ? Vv[i][k] : 0.0;
+        b.restart[t] = keep;
     }
 }
 
-// x = V y, Ax = S y, r = Ax - theta x, T = r / (theta - Hd) (clamped);
-// partials |r|^2, |T|^2 and the projections V_i . T on the subspace the
-// correction is added to (V_i, i < m, or x alone on restart), and for
-// MS <= kSdMax the dots S_i . T (Ax . T on restart) from partial kSdOff.  T is stored as
-// the next basis vector itself: V_m, or V_1 on restart, where V_0 <- x and
-// S_0 <- Ax in place (each thread owns its d and reads every vector there
-// before it writes).
-template <int MS, bool V2>
-__global__ __launch_bounds__(256) void k_ritz(Batch b) {
-    const int t = blockIdx.y;
-    if (b.status[t] != ST_RUNNING) return;
-    const int m = b.m[t], rs = b.restart[t];
+template <int MS, bool V2, bool K2>
+__device__ __forceinline__ void ritz_body(const Batch &b, int t, int m, int rs) {
     const double th = b.theta[t];
-    const double *yv = b.y + (int64_t)t * kMaxSpace;
-    double yy[MS];
+    const double *yv = b.y + (int64_t)t * kMaxSpace, *zv = b.y2 + (int64_t)t * kMaxSpace;
+    double yy[MS], zz[MS];
 #pragma unroll
-    for (int i = 0; i < MS; ++i) yy[i] = (i < m) ? yv[i] : 0.0;
+    for (int i = 0; i < MS; ++i) {
+        yy[i] = (i < m) ? yv[i] : 0.0;
+        zz[i] = (K2 && i < m) ? zv[i] : 0.0;
+    }
     double *V = b.V + (int64_t)t * b.max_space * b.dim;
     double *S = b.S + (int64_t)t * b.max_space * b.dim;
     const double *hd = b.Hd + (int64_t)t * b.dim;
-    double *T = V + (int64_t)(rs ? 1 : m) * b.dim;
+    double *T = V + (int64_t)(rs ? rs : m) * b.dim;
     constexpr bool SD = MS <= kSdMax;
     constexpr int NACC = SD ? kSdOff + MS : 2 + MS;
     double acc[NACC];
@@ -982,7 +1028,8 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
     for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
     // one determinant: Ritz vector, residual, preconditioned correction, its
     // projections on the basis and its dots with the basis' sigma vectors
-    auto one = [&](const double (&vd)[MS], const double (&sd)[MS], double x, double ax, double h) -> double {
+    auto one = [&](const double (&vd)[MS], const double (&sd)[MS], double x, double ax, double x2, double a2,
+                   double h) -> double {
         const double r = ax - th * x;
         acc[0] += r * r;
         double den = th - h;
@@ -992,6 +1039,10 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
         if (rs) {
             acc[2] += x * tv;
             if (SD) acc[kSdOff] += ax * tv;
+            if (K2) {
+                acc[3] += x2 * tv;
+                if (SD) acc[kSdOff + 1] += a2 * tv;
+            }
         } else {
             // (vd[i] = sd[i] = 0 for i >= m: those sums stay unused)
 #pragma unroll
@@ -1018,7 +1069,7 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
             const int64_t d = d2 << 1;
             const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
             double v0[MS], v1[MS], s0[MS], s1[MS];
-            double x0 = 0.0, x1 = 0.0, a0 = 0.0, a1 = 0.0;
+            double x0 = 0.0, x1 = 0.0, a0 = 0.0, a1 = 0.0, z0 = 0.0, z1 = 0.0, c0 = 0.0, c1 = 0.0;
             dbl2 vv[MS], ss[MS];
 #pragma unroll
             for (int i = 0; i < MS; ++i) {
@@ -1035,20 +1086,30 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
                 x1 += yy[i] * vv[i].y;
                 a0 += yy[i] * ss[i].x;
                 a1 += yy[i] * ss[i].y;
+                if (K2) {
+                    z0 += zz[i] * vv[i].x;
+                    z1 += zz[i] * vv[i].y;
+                    c0 += zz[i] * ss[i].x;
+                    c1 += zz[i] * ss[i].y;
+                }
             }
             const dbl2 h = *reinterpret_cast<const dbl2 *>(hd + d);
-            const double t0 = one(v0, s0, x0, a0, h.x);
-            const double t1 = one(v1, s1, x1, a1, h.y);
+            const double t0 = one(v0, s0, x0, a0, z0, c0, h.x);
+            const double t1 = one(v1, s1, x1, a1, z1, c1, h.y);
             *reinterpret_cast<dbl2 *>(T + d) = dbl2{t0, t1};
             if (rs) {
                 *reinterpret_cast<dbl2 *>(V + d) = dbl2{x0, x1};
                 *reinterpret_cast<dbl2 *>(S + d) = dbl2{a0, a1};
+                if (K2) {
+                    *reinterpret_cast<dbl2 *>(V + b.dim + d) = dbl2{z0, z1};
+                    *reinterpret_cast<dbl2 *>(S + b.dim + d) = dbl2{c0, c1};
+                }
             }
         }
     } else {
         for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
             const uint32_t vo = (uint32_t)d * (uint32_t)sizeof(double);
-            double x = 0.0, ax = 0.0, vd[MS], sd[MS];
+            double x = 0.0, ax = 0.0, x2 = 0.0, a2 = 0.0, vd[MS], sd[MS];
 #pragma unroll
             for (int i = 0; i < MS; ++i) {
                 vd[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rV, vo, (uint32_t)i * vstride, 0));
@@ -1058,15 +1119,40 @@ __global__ __launch_bounds__(256) void k_ritz(Batch b) {
             for (int i = 0; i < MS; ++i) {
                 x += yy[i] * vd[i];
                 ax += yy[i] * sd[i];
+                if (K2) {
+                    x2 += zz[i] * vd[i];
+                    a2 += zz[i] * sd[i];
+                }
             }
-            T[d] = one(vd, sd, x, ax, hd[d]);
+            T[d] = one(vd, sd, x, ax, x2, a2, hd[d]);
             if (rs) {
                 V[d] = x;
                 S[d] = ax;
+                if (K2) {
+                    V[b.dim + d] = x2;
+                    S[b.dim + d] = a2;
+                }
             }
         }
     }
-    store_block_partials<NACC>(b, t, acc, (SD ? kSdOff : 2) + (rs ? 1 : m));
+    store_block_partials<NACC>(b, t, acc, (SD ? kSdOff : 2) + (rs ? rs : m));
+}
+
+// x = V y, Ax = S y, r = Ax - theta x, T = r / (theta - Hd) (clamped);
+// partials |r|^2, |T|^2 and the projections V_i . T on the subspace the
+// correction is added to (V_i, i < m, or on restart the kept vectors: x, and
+// x2 = V y2 when restart = 2), and for MS <= kSdMax the dots S_i . T (Ax . T,
+// A x2 . T on restart) from partial kSdOff.  T is stored as the next basis
+// vector itself: V_m, or V_restart on restart, where V_0 <- x, S_0 <- Ax (and
+// V_1 <- x2, S_1 <- A x2) in place (each thread owns its d and reads every
+// vector there before it writes).
+template <int MS, bool V2>
+__global__ __launch_bounds__(256) void k_ritz(Batch b) {
+    const int t = blockIdx.y;
+    if (b.status[t] != ST_RUNNING) return;
+    const int m = b.m[t], rs = b.restart[t];
+    if (rs == 2) ritz_body<MS, V2, true>(b, t, m, rs);
+    else ritz_body<MS, V2, false>(b, t, m, rs);
 }
 
 // convergence test, restart bookkeeping, running count
@@ -1084,11 +1170,22 @@ __global__ void k_converge(Batch b) {
     b.iter[t] = it;
     if (st == ST_RUNNING && it >= b.max_iter) st = ST_MAXITER;
     b.theta_prev[t] = th;
-    if (b.restart[t]) {   // V_0 = x, S_0 = A x already: the subspace is {x} whatever the outcome
-        b.m[t] = 1;
-        b.G[(int64_t)t * kMaxSpace * kMaxSpace] = th;
-        b.R[(int64_t)t * kMaxSpace * kMaxSpace] = 1.0;   // x = Q y has unit norm
-        b.y[(int64_t)t * kMaxSpace] = 1.0;
+    const int keep = b.restart[t];
+    if (keep) {   // V_0 = x, S_0 = A x (and V_1, S_1 the kept direction) already written
+        b.m[t] = keep;
+        double *G = b.G + (int64_t)t * kMaxSpace * kMaxSpace, *R = b.R + (int64_t)t * kMaxSpace * kMaxSpace;
+        double *y = b.y + (int64_t)t * kMaxSpace, *zp = b.zp + (int64_t)t * kMaxSpace;
+        G[0] = th;
+        R[0] = 1.0;   // x = Q y has unit norm
+        y[0] = 1.0;
+        if (keep == 2) {
+            G[1] = G[kMaxSpace] = 0.0;
+            G[kMaxSpace + 1] = b.mu[t];
+            R[1] = 0.0;
+            R[kMaxSpace + 1] = 1.0;
+            y[1] = 0.0;
+        }
+        for (int i = 0; i < kMaxSpace; ++i) zp[i] = i == 0 ? 1.0 : 0.0;   // x, in the new coordinates
     }
     b.status[t] = st;
     if (st == ST_RUNNING) atomicAdd(b.counter, 1);

@@ -455,7 +455,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.NP = rdm_np(key.nA);
     cp.nblk_r = nblk_rdm(cp.dim);
     if (rdm) pt += 8 * (size_t)(cp.nblk_r + 1) * cp.NP * cp.NP + 8 + 256;  // RDM Gram partials, sum, weight
-    pt += 8 * (size_t)(2 * kMaxSpace * kMaxSpace + 3 * kMaxSpace + 6) + 4 * 7;
+    pt += 8 * (size_t)(2 * kMaxSpace * kMaxSpace + 5 * kMaxSpace + 7) + 4 * 7;
     cp.per_tuple = pt + 256;
 }
 
@@ -528,6 +528,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.core = cv.take<int32_t>((size_t)B * b.nC + 1);
     b.params = cv.take<double>((size_t)B * cp.pl.stride);
     b.max_space = davidson ? ctx->opt.max_space : 0;
+    b.restart_keep = ctx->opt.max_space >= 3 ? ctx->opt.restart_keep : 1;
     b.max_iter = ctx->opt.max_iter;
     b.e_tol = ctx->opt.e_tol;
     b.r_tol = ctx->opt.r_tol;
@@ -563,6 +564,9 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.G = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.R = cv.take<double>((size_t)B * kMaxSpace * kMaxSpace);
     b.y = cv.take<double>((size_t)B * kMaxSpace);
+    b.y2 = cv.take<double>((size_t)B * kMaxSpace);
+    b.zp = cv.take<double>((size_t)B * kMaxSpace);
+    b.mu = cv.take<double>(B);
     b.coef = cv.take<double>((size_t)B * kMaxSpace);
     b.sdot = cv.take<double>((size_t)B * kMaxSpace);
     b.theta = cv.take<double>(B);
@@ -1518,6 +1522,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->profile = 0;
     o->graph = 1;
     o->autotune = 1;
+    o->restart_keep = 2;
 }
 
 mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
@@ -1689,6 +1694,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->sigma_variant < 0 || o->sigma_variant > 2) return ctx->fail(MBEFCI_EINVAL, "sigma_variant must be 0, 1 or 2");
     if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
     if (o->linked_rows < 0 || o->linked_rows > 5) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..5");
+    if (o->restart_keep < 1 || o->restart_keep > 2) return ctx->fail(MBEFCI_EINVAL, "restart_keep must be 1 or 2");
     ctx->opt = *o;
     return MBEFCI_OK;
 }
