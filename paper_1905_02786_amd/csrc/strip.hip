@@ -1162,45 +1162,38 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
 // a fixed order.  Slots per string: 0 the diagonal sum, then the off-diagonal
 // links in link order, up to 48 (three MFMA row tiles).
 //
-// W kernel: one workgroup of eight waves per (tuple, 16-column strip), in two
-// halves of four; the alpha strings are taken in groups of four (one per
-// wave), group q belonging to half q % 2.  In phase p (one barrier after
-// each) half p % 2 runs the MFMAs of group p (each wave all three row tiles
-// of its string, B operands from the string's D tile, A rows resident in
-// LDS, slot 0 from the staged diagonal-sum row), while the other half writes
-// the W rows of its group p - 1 from the MFMA registers to HBM, writes D and
-// the diagonal-sum rows of its group p + 1 (values loaded two phases
-// earlier) and loads those of group p + 3.
+// W kernel: one workgroup of four waves per (tuple, 16-column strip, part of
+// the strings), the A rows resident in LDS (staged once, the only barrier).
+// Each wave then takes every fourth string of the
+// part on its own: it loads the string's D straight into its MFMA B operands
+// (lane (ar, kr) of K step ks holds the signed c(K, J) of the beta link of
+// column B0 + ar and pair 4 ks + kr), stages the string's diagonal-sum row in
+// an LDS slot of its own, runs the three row tiles and stores the W rows;
+// the loads of its next string are issued before the MFMAs of this one.  Two
+// workgroups per CU: while one wave of a SIMD runs its MFMAs the other's
+// loads and stores proceed.  Every W element is written by one lane, so the
+// result does not depend on the order in which the waves run.
 template <int NA>
-__global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int skip_done, int aparts) {
+__global__ __launch_bounds__(256) void k_linked_wr(Batch b, VecRef cref, int skip_done, int aparts) {
     constexpr int P = NA * (NA + 1) / 2, KP = (P + 3) / 4 * 4, KS = KP / 4;
     constexpr int RL = (KS + 1) / 2 * 8;
     constexpr uint32_t RLB = RL * sizeof(double);
-    constexpr uint32_t DB = KP * kStrip * sizeof(double);     // one string's D
-    constexpr int NDI = (4 * KP * kStrip + 255) / 256;        // D items per thread of a half
     const int nstrips = (int)((b.Nb + kStrip - 1) / kStrip);
     int t, sp;
     if (!xcd_map(blockIdx.x, nstrips * aparts, b.B, t, sp)) return;
     if (skip_done && b.status[t] != ST_RUNNING) return;
-    // a workgroup owns a 16-column strip and one of `aparts` consecutive
-    // ranges of the string groups (small batches split the strings to fill
-    // the chip; the W rows do not depend on the split)
     const int strip_id = sp / aparts, part = sp % aparts;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int z = wu >> 2, g = wu & 3;     // half, string of the group
-    const int th = tid & 255;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ar = lane & 15, kr = lane >> 4;
     const uint32_t Na = (uint32_t)b.Na, Nb = (uint32_t)b.Nb, SW = (uint32_t)b.lw_slots;
     const uint32_t B0 = (uint32_t)strip_id * kStrip;
     const bool colok = B0 + ar < Nb;
-    const uint32_t ngr = (Na + 3) / 4, gpp = (ngr + aparts - 1) / aparts;
-    const uint32_t qb = (uint32_t)part * gpp, qe = qb + gpp < ngr ? qb + gpp : ngr;
-    if (qb >= ngr) return;   // an empty part (the whole workgroup)
-    const uint32_t S0 = 4 * qb, Nend = 4 * qe < Na ? 4 * qe : Na;   // strings [S0, Nend) of this part
+    const uint32_t per = (Na + (uint32_t)aparts - 1) / (uint32_t)aparts;
+    const uint32_t S0 = (uint32_t)part * per, S1 = S0 + per < Na ? S0 + per : Na;   // strings [S0, S1)
+    if (S0 >= S1) return;   // an empty part (the whole workgroup)
     extern __shared__ double lds[];
-    const uint32_t A0 = 8 * DB;                  // D [2 halves][4][KP][16] at 0, then A rows [P][RL]
-    const uint32_t G0 = A0 + P * RLB;            // diagonal-sum rows [2 halves][4][RL]
+    const uint32_t G0 = P * RLB;   // after the A rows [P][RL]: diagonal-sum rows [4 waves][2][RL]
     const double *c = vref(cref, t, b.dim);
     double *W = b.lw + (int64_t)t * b.lw_stride;
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(c), (short)0,
@@ -1210,79 +1203,67 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
     const uint32_t rowT = kLinkedRowsW * (uint32_t)sizeof(uint32_t);
     const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t *>(b.lrow_w), (short)0, (int)((Na + 1) * rowT), 0x00020000);
-    // D items of a half: element j = th + 256 i of its D [4][KP][16]
-    uint32_t boff[NDI], bsg[NDI];
+    // this lane's D elements: byte offset of c(., J) in a C row (out of range:
+    // an absent link, the load returns 0) and the link sign
+    uint32_t boff[KS], bsg[KS];
 #pragma unroll
-    for (int i = 0; i < NDI; ++i) {
-        const int j = th + 256 * i, q = (j >> 4) % KP;
-        const uint32_t eb = (colok && j < 4 * KP * kStrip && q < P) ? b.pairB[(B0 + ar) * (uint32_t)P + q] : 0u;
+    for (int ks = 0; ks < KS; ++ks) {
+        const int q = 4 * ks + kr;
+        const uint32_t eb = (colok && q < P) ? b.pairB[(B0 + ar) * (uint32_t)P + q] : 0u;
         const bool vb = (eb & kPairValid) != 0;
-        boff[i] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
-        bsg[i] = vb ? (eb & kPairSign) : 0u;
+        boff[ks] = vb ? (eb & kPairJ) * (uint32_t)sizeof(double) : 0x80000000u;
+        bsg[ks] = vb ? (eb & kPairSign) : 0u;
     }
-    auto item_on = [&](int i) { return 256 * (i + 1) <= 4 * KP * kStrip || 64 * g + 256 * i < 4 * KP * kStrip; };
-    auto item_str = [&](int i) { return (64 * g + 256 * i) / (KP * kStrip); };
     const uint32_t rowC = Nb * (uint32_t)sizeof(double);
     auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
-    // strings of the part, local index s (string S0 + s); past the part's end:
-    // any C row, the discard table row, no W written
-    auto crow = [&](uint32_t s) -> uint32_t { return S0 + s < Nend ? S0 + s : 0u; };
-    auto trow = [&](uint32_t s) -> uint32_t { return S0 + s < Nend ? S0 + s : Na; };
-    auto load_c = [&](uint32_t s, int i) -> double {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[i], crow(s) * rowC, 0));
+    auto load_d = [&](uint32_t K, int ks) -> double {
+        const double v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[ks], K * rowC, 0));
+        return __hiloint2double(__double2hiint(v) ^ (int)bsg[ks], __double2loint(v));
     };
-    auto load_row = [&](uint32_t s, int h) -> uint32_t {   // A-row offset of this lane's slot 16 h + ar
-        return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u, trow(s) * rowT, 0);
+    auto load_row = [&](uint32_t K, int h) -> uint32_t {   // A-row offset of this lane's slot 16 h + ar
+        return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u, K * rowT, 0);
     };
     const bool dgl = lane < RL / 2;
-    auto load_dg = [&](uint32_t s) -> dbl2v {
-        const uint32_t r = (uint32_t)P + crow(s);
-        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, r * RLB, 0));
+    auto load_dg = [&](uint32_t K) -> dbl2v {
+        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, ((uint32_t)P + K) * RLB, 0));
     };
-    auto dval = [&](double v, int i) -> double {
-        return __hiloint2double(__double2hiint(v) ^ (int)bsg[i], __double2loint(v));
-    };
-    const uint32_t dw = (uint32_t)z * 4 * DB + (uint32_t)th * (uint32_t)sizeof(double);
-    const uint32_t dr = (uint32_t)(4 * z + g) * DB + (uint32_t)(kr * kStrip + ar) * (uint32_t)sizeof(double);
-    const uint32_t gd = G0 + (uint32_t)(4 * z + g) * RLB;
-    const uint32_t gw = gd + (uint32_t)lane * 16u;
 
-    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 512)
-        *reinterpret_cast<dbl2v *>(lds_at(A0 + 16u * i)) =
+    for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 256)
+        *reinterpret_cast<dbl2v *>(lds_at(16u * i)) =
             __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, 16u * i, 0, 0));
-    // prologue: half 0 stages group 0 and holds the loads of group 2; half 1
-    // holds the loads of group 1
-    uint32_t ra[3] = {0u, 0u, 0u}, rap[3];
-    double cb[NDI];
-    dbl2v dg = {0.0, 0.0};
-    if (z == 0) {
-#pragma unroll
-        for (int i = 0; i < NDI; ++i)
-            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(load_c((uint32_t)item_str(i), i), i);
-        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = load_dg((uint32_t)g);
-#pragma unroll
-        for (int h = 0; h < 3; ++h) ra[h] = load_row((uint32_t)g, h);
-    }
-    const uint32_t q0 = z == 0 ? 2u : 1u;
-#pragma unroll
-    for (int i = 0; i < NDI; ++i) cb[i] = item_on(i) ? load_c(4 * q0 + item_str(i), i) : 0.0;
-    if (dgl) dg = load_dg(4 * q0 + g);
-#pragma unroll
-    for (int h = 0; h < 3; ++h) rap[h] = load_row(4 * q0 + g, h);
-    dbl4 acc[3];
-#pragma unroll
-    for (int h = 0; h < 3; ++h) acc[h] = dbl4{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
 
-    // MFMAs of group q: this wave's string, all three row tiles
-    auto mphase = [&]() {
-        double bv[KS];
+    uint32_t s = S0 + (uint32_t)wv;
+    if (s >= S1) return;
+    double bv[KS];
+    dbl2v dg = {0.0, 0.0};
+    uint32_t ra[3];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bv[ks] = *lds_at(dr + ks * 4u * kStrip * (uint32_t)sizeof(double));
+    for (int ks = 0; ks < KS; ++ks) bv[ks] = load_d(s, ks);
+    if (dgl) dg = load_dg(s);
+#pragma unroll
+    for (int h = 0; h < 3; ++h) ra[h] = load_row(s, h);
+    const uint32_t gb0 = G0 + (uint32_t)(2 * wv) * RLB;
+    uint32_t gbuf = gb0;
+    for (; s < S1; s += 4) {
+        // the next string's loads (the last string loads itself again, unused)
+        const uint32_t sn = s + 4 < S1 ? s + 4 : s;
+        double bn[KS];
+        dbl2v dgn = {0.0, 0.0};
+        uint32_t rn[3];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bn[ks] = load_d(sn, ks);
+        if (dgl) dgn = load_dg(sn);
+#pragma unroll
+        for (int h = 0; h < 3; ++h) rn[h] = load_row(sn, h);
+        // this string's diagonal-sum row in the wave's own slot (LDS accesses
+        // of one wave complete in order: the reads below see it)
+        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gbuf + (uint32_t)lane * 16u)) = dg;
+        dbl4 acc[3];
 #pragma unroll
         for (int h = 0; h < 3; ++h) {
             double af[KS];
-            const uint32_t arow = ((h == 0 && ar == 0) ? gd : A0 + ra[h]) + (uint32_t)kr * 16u;
+            const uint32_t arow = ((h == 0 && ar == 0) ? gbuf : ra[h]) + (uint32_t)kr * 16u;
 #pragma unroll
             for (int j = 0; j < KS / 2; ++j) {
                 const dbl2v v = *reinterpret_cast<const dbl2v *>(lds_at(arow + 64u * j));
@@ -1295,13 +1276,8 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
             for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
             acc[h] = a;
         }
-    };
-    // phase p of the other half: W rows of its group p - 1; D and
-    // diagonal-sum rows of group p + 1; loads of group p + 3
-    auto nphase = [&](uint32_t p) {
-        const uint32_t sw = S0 + 4 * (p - 1) + g;   // wraps past Nend for p = 0
-        if (4 * (p - 1) + g < Nend - S0 && colok) {
-            double *wrow = W + ((int64_t)sw * SW) * Nb + B0 + ar;
+        if (colok) {
+            double *wrow = W + ((int64_t)s * SW) * Nb + B0 + ar;
 #pragma unroll
             for (int h = 0; h < 3; ++h)
 #pragma unroll
@@ -1311,33 +1287,11 @@ __global__ __launch_bounds__(512) void k_linked_wr(Batch b, VecRef cref, int ski
                 }
         }
 #pragma unroll
-        for (int i = 0; i < NDI; ++i)
-            if (item_on(i)) *lds_at(dw + 2048u * i) = dval(cb[i], i);
-        if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gw)) = dg;
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = bn[ks];
+        dg = dgn;
 #pragma unroll
-        for (int h = 0; h < 3; ++h) ra[h] = rap[h];
-#pragma unroll
-        for (int i = 0; i < NDI; ++i)
-            if (item_on(i)) cb[i] = load_c(4 * (p + 3) + item_str(i), i);
-        if (dgl) dg = load_dg(4 * (p + 3) + g);
-#pragma unroll
-        for (int h = 0; h < 3; ++h) rap[h] = load_row(4 * (p + 3) + g, h);
-    };
-    const uint32_t nph = (qe > qb ? qe - qb : 0) + 1;   // groups, and the last group's W in the phase after
-    if (z == 0) {
-        for (uint32_t p = 0; p < nph; p += 2) {
-            mphase();
-            __syncthreads();
-            nphase(p + 1);
-            __syncthreads();
-        }
-    } else {
-        for (uint32_t p = 0; p < nph; p += 2) {
-            nphase(p);
-            __syncthreads();
-            mphase();
-            __syncthreads();
-        }
+        for (int h = 0; h < 3; ++h) ra[h] = rn[h];
+        gbuf = gbuf == gb0 ? gb0 + RLB : gb0;
     }
 }
 
@@ -1402,8 +1356,7 @@ __global__ __launch_bounds__(256) void k_linked_gw(Batch b, VecRef cref, VecRef 
 }
 
 static size_t linked_lds_w(const ParamLayout &pl) {
-    const size_t rl = (size_t)linked_row_len(pl.Kpad);
-    return sizeof(double) * (8 * (size_t)pl.Kpad * kStrip + (size_t)(pl.P + 8) * rl);
+    return sizeof(double) * (size_t)(pl.P + 8) * (size_t)linked_row_len(pl.Kpad);
 }
 
 bool linked_w_fits(const ParamLayout &pl, int64_t Na, int nel) {
@@ -1415,13 +1368,12 @@ template <int NA>
 static hipError_t launch_linked_w_na(const Batch &b, VecRef c, VecRef sig, double shift, int skip, hipStream_t s,
                                      hipEvent_t ev_mid) {
     const int64_t nstrips = (b.Nb + kStrip - 1) / kStrip;
-    // at least two workgroups per CU: split the string groups of a strip
-    // over up to four workgroups when the batch alone does not give that
-    const int64_t ngr = (b.Na + 3) / 4;
+    // two workgroups run per CU: small batches split the strings of a strip
+    // over up to eight workgroups, until there are 2048 (four per slot)
     int aparts = 1;
-    while (aparts < 4 && (int64_t)b.B * nstrips * aparts < 512 && ngr >= 8 * (aparts + 1)) ++aparts;
+    while (aparts < 8 && (int64_t)b.B * nstrips * aparts < 2048 && b.Na >= 32 * (aparts + 1)) ++aparts;
     const dim3 grid((unsigned)(((b.B + kXcds - 1) / kXcds) * kXcds * nstrips * aparts));
-    hipLaunchKernelGGL(k_linked_wr<NA>, grid, dim3(512), linked_lds_w(b.pl), s, b, c, skip, aparts);
+    hipLaunchKernelGGL(k_linked_wr<NA>, grid, dim3(256), linked_lds_w(b.pl), s, b, c, skip, aparts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev_mid) (void)hipEventRecord(ev_mid, s);
