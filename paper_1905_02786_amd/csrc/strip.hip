@@ -1445,6 +1445,7 @@ hipError_t launch_strip(const Batch &b, VecRef c, VecRef sig, double shift, int 
             case 10: return launch_linked_w_na<10>(b, c, sig, shift, skip, s, ev_mid);
             case 11: return launch_linked_w_na<11>(b, c, sig, shift, skip, s, ev_mid);
             case 12: return launch_linked_w_na<12>(b, c, sig, shift, skip, s, ev_mid);
+            case 13: return launch_linked_w_na<13>(b, c, sig, shift, skip, s, ev_mid);
             default: return hipErrorInvalidValue;
         }
     }
@@ -1515,7 +1516,7 @@ hipError_t init_strip_kernels() {
                             (const void *)k_linked_wr<6>,  (const void *)k_linked_wr<7>,
                             (const void *)k_linked_wr<8>,  (const void *)k_linked_wr<9>,
                             (const void *)k_linked_wr<10>, (const void *)k_linked_wr<11>,
-                            (const void *)k_linked_wr<12>};
+                            (const void *)k_linked_wr<12>, (const void *)k_linked_wr<13>};
     for (const void *f : strips) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
