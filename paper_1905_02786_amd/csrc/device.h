@@ -6,6 +6,7 @@ namespace mbefci {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 #define ERI_AT(eri, n, p, q, r, s) (eri)[((((int64_t)(p) * (n) + (q)) * (n) + (r)) * (n) + (s))]
 

@@ -424,7 +424,9 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.linked_dv = dvf && (lm == 4 || !classic);
     // linked rows through W in HBM where neither LDS form fits (or always with
     // linked_rows 5)
-    const bool wf = lin_ok && cp.ta->w_slots > 0 && linked_w_fits(cp.pl, cp.ta->nstr, key.na);
+    // (the W kernel addresses a tuple's W rows through a 32-bit buffer offset)
+    const bool wf = lin_ok && cp.ta->w_slots > 0 && linked_w_fits(cp.pl, cp.ta->nstr, key.na) &&
+                    (double)cp.dim * cp.ta->w_slots * sizeof(double) < 2147483647.0;
     cp.linked_w = wf && (lm == 5 || (!classic && !cp.linked_dv));
     if (lm == 5 && cp.linked_w) cp.linked_dv = false;
     const bool cls = classic && !cp.linked_dv && !cp.linked_w;

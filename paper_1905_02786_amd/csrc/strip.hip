@@ -1216,17 +1216,39 @@ __global__ __launch_bounds__(256) void k_linked_wr(Batch b, VecRef cref, int ski
     }
     const uint32_t rowC = Nb * (uint32_t)sizeof(double);
     auto lds_at = [&](uint32_t byte) -> double * { return reinterpret_cast<double *>(reinterpret_cast<char *>(lds) + byte); };
+    // the C value of this lane's D element (unsigned), and with its sign
     auto load_d = [&](uint32_t K, int ks) -> double {
-        const double v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[ks], K * rowC, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rc, boff[ks], K * rowC, 0));
+    };
+    auto sign_d = [&](double v, int ks) -> double {
         return __hiloint2double(__double2hiint(v) ^ (int)bsg[ks], __double2loint(v));
     };
     auto load_row = [&](uint32_t K, int h) -> uint32_t {   // A-row offset of this lane's slot 16 h + ar
         return __builtin_amdgcn_raw_buffer_load_b32(rr, (uint32_t)(16 * h + ar) * 4u, K * rowT, 0);
     };
     const bool dgl = lane < RL / 2;
+    // lanes past the row read out of range (zero): no branch around the load
+    const uint32_t dgo = dgl ? (uint32_t)lane * 16u : 0x80000000u;
     auto load_dg = [&](uint32_t K) -> dbl2v {
-        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, (uint32_t)lane * 16u, ((uint32_t)P + K) * RLB, 0));
+        return __builtin_bit_cast(dbl2v, __builtin_amdgcn_raw_buffer_load_b128(rl, dgo, ((uint32_t)P + K) * RLB, 0));
     };
+    // W rows through a buffer resource: this lane's element of output row
+    // 16 h + kr + 4 v at a fixed offset (out of range, so the store is
+    // dropped, for slots past the string's and columns past N_b), the string
+    // as the scalar offset.  No branch around the stores: the compiler's wait
+    // counts then cover them, and the next string's loads need not wait for
+    // them.
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+        W, (short)0, (int)((int64_t)Na * SW * Nb * (int64_t)sizeof(double)), 0x00020000);
+    uint32_t wo[3][4];
+#pragma unroll
+    for (int h = 0; h < 3; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const uint32_t slot = 16 * h + kr + 4 * v;
+            wo[h][v] = (colok && slot < SW) ? (slot * Nb + B0 + ar) * (uint32_t)sizeof(double) : 0x80000000u;
+        }
+    const uint32_t rowW = SW * Nb * (uint32_t)sizeof(double);
 
     for (uint32_t i = tid; i < (uint32_t)P * RL / 2; i += 256)
         *reinterpret_cast<dbl2v *>(lds_at(16u * i)) =
@@ -1235,27 +1257,43 @@ __global__ __launch_bounds__(256) void k_linked_wr(Batch b, VecRef cref, int ski
 
     uint32_t s = S0 + (uint32_t)wv;
     if (s >= S1) return;
-    double bv[KS];
-    dbl2v dg = {0.0, 0.0};
-    uint32_t ra[3];
+    // Loads run one string ahead in two register sets used in turn (no
+    // copies between them), kept unsigned: the signs are applied when the
+    // string's MFMAs start, so the wait is for loads issued one string before.
+    // The prologue issues twelve stores that the bounds check drops, so that
+    // the compiler's wait counts on entering the loop match those of later
+    // iterations (a string's loads, then its stores).
+    double blA[KS], blB[KS];
+    dbl2v dgA, dgB;
+    uint32_t raA[3], raB[3];
+    auto issue = [&](uint32_t K, double (&bl)[KS], dbl2v &dgv, uint32_t (&rav)[3]) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) bv[ks] = load_d(s, ks);
-    if (dgl) dg = load_dg(s);
+        for (int ks = 0; ks < KS; ++ks) bl[ks] = load_d(K, ks);
+        dgv = load_dg(K);
 #pragma unroll
-    for (int h = 0; h < 3; ++h) ra[h] = load_row(s, h);
+        for (int h = 0; h < 3; ++h) rav[h] = load_row(K, h);
+    };
+    issue(s, blA, dgA, raA);
+#pragma unroll
+    for (int v = 0; v < 12; ++v)   // (distinct offsets, or the compiler would keep one)
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{0u, 0u}, rw, 0x80000000u + 8u * (uint32_t)v, 0, 0);
     const uint32_t gb0 = G0 + (uint32_t)(2 * wv) * RLB;
-    uint32_t gbuf = gb0;
-    for (; s < S1; s += 4) {
+    // string s from the set (bl, dgv, rav) while the next string's loads go
+    // to the other set
+    auto string = [&](uint32_t s, uint32_t gbuf, const double (&bl)[KS], const dbl2v &dgv, const uint32_t (&rav)[3],
+                      double (&bo)[KS], dbl2v &dgo_, uint32_t (&rao)[3]) {
+        s = __builtin_amdgcn_readfirstlane(s);   // wave-uniform: scalar offsets
+        double bv[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = sign_d(bl[ks], ks);
+        const dbl2v dg = dgv;
+        uint32_t ra[3];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) ra[h] = rav[h];
+        __builtin_amdgcn_sched_barrier(0);
         // the next string's loads (the last string loads itself again, unused)
-        const uint32_t sn = s + 4 < S1 ? s + 4 : s;
-        double bn[KS];
-        dbl2v dgn = {0.0, 0.0};
-        uint32_t rn[3];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bn[ks] = load_d(sn, ks);
-        if (dgl) dgn = load_dg(sn);
-#pragma unroll
-        for (int h = 0; h < 3; ++h) rn[h] = load_row(sn, h);
+        issue(s + 4 < S1 ? s + 4 : s, bo, dgo_, rao);
+        __builtin_amdgcn_sched_barrier(0);
         // this string's diagonal-sum row in the wave's own slot (LDS accesses
         // of one wave complete in order: the reads below see it)
         if (dgl) *reinterpret_cast<dbl2v *>(lds_at(gbuf + (uint32_t)lane * 16u)) = dg;
@@ -1276,22 +1314,23 @@ __global__ __launch_bounds__(256) void k_linked_wr(Batch b, VecRef cref, int ski
             for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
             acc[h] = a;
         }
-        if (colok) {
-            double *wrow = W + ((int64_t)s * SW) * Nb + B0 + ar;
 #pragma unroll
-            for (int h = 0; h < 3; ++h)
+        for (int h = 0; h < 3; ++h)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const uint32_t slot = 16 * h + kr + 4 * v;
-                    if (slot < SW) wrow[(int64_t)slot * Nb] = acc[h][v];
-                }
-        }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bv[ks] = bn[ks];
-        dg = dgn;
-#pragma unroll
-        for (int h = 0; h < 3; ++h) ra[h] = rn[h];
-        gbuf = gbuf == gb0 ? gb0 + RLB : gb0;
+            for (int v = 0; v < 4; ++v) {
+                // (the element copied out first: a bit cast of the vector
+                // element expression itself stored element 0 four times)
+                const double x = acc[h][v];
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), rw, wo[h][v], s * rowW, 0);
+            }
+    };
+    for (;;) {
+        string(s, gb0, blA, dgA, raA, blB, dgB, raB);
+        s += 4;
+        if (s >= S1) break;
+        string(s, gb0 + RLB, blB, dgB, raB, blA, dgA, raA);
+        s += 4;
+        if (s >= S1) break;
     }
 }
 
