@@ -484,3 +484,94 @@ def test_pi_pruning_screening_rule_on_handmade_table():
     o3 = mbe.candidates(P, 3, orders[2], dinc, orders)
     # from (1,2) + unpaired; pairs onto significant order-1 tuples (0,), (4,)
     assert o3 == [(0, 1, 2), (1, 2, 3), (1, 2, 4)]
+
+
+# --------------------------------------------------------------- total spin --
+def _fock_spin_ops(n):
+    """S_+, S_z and S^2 in the full Fock space from Jordan-Wigner mode
+    operators (mode p: p alpha, mode n + p: p beta)."""
+    from tests.fockspace import mode_annihilators
+    a = mode_annihilators(2 * n)
+    ad = [x.T.tocsr() for x in a]
+    Sp = sum(ad[p] @ a[n + p] for p in range(n))
+    Sz = 0.5 * sum(ad[p] @ a[p] - ad[n + p] @ a[n + p] for p in range(n))
+    S2 = Sp.T @ Sp + Sz @ Sz + Sz
+    return Sp.tocsr(), S2.tocsr()
+
+
+@pytest.mark.parametrize("na,nb,core", [(2, 2, ()), (3, 1, ()), (2, 1, (0,)), (3, 2, (0,))])
+def test_s2_matches_fock_space(na, nb, core):
+    """<S^2> and S_- S_+ c of the oracle's spin module equal the brute-force
+    Jordan-Wigner S^2 on random CAS vectors (closed and open shells, with a
+    doubly occupied core orbital)."""
+    from oracle import spin
+    n = 5
+    act = [p for p in range(n) if p not in core]
+    sp = _space(n, na, nb, core=core, active=act)
+    _, S2 = _fock_spin_ops(n)
+    idx = [det_index(a, b, n) for a in sp.alist for b in sp.blist]
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        c = rng.standard_normal(sp.dim)
+        full = np.zeros(2 ** (2 * n))
+        full[idx] = c
+        ref = float(full @ (S2 @ full)) / float(c @ c)
+        assert abs(spin.s2_expectation(sp, c) - ref) < 1e-11
+        m = spin.sz(sp)
+        y = spin.s_minus_s_plus(sp, c)
+        yref = (S2 @ full)[idx] - m * (m + 1.0) * c
+        np.testing.assert_allclose(y, yref, rtol=0, atol=1e-11)
+
+
+def test_spin_targeted_closed_form_and_multiplets():
+    """Two electrons in two orbitals: the lowest singlet is the lower of the
+    closed-shell pair energy 1/2(E11+E22) - sqrt(1/4(E22-E11)^2 + K^2) and the
+    open-shell singlet h11+h22+J+K, even when the triplet lies below both; the
+    triplet's energy is h11+h22+J-K, found as S = 1
+    in the M_s = 0 sector and as the only state of the M_s = 1 sector; every
+    eigenvector of H has <S^2> = S(S+1)."""
+    from oracle import spin
+    h11, h22, J11, J22, J12, K12 = -1.3, -1.25, 0.9, 0.85, 0.45, 0.18
+    h = np.diag([h11, h22])
+    eri = np.zeros((2, 2, 2, 2))
+    eri[0, 0, 0, 0], eri[1, 1, 1, 1] = J11, J22
+    eri[0, 0, 1, 1] = eri[1, 1, 0, 0] = J12
+    for p, q, r, s in [(0, 1, 0, 1), (1, 0, 1, 0), (0, 1, 1, 0), (1, 0, 0, 1)]:
+        eri[p, q, r, s] = K12
+    P = _prob(h, eri, 1, 1)
+    sp0 = _space(2, 1, 1)
+    E11, E22 = 2 * h11 + J11, 2 * h22 + J22
+    sing = min(0.5 * (E11 + E22) - math.sqrt(0.25 * (E22 - E11) ** 2 + K12 ** 2), h11 + h22 + J12 + K12)
+    trip = h11 + h22 + J12 - K12
+    assert trip < sing   # the case the targeting is for
+    assert abs(fci.lowest_eigenpair(P, sp0)[0] - trip) < 1e-13
+    assert abs(spin.lowest_with_spin(P, sp0)[0] - sing) < 1e-13
+    assert abs(spin.lowest_with_spin(P, sp0, S=1)[0] - trip) < 1e-13
+    P1 = _prob(h, eri, 2, 0)
+    assert abs(spin.lowest_with_spin(P1, _space(2, 2, 0))[0] - trip) < 1e-13
+    w, v = np.linalg.eigh(fci.hamiltonian_matrix(P, sp0))
+    for i in range(len(w)):
+        s2 = spin.s2_expectation(sp0, v[:, i])
+        assert min(abs(s2 - S * (S + 1)) for S in (0, 1)) < 1e-10
+
+
+def test_spin_multiplets_agree_across_sectors():
+    """The lowest triplet of a 6-orbital, 4-electron CAS found in the M_s = 0
+    sector (S = 1 targeted) equals the lowest state of the M_s = 1 sector
+    with S = 1 (the multiplet's components are degenerate); likewise S = 0 in
+    the M_s = 0 sector lies at or above the lowest M_s = 0 eigenvalue, and
+    every eigenvector's <S^2> is S(S+1) for an integer S."""
+    from oracle import spin
+    P0 = synth.small_problem(6, 2, 2, list(range(6)), nvec=6, seed=7, vec_std=0.3)
+    P1 = synth.Problem("t1", P0.h, P0.eri, 3, 1, 0, list(range(6)))
+    sp0, sp1 = fci.cas_space(P0, ()), fci.cas_space(P1, ())
+    t0 = spin.lowest_with_spin(P0, sp0, S=1)[0]
+    t1 = spin.lowest_with_spin(P1, sp1)[0]
+    assert abs(t0 - t1) < 1e-10
+    s0 = spin.lowest_with_spin(P0, sp0)[0]
+    assert s0 >= fci.lowest_eigenpair(P0, sp0)[0] - 1e-12
+    w, v = np.linalg.eigh(fci.hamiltonian_matrix(P0, sp0))
+    for i in range(len(w)):
+        s2 = spin.s2_expectation(sp0, v[:, i])
+        S = 0.5 * (math.sqrt(1.0 + 4.0 * s2) - 1.0)
+        assert abs(S - round(S)) < 1e-8
