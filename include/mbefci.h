@@ -154,6 +154,17 @@ typedef struct {
                                the locally optimal restarts of Murray, Racine and Davidson and of
                                Stathopoulos, Saad and Wu.  Same eigenvalue within the tolerances;
                                fewer iterations where restarts are frequent. */
+    double spin_shift;      /* lambda >= 0 (default 0: off).  Spin-targeted CASCI: every tuple takes
+                               the lowest eigenvalue of H + lambda S_- S_+ over its CAS instead of
+                               H's, i.e. of its lowest state of total spin S = (n_alpha - n_beta) / 2
+                               (the lowest singlet for closed shells).  S_- S_+ = N_beta -
+                               sum_pq E^alpha_qp E^beta_pq is zero on the states of that spin and at
+                               least lambda (S'(S'+1) - S(S+1)) on a state of spin S', so lambda must
+                               exceed the energy by which the lowest state of any higher spin lies
+                               below the target, divided by that factor; the energy returned is the
+                               state's own (the shift vanishes on it).  The paper's energies are those
+                               of singlet ground states (Sec. 4); the diagonal and the P space include
+                               the shift. */
 } mbefci_options;
 
 typedef struct {

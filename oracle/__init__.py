@@ -13,6 +13,8 @@ Full Configuration Interaction. II. Strongly Correlated Regime"):
 * ``mbe``  -- the increment recursion of Eq. 3 over orbital tuples that are
   supersets of the reference space [Pi] (Eq. 1-3), the screening rule and the
   order sums.
+* ``spin`` -- total spin <S^2> of CAS vectors from S_+ on full-space
+  determinants, and the lowest CASCI state of a given total spin.
 * ``rdm``  -- one- and two-particle density matrices by explicit operator
   action, the adjoint weights of the increment recursion and the gradient of
   the summed MBE energy with respect to h_pq and (pq|rs).

@@ -20,7 +20,8 @@ class Options(ctypes.Structure):
                 ("max_iter", c_int32), ("max_space", c_int32), ("batched", c_int32),
                 ("gradient", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
                 ("pspace", c_int32), ("linked_rows", c_int32), ("stream_last", c_int32),
-                ("graph", c_int32), ("autotune", c_int32), ("restart_keep", c_int32)]
+                ("graph", c_int32), ("autotune", c_int32), ("restart_keep", c_int32),
+                ("spin_shift", c_double)]
 
 
 class Stats(ctypes.Structure):

@@ -20,6 +20,8 @@ static_assert(kSdOff + kSdMax <= kParts, "S-dot partials past the partial block"
 constexpr int kPsp = 128;          // largest P space of the Davidson preconditioner
 constexpr int kTile = 64;          // determinants per sigma tile (materialised-W variant)
 constexpr int kStrip = 16;         // beta columns per workgroup (column-strip variant)
+// dense pair table entries (pairB): linked string J, link present, link sign
+constexpr uint32_t kPairJ = 0xFFFFFu, kPairValid = 1u << 30, kPairSign = 1u << 31;
 constexpr int kXcds = 8;           // accelerator complex dies, each with its own L2
 constexpr int kMaxKS = 24;         // K steps of 4 covering the padded pair count (<= 92)
 constexpr int kRdmMaxPairs = 16;   // upper 16x16 tile pairs of the RDM Gram per wave (n_A <= 12)
@@ -120,6 +122,7 @@ struct Batch {
     // length), y2 the coefficients on V of the kept direction, mu its Rayleigh
     // quotient
     int restart_keep;
+    double spin_shift;      // lambda of the level shift lambda S_- S_+ (0: none)
     double *y2, *zp;        // [B][kMaxSpace]
     double *mu;             // [B]
     double *sdot;           // [B][kMaxSpace] S_i . V_m, i < m, of the basis vector V_m being added

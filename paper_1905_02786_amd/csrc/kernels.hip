@@ -124,6 +124,9 @@ __global__ __launch_bounds__(256) void k_hdiag(Batch b, double *out, int64_t ost
                 e += 0.5 * (J[i * nA + j] - K[i * nA + j]);
             }
         }
+        // level shift toward the lowest spin of the sector: lambda times the
+        // diagonal of S_- S_+, n_b - (orbitals holding both spins)
+        if (b.spin_shift != 0.0) e += b.spin_shift * (double)(b.nb - __popc(ma & mb));
         out[(int64_t)t * ostride + d] = e + ec;
     }
 }
@@ -289,8 +292,22 @@ __device__ __forceinline__ int string_transition(uint32_t mi, uint32_t mj, int *
     return 1;
 }
 
+// Sign of the single excitation that turns string J into string I (one
+// orbital created in I, one annihilated from J): the parity of J's occupied
+// orbitals strictly between the two.
+__device__ __forceinline__ double excitation_sign(uint32_t mi, uint32_t mj) {
+    const uint32_t diff = mi ^ mj;
+    const int p = __ffs(mi & diff) - 1, q = __ffs(mj & diff) - 1;
+    const int lo = p < q ? p : q, hi = p < q ? q : p;
+    const uint32_t between = mj & (((1u << hi) - 1u) & ~((1u << (lo + 1)) - 1u));
+    return (__popc(between) & 1) ? -1.0 : 1.0;
+}
+
 // H_PP[i][j] = H_a[Ia][Ja] d(Ib,Jb) + H_b[Ib][Jb] d(Ia,Ja)
 //            + sum_PQ (P|Q) <Ia|E+_P|Ja> <Ib|E+_Q|Jb>  (upper triangle, mirrored)
+// plus, with a spin level shift, lambda <I|S_- S_+|J>: n_b - (orbitals
+// holding both spins) on the diagonal, -s_a s_b where an alpha electron
+// moves q <- p and a beta electron p <- q (I = E^a_qp E^b_pq J).
 __global__ __launch_bounds__(256) void k_psp_build(Batch b) {
     const int t = blockIdx.x, n = b.psp;
     const ParamLayout &pl = b.pl;
@@ -314,6 +331,16 @@ __global__ __launch_bounds__(256) void k_psp_build(Batch b) {
         for (int u = 0; u < na; ++u)
             for (int w2 = 0; w2 < nb; ++w2) x += ca[u] * cb2[w2] * prm[pl.off_eri + Pa[u] * pl.Kpad + Pb[w2]];
         v += 2.0 * x;   // stored as 1/2 (P|Q)
+        if (b.spin_shift != 0.0) {
+            const uint32_t mia = b.strA[ia], mja = b.strA[ja], mib = b.strB[ib], mjb = b.strB[jb];
+            if (I == J) {
+                v += b.spin_shift * (double)(b.nb - __popc(mia & mib));
+            } else {
+                const uint32_t da = mia ^ mja, db = mib ^ mjb;
+                if (__popc(da) == 2 && __popc(db) == 2 && (mia & da) == (mjb & db) && (mja & da) == (mib & db))
+                    v -= b.spin_shift * excitation_sign(mia, mja) * excitation_sign(mib, mjb);
+            }
+        }
         H[i * kPsp + j] = v;
         H[j * kPsp + i] = v;
     }

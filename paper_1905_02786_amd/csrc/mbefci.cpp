@@ -531,6 +531,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.params = cv.take<double>((size_t)B * cp.pl.stride);
     b.max_space = davidson ? ctx->opt.max_space : 0;
     b.restart_keep = ctx->opt.max_space >= 3 ? ctx->opt.restart_keep : 1;
+    b.spin_shift = ctx->opt.spin_shift;
     b.max_iter = ctx->opt.max_iter;
     b.e_tol = ctx->opt.e_tol;
     b.r_tol = ctx->opt.r_tol;
@@ -1525,6 +1526,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->graph = 1;
     o->autotune = 1;
     o->restart_keep = 2;
+    o->spin_shift = 0.0;
 }
 
 mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
@@ -1697,6 +1699,8 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->pspace < 0 || o->pspace > kPsp) return ctx->fail(MBEFCI_EINVAL, "pspace must be in 0..128");
     if (o->linked_rows < 0 || o->linked_rows > 5) return ctx->fail(MBEFCI_EINVAL, "linked_rows must be in 0..5");
     if (o->restart_keep < 1 || o->restart_keep > 2) return ctx->fail(MBEFCI_EINVAL, "restart_keep must be 1 or 2");
+    if (!(o->spin_shift >= 0.0) || !std::isfinite(o->spin_shift))
+        return ctx->fail(MBEFCI_EINVAL, "spin_shift must be finite and >= 0");
     ctx->opt = *o;
     return MBEFCI_OK;
 }

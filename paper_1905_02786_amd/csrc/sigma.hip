@@ -370,6 +370,49 @@ static hipError_t launch_gemm_h(const Batch &b, VecRef c, VecRef sig, int skip, 
 
 
 
+// Level shift toward the lowest state of total spin S = (n_a - n_b) / 2 of
+// the sector: sigma += lambda S_- S_+ c over the active orbitals, with
+// S_- S_+ = N_b - sum_pq E^a_qp E^b_pq (the doubly occupied core adds
+// nothing).  S_- S_+ vanishes on states of spin S and is positive on all
+// others.  Gather per determinant (I_a, I_b): the diagonal
+// (n_b - orbitals holding both spins) c(I), and for each alpha link
+// J_a = E_pq I_a (q in I_a, p not) with p in I_b and q not, the beta string
+// J_b = E_qp I_b from the dense pair table: - s_a s_b c(J_a, J_b).
+__global__ __launch_bounds__(256) void k_spin_sigma(Batch b, VecRef cref, VecRef sref, int skip_done) {
+    const int t = blockIdx.y;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    const int nA = b.nA, P = b.pl.P;
+    const double lam = b.spin_shift;
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
+        const int64_t Ia = d / b.Nb, Ib = d % b.Nb;
+        const uint32_t ma = b.strA[Ia], mb = b.strB[Ib];
+        double acc = (double)(b.nb - __popc(ma & mb)) * c[d];
+        const uint32_t *la = b.linkA + Ia * b.nentA;
+        for (int e = 0; e < b.nentA; ++e) {
+            const uint32_t L = la[e];
+            const int Q = (int)((L >> 20) & 0x3FFu);
+            int hi, lo;
+            pair_of(Q, hi, lo);
+            if (hi == lo) continue;
+            const int q = ((ma >> hi) & 1u) ? hi : lo, p = q == hi ? lo : hi;   // q annihilated, p created
+            if (!((mb >> p) & 1u) || ((mb >> q) & 1u)) continue;
+            const uint32_t eb = b.pairB[Ib * P + nA + Q - hi];   // E_qp on I_b (p in I_b, q not)
+            const double x = c[(int64_t)(L & 0xFFFFFu) * b.Nb + (eb & kPairJ)];
+            acc += ((L ^ eb) >> 31) ? x : -x;
+        }
+        sg[d] += lam * acc;
+    }
+}
+
+static hipError_t launch_spin_sigma(const Batch &b, VecRef c, VecRef sig, bool skip_done, hipStream_t s) {
+    if (b.spin_shift == 0.0) return hipSuccess;
+    hipLaunchKernelGGL(k_spin_sigma, dim3(grid_for(b.dim, 256, 4096), b.B), dim3(256), 0, s, b, c, sig,
+                       skip_done ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done, bool dots,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t evg, hipEvent_t ev2) {
     if (b.sigma_variant == SIGMA_STRIP) {
@@ -377,6 +420,8 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
         hipError_t e = launch_strip(b, c, sig, shift, skip_done ? 1 : 0, s, ev1);
         if (e != hipSuccess) return e;
         if (evg) (void)hipEventRecord(evg, s);
+        // (before the GEMM, whose epilogue forms the Davidson dots of the final sigma)
+        if ((e = launch_spin_sigma(b, c, sig, skip_done, s)) != hipSuccess) return e;
         e = launch_gemm_h(b, c, sig, skip_done ? 1 : 0, dots ? 1 : 0, s);
         if (ev2) (void)hipEventRecord(ev2, s);
         return e;
@@ -398,6 +443,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
     dim3 grid(grid_for(b.dim, 256, 4096), b.B);
     hipLaunchKernelGGL(k_sigma_g, grid, dim3(256), 0, s, b, c, sig, shift, skip_done ? 1 : 0);
     e = hipGetLastError();
+    if (e == hipSuccess) e = launch_spin_sigma(b, c, sig, skip_done, s);
     if (ev2) (void)hipEventRecord(ev2, s);
     return e;
 }

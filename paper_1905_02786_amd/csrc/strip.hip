@@ -38,7 +38,6 @@ __host__ __device__ inline int strip_pair_packed(int qs, int nA) {
 //  * scatter form [N_s + 1][P + 1]: byte offset J * 128 of the target row of
 //    the sigma strip for off-diagonal links, else the discard row (N_s * 128);
 //    bit 31 the sign; column P and row N_s are all discard.
-constexpr uint32_t kPairJ = 0xFFFFFu, kPairValid = 1u << 30, kPairSign = 1u << 31;
 
 // Compile-time shape of the strip kernel for n_A active orbitals.
 template <int NA>

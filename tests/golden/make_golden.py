@@ -20,6 +20,10 @@ Outputs (JSON, one file per workload) next to this script:
                        problem up to order 4 (dims up to 853776)
   rdm_large.npz        CASCI energy and the active blocks of gamma and Gamma of
                        tuples with 10, 11 and 12 active orbitals
+  plain_spin.json      full-order MBE of the plain 10-orbital problem with every
+                       CASCI energy that of the tuple's lowest singlet
+                       (spin-targeted; the problem's lowest states are often
+                       triplets)
 """
 from __future__ import annotations
 
@@ -278,6 +282,20 @@ def rdm_large():
         print(tag, sp.dim, w[o[0]], w[o[1]], f"{time.time() - t:.1f}s", flush=True)
         np.savez_compressed(os.path.join(HERE, "rdm_large.npz"), **out)
     print("wrote rdm_large.npz", flush=True)
+
+
+def plain_spin():
+    from oracle import spin
+    P = synth.config_plain(0)
+    t0 = time.time()
+    res = mbe.run(P, energy=lambda S: spin.casci_energy_spin(P, S))
+    plain_e = {}
+    for o in res.orders:
+        for S in o.tuples:
+            if len(S) <= 2:
+                plain_e[",".join(map(str, S))] = fci.casci_energy(P, S)
+    write("plain_spin.json", mbe_json(P, res, {"spin": 0, "lowest_any_spin": plain_e,
+                                              "seconds": time.time() - t0}))
 
 
 if __name__ == "__main__":
