@@ -36,7 +36,7 @@ METRIC = "CASCI increments/s + sigma FP64 GFLOP/s, batched vs per-solve, |Î”E|â‰
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {0: "k_sigma_strip", 1: "k_sigma_linked_gat", 2: "k_sigma_linked_res", 3: "k_sigma_linked_dv",
-                4: "k_sigma_w", 5: "k_linked_wr"}
+                4: "k_sigma_w", 5: "k_linked_wr", 6: "k_whole"}
 # Calibrated HBM bytes per dispatch of the dominant kernel from the FETCH_SIZE /
 # WRITE_SIZE passes of profiles/, valid only while the kernel sources hash to
 # the value they were taken on.

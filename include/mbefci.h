@@ -165,6 +165,13 @@ typedef struct {
                                state's own (the shift vanishes on it).  The paper's energies are those
                                of singlet ground states (Sec. 4); the diagonal and the P space include
                                the shift. */
+    int32_t whole_dim;      /* whole-tuple mode: with profile = 0, shape classes of at most this many
+                               determinants (0..4900, default 1225; 0: off) and at most 10 active
+                               orbitals run each tuple's whole Davidson solve in one workgroup of a
+                               single launch (the batched path launches a dozen kernels per
+                               iteration); their P space is at most 32 determinants unless it holds
+                               the whole CAS.  Above about 1225 determinants the batched path's
+                               MFMA sigma is faster.  Same energies within the tolerances. */
 } mbefci_options;
 
 typedef struct {
@@ -186,6 +193,7 @@ typedef struct {
                                    sigma_ms holds that form's MFMA kernel alone) */
     int64_t graph_batches;      /* batches whose iteration ran as a captured hipGraph */
     int64_t tuned_classes;      /* shape classes timed by the autotuner in this call */
+    int64_t whole_batches;      /* batches solved in whole-tuple mode (options.whole_dim) */
 } mbefci_stats;
 
 /* Counters of one shape class (active orbitals, active alpha and beta
@@ -195,7 +203,8 @@ typedef struct {
     int32_t kernel;             /* alpha-beta sigma kernel: 0 k_sigma_strip (all pair rows),
                                    1 k_sigma_linked_gat, 2 k_sigma_linked_res, 3 k_sigma_linked_dv,
                                    4 k_sigma_w + k_sigma_g (W materialised), 5 k_linked_wr +
-                                   k_linked_gw (linked rows through W in the workspace) */
+                                   k_linked_gw (linked rows through W in the workspace), 6 whole-
+                                   tuple mode (k_whole: sigma by link pairs inside the solve) */
     int64_t dim;                /* determinants per tuple */
     int64_t tuples, iterations, sigma_calls, sigma_launches;
     double sigma_flops;         /* as mbefci_stats.sigma_flops */

@@ -21,7 +21,7 @@ class Options(ctypes.Structure):
                 ("gradient", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
                 ("pspace", c_int32), ("linked_rows", c_int32), ("stream_last", c_int32),
                 ("graph", c_int32), ("autotune", c_int32), ("restart_keep", c_int32),
-                ("spin_shift", c_double)]
+                ("spin_shift", c_double), ("whole_dim", c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -30,7 +30,8 @@ class Stats(ctypes.Structure):
                 ("sigma_total_ms", c_double), ("iterations_total", c_int64),
                 ("iterations_max", c_int64), ("solve_ms", c_double),
                 ("gs_second_pass", c_int64), ("second_pass", c_int64), ("gather_ms", c_double),
-                ("graph_batches", c_int64), ("tuned_classes", c_int64)]
+                ("graph_batches", c_int64), ("tuned_classes", c_int64),
+                ("whole_batches", c_int64)]
 
 
 class ClassStats(ctypes.Structure):

@@ -60,6 +60,31 @@ __device__ __forceinline__ double *parts(const Batch &b, int t, int blk) {
     return b.part + ((int64_t)t * (b.nblk + 1) + blk) * kParts;
 }
 
+// (S_- S_+ c)(I_a, I_b) over the active orbitals, with S_- S_+ = N_b -
+// sum_pq E^a_qp E^b_pq (the doubly occupied core adds nothing): the diagonal
+// (n_b - orbitals holding both spins) c(I), and for each alpha link
+// J_a = E_pq I_a (q in I_a, p not) with p in I_b and q not, the beta string
+// J_b = E_qp I_b from the dense pair table: - s_a s_b c(J_a, J_b).
+__device__ __forceinline__ double spin_ss(const Batch &b, const double *c, int64_t Ia, int64_t Ib) {
+    const uint32_t ma = b.strA[Ia], mb = b.strB[Ib];
+    const int nA = b.nA, P = b.pl.P;
+    double acc = (double)(b.nb - __popc(ma & mb)) * c[Ia * b.Nb + Ib];
+    const uint32_t *la = b.linkA + Ia * b.nentA;
+    for (int e = 0; e < b.nentA; ++e) {
+        const uint32_t L = la[e];
+        const int Q = (int)((L >> 20) & 0x3FFu);
+        int hi, lo;
+        pair_of(Q, hi, lo);
+        if (hi == lo) continue;
+        const int q = ((ma >> hi) & 1u) ? hi : lo, p = q == hi ? lo : hi;   // q annihilated, p created
+        if (!((mb >> p) & 1u) || ((mb >> q) & 1u)) continue;
+        const uint32_t eb = b.pairB[Ib * P + nA + Q - hi];   // E_qp on I_b (p in I_b, q not)
+        const double x = c[(int64_t)(L & 0xFFFFFu) * b.Nb + (eb & kPairJ)];
+        acc += ((L ^ eb) >> 31) ? x : -x;
+    }
+    return acc;
+}
+
 static inline int grid_for(int64_t work, int per_block, int cap) {
     int64_t g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;

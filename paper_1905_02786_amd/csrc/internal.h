@@ -123,6 +123,7 @@ struct Batch {
     // quotient
     int restart_keep;
     double spin_shift;      // lambda of the level shift lambda S_- S_+ (0: none)
+    int whole;              // whole-tuple mode: one workgroup per tuple runs the whole Davidson solve
     double *y2, *zp;        // [B][kMaxSpace]
     double *mu;             // [B]
     double *sdot;           // [B][kMaxSpace] S_i . V_m, i < m, of the basis vector V_m being added
@@ -217,5 +218,21 @@ hipError_t launch_rdm(const Batch &b, VecRef x, double *part, double *G, int nbl
 // weighted embedding of the batch's density matrices (b.rdm_G) into the
 // full-space gradient gh [n^2], ge [n^4] (device), weights w [B] (device)
 hipError_t launch_rdm_embed(const Batch &b, const double *w, double *gh, double *ge, hipStream_t s);
+
+// whole-tuple mode (whole.hip): classes of at most kWholeMaxDim determinants
+// and kWholeMaxActive orbitals, with the vector of each sigma, the pair
+// integrals, the string Hamiltonians and both link tables in LDS
+constexpr int kWholeMaxDim = 4900;
+constexpr int kWholeDefaultDim = 1225;   // default options.whole_dim (measured crossover)
+constexpr int kWholeMaxActive = 10;
+constexpr int kWholeMaxNent = 32;
+constexpr int kWholePsp = 32;      // P space of the whole-tuple mode (at most options.pspace)   // link entries per string (n (n_A - n + 1) <= 30 for n_A <= 10)
+// (same: both spins have the same electron count and share one string Hamiltonian)
+bool whole_fits(const ParamLayout &pl, int64_t dim, int64_t Na, int64_t Nb, int nentA, int nentB, bool same);
+// after the set-up (gather, string Hamiltonians, diagonal, P space, guess):
+// every iteration of every tuple, then theta, status, iter, m and y as the
+// batched iteration leaves them
+hipError_t launch_whole(const Batch &b, hipStream_t s);
+hipError_t init_whole_kernels();
 
 }  // namespace mbefci

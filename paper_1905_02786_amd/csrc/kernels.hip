@@ -1667,6 +1667,7 @@ hipError_t scratch_address(void **ptr) {
 hipError_t init_kernels() {
     hipError_t e = init_sigma_kernels();
     if (e != hipSuccess) return e;
+    if ((e = init_whole_kernels()) != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_psp_factor, hipFuncAttributeMaxDynamicSharedMemorySize, (int)psp_factor_lds());
 }
 

@@ -387,6 +387,7 @@ struct ClassPlan {
     bool linked;   // linked-row strip kernel
     bool linked_dv;   // its form without the diagonal slot (diagonal sums on the vector ALU)
     bool linked_w;    // linked rows through W in HBM (no sigma strip in LDS)
+    bool whole;       // whole-tuple mode (one workgroup per tuple, the Davidson loop on the device)
     bool rdm;
     int nblk_r, NP;
     size_t fixed_bytes, per_tuple;
@@ -431,6 +432,14 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     if (lm == 5 && cp.linked_w) cp.linked_dv = false;
     const bool cls = classic && !cp.linked_dv && !cp.linked_w;
     cp.linked = cls || cp.linked_dv || cp.linked_w;
+    // whole-tuple mode for small classes (not with per-launch sigma timing)
+    cp.whole = davidson && cp.variant == SIGMA_STRIP && !ctx->opt.profile && cp.dim <= ctx->opt.whole_dim &&
+               whole_fits(cp.pl, cp.dim, cp.ta->nstr, cp.tb->nstr, cp.ta->nent, cp.tb->nent,
+                          key.na == key.nb);
+    // a smaller P space there unless it holds the whole CAS: its
+    // factorisation is part of every class's set-up, and the iterations it
+    // saves are cheap in that mode
+    if (cp.whole && cp.dim > kPsp) cp.psp = std::min(cp.psp, kWholePsp);
     cp.fixed_bytes = align256(4 * (cp.ta->nstr + cp.tb->nstr)) +
                      align256(4 * (size_t)cp.ta->nstr * cp.ta->nent) +
                      align256(4 * (size_t)cp.tb->nstr * cp.tb->nent) +
@@ -532,6 +541,7 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.max_space = davidson ? ctx->opt.max_space : 0;
     b.restart_keep = ctx->opt.max_space >= 3 ? ctx->opt.restart_keep : 1;
     b.spin_shift = ctx->opt.spin_shift;
+    b.whole = cp.whole ? 1 : 0;
     b.max_iter = ctx->opt.max_iter;
     b.e_tol = ctx->opt.e_tol;
     b.r_tol = ctx->opt.r_tol;
@@ -674,7 +684,7 @@ mbefci_class_stats &class_stats(mbefci_ctx *ctx, const Batch &b) {
     c.n_alpha = b.na;
     c.n_beta = b.nb;
     c.dim = b.dim;
-    c.kernel = alpha_beta_kernel(b);
+    c.kernel = b.whole ? 6 : alpha_beta_kernel(b);
     return c;
 }
 
@@ -710,6 +720,8 @@ struct RdmOut {
     const double *w = nullptr;
 };
 
+mbefci_status davidson_finish(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out, const RdmOut *ro);
+
 // Davidson for one batch; energies/status (public codes) written at out[t].
 mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out,
                              const RdmOut *ro = nullptr) {
@@ -723,6 +735,12 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
     if ((e = launch_guess(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     const int64_t tstride = (int64_t)b.max_space * b.dim;
     VecRef vm{b.V, tstride, b.m, 0}, sm{b.S, tstride, b.m, 0};
+    if (b.whole) {
+        // every iteration of every tuple in one launch
+        if ((e = launch_whole(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        ++ctx->stats.whole_batches;
+        return davidson_finish(ctx, b, e_out, st_out, ro);
+    }
     // sigma of V_m into S_m, then column m of G (from the GEMM's partial dots
     // where the sigma variant computes them)
     auto sigma_and_G = [&](int64_t napps) -> mbefci_status {
@@ -797,6 +815,15 @@ mbefci_status davidson_batch(mbefci_ctx *ctx, const Batch &b, double *e_out, int
         if (graph) (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, std::string("Davidson iterations: ") + hipGetErrorString(e));
     }
+    return davidson_finish(ctx, b, e_out, st_out, ro);
+}
+
+// Energies, statuses and counters of a solved batch (and its density
+// matrices for an RDM run).
+mbefci_status davidson_finish(mbefci_ctx *ctx, const Batch &b, double *e_out, int32_t *st_out, const RdmOut *ro) {
+    hipStream_t s = ctx->stream;
+    hipError_t e;
+    const bool prof = ctx->opt.profile != 0;
     if ((e = launch_finalize(b, s)) != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
     if (ro) {
         const int NP = rdm_np(b.nA);
@@ -1527,6 +1554,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->autotune = 1;
     o->restart_keep = 2;
     o->spin_shift = 0.0;
+    o->whole_dim = kWholeDefaultDim;
 }
 
 mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
@@ -1701,6 +1729,8 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->restart_keep < 1 || o->restart_keep > 2) return ctx->fail(MBEFCI_EINVAL, "restart_keep must be 1 or 2");
     if (!(o->spin_shift >= 0.0) || !std::isfinite(o->spin_shift))
         return ctx->fail(MBEFCI_EINVAL, "spin_shift must be finite and >= 0");
+    if (o->whole_dim < 0 || o->whole_dim > kWholeMaxDim)
+        return ctx->fail(MBEFCI_EINVAL, "whole_dim must be in 0.." + std::to_string(kWholeMaxDim));
     ctx->opt = *o;
     return MBEFCI_OK;
 }

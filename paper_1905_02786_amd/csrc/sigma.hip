@@ -371,39 +371,16 @@ static hipError_t launch_gemm_h(const Batch &b, VecRef c, VecRef sig, int skip, 
 
 
 // Level shift toward the lowest state of total spin S = (n_a - n_b) / 2 of
-// the sector: sigma += lambda S_- S_+ c over the active orbitals, with
-// S_- S_+ = N_b - sum_pq E^a_qp E^b_pq (the doubly occupied core adds
-// nothing).  S_- S_+ vanishes on states of spin S and is positive on all
-// others.  Gather per determinant (I_a, I_b): the diagonal
-// (n_b - orbitals holding both spins) c(I), and for each alpha link
-// J_a = E_pq I_a (q in I_a, p not) with p in I_b and q not, the beta string
-// J_b = E_qp I_b from the dense pair table: - s_a s_b c(J_a, J_b).
+// the sector: sigma += lambda S_- S_+ c over the active orbitals (spin_ss).
+// S_- S_+ vanishes on states of spin S and is positive on all others.
 __global__ __launch_bounds__(256) void k_spin_sigma(Batch b, VecRef cref, VecRef sref, int skip_done) {
     const int t = blockIdx.y;
     if (skip_done && b.status[t] != ST_RUNNING) return;
     const double *c = vref(cref, t, b.dim);
     double *sg = const_cast<double *>(vref(sref, t, b.dim));
-    const int nA = b.nA, P = b.pl.P;
     const double lam = b.spin_shift;
-    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256) {
-        const int64_t Ia = d / b.Nb, Ib = d % b.Nb;
-        const uint32_t ma = b.strA[Ia], mb = b.strB[Ib];
-        double acc = (double)(b.nb - __popc(ma & mb)) * c[d];
-        const uint32_t *la = b.linkA + Ia * b.nentA;
-        for (int e = 0; e < b.nentA; ++e) {
-            const uint32_t L = la[e];
-            const int Q = (int)((L >> 20) & 0x3FFu);
-            int hi, lo;
-            pair_of(Q, hi, lo);
-            if (hi == lo) continue;
-            const int q = ((ma >> hi) & 1u) ? hi : lo, p = q == hi ? lo : hi;   // q annihilated, p created
-            if (!((mb >> p) & 1u) || ((mb >> q) & 1u)) continue;
-            const uint32_t eb = b.pairB[Ib * P + nA + Q - hi];   // E_qp on I_b (p in I_b, q not)
-            const double x = c[(int64_t)(L & 0xFFFFFu) * b.Nb + (eb & kPairJ)];
-            acc += ((L ^ eb) >> 31) ? x : -x;
-        }
-        sg[d] += lam * acc;
-    }
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256)
+        sg[d] += lam * spin_ss(b, c, d / b.Nb, d % b.Nb);
 }
 
 static hipError_t launch_spin_sigma(const Batch &b, VecRef c, VecRef sig, bool skip_done, hipStream_t s) {

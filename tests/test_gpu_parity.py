@@ -287,13 +287,15 @@ def test_pspace_settings_match_oracle(ws, pspace):
     """With the P-space preconditioner some corrections lie mostly inside the
     subspace and take the two explicit Gram-Schmidt passes instead of joining
     the basis through the triangular factor: with P spaces of 7 and 128 these
-    cases go through that path too (counted in the stats)."""
+    cases go through that path too (counted in the stats).  The batched
+    iteration (whole-tuple mode off; that mode's settings are covered in
+    test_gpu_whole.py)."""
     probs = {"hubbard8": synth.config_hubbard(8.0), "openshell": PROBLEMS["openshell"]()}
     worst = 0.0
     second = 0
     for name, S in PSPACE_CASES:
         P = probs[name]
-        ctx = _ctx(P, pspace=pspace)
+        ctx = _ctx(P, pspace=pspace, whole_dim=0)
         e, st = ctx.solve_tuples(len(S), [S] if S else [()], ws)
         second += ctx.stats()["gs_second_pass"]
         e_ref = fci.casci_energy(P, S)
@@ -419,12 +421,13 @@ def test_iteration_blocks_and_graphs_give_the_same_energies(ws):
     """Davidson iterations launched one per host round trip (profile = 1), in
     blocks (graph = 0) and as a replayed hipGraph (graph = 1): the same
     arithmetic, so bitwise the same energies, on tuples that take the
-    explicit Gram-Schmidt passes too (Hubbard U/t = 8, P space 7)."""
+    explicit Gram-Schmidt passes too (Hubbard U/t = 8, P space 7; the
+    whole-tuple mode, which would take these small classes, off)."""
     P = synth.config_hubbard(8.0)
     tuples = _tuples_with_dims(P, 4, 10 ** 9)
     out = []
     for opts in (dict(profile=1), dict(profile=0, graph=0), dict(profile=0, graph=1)):
-        ctx = _ctx(P, pspace=7, **opts)
+        ctx = _ctx(P, pspace=7, whole_dim=0, **opts)
         e, st = ctx.solve_tuples(4, tuples, ws)
         assert (st == 0).all()
         out.append(e)
