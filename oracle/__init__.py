@@ -18,6 +18,9 @@ Full Configuration Interaction. II. Strongly Correlated Regime"):
 * ``rdm``  -- one- and two-particle density matrices by explicit operator
   action, the adjoint weights of the increment recursion and the gradient of
   the summed MBE energy with respect to h_pq and (pq|rs).
+* ``casscf`` -- CASSCF orbitals of the reference space (the expansion
+  reference of Sec. 2): BFGS over the non-redundant rotations with the exact
+  gradient, then the canonical orbitals, and the integrals in them.
 
 Only ``tests/``, the smoke check of ``__graft_entry__`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no

@@ -20,6 +20,9 @@ Outputs (JSON, one file per workload) next to this script:
                        problem up to order 4 (dims up to 853776)
   rdm_large.npz        CASCI energy and the active blocks of gamma and Gamma of
                        tuples with 10, 11 and 12 active orbitals
+  casscf.json          canonical CASSCF orbitals of [Pi] (energy, U, h) and the
+                       full-order MBE in them, plain problem and a 7-orbital
+                       problem with a frozen orbital
   plain_spin.json      full-order MBE of the plain 10-orbital problem with every
                        CASCI energy that of the tuple's lowest singlet
                        (spin-targeted; the problem's lowest states are often
@@ -282,6 +285,24 @@ def rdm_large():
         print(tag, sp.dim, w[o[0]], w[o[1]], f"{time.time() - t:.1f}s", flush=True)
         np.savez_compressed(os.path.join(HERE, "rdm_large.npz"), **out)
     print("wrote rdm_large.npz", flush=True)
+
+
+def casscf():
+    """CASSCF expansion references: the canonical CASSCF orbitals of [Pi]
+    and the full-order MBE in them, for the plain problem and a 7-orbital
+    problem with a frozen orbital."""
+    from oracle import casscf as cs
+    out = {}
+    for key, P in (("plain", synth.config_plain(0)),
+                   ("small7", synth.small_problem(7, 3, 3, [2, 3], nfrozen=1, nvec=6, seed=11, vec_std=0.15,
+                                                  offdiag_std=0.2))):
+        t0 = time.time()
+        e, U, Pc = cs.casscf(P)
+        res = mbe.run(Pc, energy=lambda S: fci.casci_energy(Pc, S))
+        out[key] = mbe_json(Pc, res, {"e_casscf": e, "e_casci_start": fci.casci_energy(P, ()),
+                                      "h": Pc.h.tolist(), "U": U.tolist(), "fci": fci.fci_energy(P),
+                                      "seconds": time.time() - t0})
+    write("casscf.json", out)
 
 
 def plain_spin():
