@@ -20,7 +20,9 @@ is then carried out in that orbital basis.  Definitions used here:
   local rotation U expm(K) at K = 0 is 2 (F_qp - F_pq);
 * the CASSCF orbitals minimise E over kappa; the oracle takes a plain BFGS
   minimisation (scipy) in the fixed frame U_0 expm(K(kappa)), whose exact
-  gradient is the chain rule through the Frechet derivative of expm;
+  gradient is the chain rule through the Frechet derivative of expm, and
+  then solves g(kappa) = 0 from that minimum by Newton's method (energies
+  stop resolving BFGS's line search near |g| = 1e-8);
 * canonical orbitals: in the optimised basis, the core and virtual blocks are
   rotated to the eigenvectors of the Fock matrix
       f_pq = h'_pq + sum_rs gamma_rs [ (pq|rs)' - 1/2 (pr|sq)' ]
@@ -136,8 +138,25 @@ def optimise(problem, U0=None, g_tol=1e-9, max_iter=2000):
         return U0, reference_state(transform(problem, U0))[0]
     res = so.minimize(lambda x: energy_and_gradient(problem, U0, pairs, x), np.zeros(len(pairs)), jac=True,
                       method="BFGS", options={"gtol": g_tol, "maxiter": max_iter})
-    U = U0 @ sl.expm(kappa_matrix(n, pairs, res.x))
-    return U, float(res.fun)
+    x = res.x
+    # BFGS stops where energy differences no longer resolve its line search
+    # (|g| of about 1e-8); the stationarity condition g(kappa) = 0 is smooth
+    # and is solved further from that minimum by Newton's method, the
+    # Jacobian of the exact gradient by central differences
+    grad = lambda y: energy_and_gradient(problem, U0, pairs, y)[1]  # noqa: E731
+    for _ in range(8):
+        g = grad(x)
+        if np.abs(g).max() <= g_tol:
+            break
+        hstep = 1e-6
+        J = np.empty((len(x), len(x)))
+        for k in range(len(x)):
+            d = np.zeros(len(x))
+            d[k] = hstep
+            J[:, k] = (grad(x + d) - grad(x - d)) / (2.0 * hstep)
+        x = x - np.linalg.solve(0.5 * (J + J.T), g)
+    U = U0 @ sl.expm(kappa_matrix(n, pairs, x))
+    return U, float(energy_and_gradient(problem, U0, pairs, x)[0])
 
 
 def canonicalise(problem, U):
