@@ -387,6 +387,42 @@ mbefci_status mbefci_string_tables(int32_t norb_active, int32_t nel, int64_t *n_
 mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double gE, void *d_workspace,
                               size_t ws_bytes, double *grad_h1, double *grad_eri);
 
+/* CASSCF expansion reference (Sec. 2: the orbitals of the reference space
+ * chosen to minimise its CASCI energy; the paper's best results use them,
+ * Sec. 4.1.3 and 4.2.2).  Minimises the reference-space CASCI energy (the
+ * state of epsilon(()) of the expansion, options.spin_shift included) over
+ * the rotations phi'_j = sum_i phi_i U_ij between the core (doubly occupied
+ * orbitals outside [Pi] that are not frozen), the active ([Pi]) and the
+ * virtual orbitals; frozen orbitals are not rotated.  Then the orbitals are
+ * made canonical: eigenvectors of the Fock matrix f_pq = h_pq + sum_rs
+ * gamma_rs [(pq|rs) - 1/2 (pr|sq)] in the core and the virtual blocks
+ * (ascending), natural orbitals in the active block (descending occupation),
+ * each space keeping its orbital positions, every column of U signed so that
+ * its largest entry is positive.  On return the context's Hamiltonian is the
+ * one in these orbitals (h' = U^T h U and the four-index transformation of
+ * (pq|rs), on the device and in mbefci_get_hamiltonian), so that mbefci_run
+ * expands in them.  The orbital gradient is 2 (F_qp - F_pq) with the
+ * generalised Fock matrix F_pq = sum_r gamma_pr h_qr + sum_rst Gamma_prst
+ * (qr|st); the steps are limited-memory BFGS in the frame of the current
+ * orbitals on a diagonal Hessian estimate, with energy backtracking; each
+ * energy is a device CASCI of [Pi] converged to |r| < 1e-11.
+ * Arguments: d_workspace of at least 2 n^4 + n^2 + n^4 doubles plus what the
+ * reference CASCI needs (the gradient accumulators and one batch); max_iter
+ * >= 1 optimisation steps; g_tol > 0 on the largest gradient entry (the
+ * tuples' energies are not stationary in the orbitals, so they follow its
+ * accuracy: 1e-10 gives them to about 1e-9).  Host outputs (each may be
+ * null): U [n*n] row-major (column j = new orbital j in the orbitals the
+ * Hamiltonian had on entry), the CASSCF energy, the steps taken.  ENOCONV if
+ * g_tol is not reached in max_iter steps (the Hamiltonian is then replaced
+ * by the canonical form of the last orbitals); ETOOLARGE for a reference space
+ * of more than 12 orbitals; ENOMEM if the workspace is too small. */
+mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes, int32_t max_iter, double g_tol,
+                            double *U, double *energy, int32_t *iterations);
+
+/* The context's current Hamiltonian (host outputs, each may be null): h1
+ * [n*n], (pq|rs) [n^4] in the full layout, the constant. */
+mbefci_status mbefci_get_hamiltonian(const mbefci_ctx *ctx, double *h1, double *eri, double *e_const);
+
 /* CASCI energy and full-space density matrices of one tuple (host outputs:
  * *energy, gamma [n*n], Gamma [n^4], conventions as at mbefci_backward). */
 mbefci_status mbefci_tuple_rdm(mbefci_ctx *ctx, int32_t order, const int16_t *tuple, void *d_workspace,

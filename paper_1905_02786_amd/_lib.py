@@ -82,6 +82,8 @@ SIGNATURES = [
     ("mbefci_get_stats", c_int32, [c_void_p, ctypes.POINTER(Stats)]),
     ("mbefci_get_class_stats", c_int32, [c_void_p, ctypes.POINTER(c_int32), c_void_p]),
     ("mbefci_backward", c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, c_void_p, c_void_p]),
+    ("mbefci_casscf", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
+    ("mbefci_get_hamiltonian", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("mbefci_tuple_rdm", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,
                                    c_void_p]),
 ]

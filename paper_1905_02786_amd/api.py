@@ -257,6 +257,27 @@ class Context:
                                             ctypes.byref(e), _p(g1), _p(g2)))
         return e.value, g1, g2
 
+    def casscf(self, workspace, max_iter: int = 500, g_tol: float = 1e-10) -> dict:
+        """CASSCF orbitals of the reference space; the context's Hamiltonian
+        is replaced by the one in the canonical CASSCF orbitals.  Returns
+        {"energy", "U" [n, n] (columns: new orbitals), "iterations"}."""
+        n = self.norb
+        U = np.zeros((n, n))
+        e = ctypes.c_double()
+        it = ctypes.c_int32()
+        self._check(self.L.mbefci_casscf(self.ptr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                         int(max_iter), float(g_tol), _p(U), ctypes.byref(e), ctypes.byref(it)))
+        return {"energy": e.value, "U": U, "iterations": it.value}
+
+    def hamiltonian(self):
+        """(h [n, n], (pq|rs) [n, n, n, n], constant) of the context."""
+        n = self.norb
+        h = np.zeros((n, n))
+        eri = np.zeros((n, n, n, n))
+        c = ctypes.c_double()
+        self._check(self.L.mbefci_get_hamiltonian(self.ptr, _p(h), _p(eri), ctypes.byref(c)))
+        return h, eri, c.value
+
     def run_host(self, energy) -> Result:
         """The planner with tuple energies from the Python callable
         energy(order, tuples[int16 ntup x order]) -> float64 array."""

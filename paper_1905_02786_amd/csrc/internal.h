@@ -235,4 +235,15 @@ bool whole_fits(const ParamLayout &pl, int64_t dim, int64_t Na, int64_t Nb, int 
 hipError_t launch_whole(const Batch &b, hipStream_t s);
 hipError_t init_whole_kernels();
 
+// CASSCF expansion reference (casscf.hip)
+constexpr int kMaxOrb = 64;         // orbital limit of the library
+// h = U^T h0 U and eri = the four-index transformation of eri0 (full n^4
+// layouts; tmp: n^4 doubles of scratch)
+hipError_t launch_rotate_integrals(const double *h0, const double *eri0, const double *U, double *h, double *eri,
+                                   double *tmp, int n, hipStream_t s);
+// generalised Fock matrix F and Fock matrix f (n x n) from the full-space
+// gamma and Gamma / 2 (g2h); occ: the no orbitals with density
+hipError_t launch_fock(const double *h, const double *eri, const double *g1, const double *g2h, const int32_t *occ,
+                       int no, int n, double *F, double *f, hipStream_t s);
+
 }  // namespace mbefci

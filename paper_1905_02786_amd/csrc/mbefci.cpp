@@ -1532,6 +1532,105 @@ void write_grad(const mbefci_ctx *ctx, const std::vector<double> &gh, const std:
 
 // ====================================================================== ABI
 
+
+namespace {
+
+// ------------------------------------------------- CASSCF (host algebra) --
+// Small dense helpers on n x n row-major matrices (n <= 64): the orbital
+// rotation exp(K) of an antisymmetric K, products, and symmetric
+// eigenvectors.  The integrals, the CASCI and the Fock matrices are on the
+// device.
+using Mat = std::vector<double>;
+
+Mat mat_mul(const Mat &A, const Mat &B, int n) {
+    Mat C((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            const double a = A[(size_t)i * n + k];
+            if (a == 0.0) continue;
+            for (int j = 0; j < n; ++j) C[(size_t)i * n + j] += a * B[(size_t)k * n + j];
+        }
+    return C;
+}
+
+// exp(K) by scaling and squaring: K / 2^s with norm below 1/4, its Taylor
+// series to 16 terms, then s squarings.
+Mat mat_exp(const Mat &K, int n) {
+    double nrm = 0.0;
+    for (double v : K) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    int sq = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++sq;
+    }
+    const double sc = std::ldexp(1.0, -sq);
+    Mat A(K);
+    for (double &v : A) v *= sc;
+    Mat E((size_t)n * n, 0.0), T((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) E[(size_t)i * n + i] = T[(size_t)i * n + i] = 1.0;
+    for (int k = 1; k <= 16; ++k) {
+        T = mat_mul(T, A, n);
+        for (double &v : T) v /= k;
+        for (size_t i = 0; i < E.size(); ++i) E[i] += T[i];
+    }
+    for (int k = 0; k < sq; ++k) E = mat_mul(E, E, n);
+    return E;
+}
+
+// Eigenvectors of the symmetric m x m matrix A (cyclic Jacobi); columns of V
+// in the order of ascending (or descending) eigenvalues.
+void sym_eig(Mat A, int m, bool descending, std::vector<double> &w, Mat &V) {
+    V.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) V[(size_t)i * m + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const double a = A[(size_t)i * m + j] * A[(size_t)i * m + j];
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-32 * tot || off == 0.0) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = A[(size_t)p * m + q];
+                if (apq == 0.0) continue;
+                const double tau = (A[(size_t)q * m + q] - A[(size_t)p * m + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < m; ++k) {   // columns p, q
+                    const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+                    A[(size_t)k * m + p] = c * akp - s * akq;
+                    A[(size_t)k * m + q] = s * akp + c * akq;
+                    const double vkp = V[(size_t)k * m + p], vkq = V[(size_t)k * m + q];
+                    V[(size_t)k * m + p] = c * vkp - s * vkq;
+                    V[(size_t)k * m + q] = s * vkp + c * vkq;
+                }
+                for (int k = 0; k < m; ++k) {   // rows p, q
+                    const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+                    A[(size_t)p * m + k] = c * apk - s * aqk;
+                    A[(size_t)q * m + k] = s * apk + c * aqk;
+                }
+            }
+    }
+    std::vector<int> ord(m);
+    for (int i = 0; i < m; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        const double da = A[(size_t)a * m + a], db = A[(size_t)b * m + b];
+        return descending ? da > db : da < db;
+    });
+    Mat Vs((size_t)m * m);
+    w.resize(m);
+    for (int j = 0; j < m; ++j) {
+        w[j] = A[(size_t)ord[j] * m + ord[j]];
+        for (int i = 0; i < m; ++i) Vs[(size_t)i * m + j] = V[(size_t)i * m + ord[j]];
+    }
+    V.swap(Vs);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *mbefci_version(void) { return "mbefci 0.1 (gfx950, FP64)"; }
@@ -2041,6 +2140,267 @@ mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double 
     if ((rc = grad_fetch(ctx, gh, ge)) != MBEFCI_OK) return rc;
     write_grad(ctx, gh, ge, gE, grad_h1, grad_eri);
     ctx->stats.solve_ms = now_ms() - t0;
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_iter, double g_tol, double *U_out,
+                            double *e_out, int32_t *iter_out) {
+    if (!ctx) return MBEFCI_EINVAL;
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    if (!ctx->ham_set || !ctx->spaces_set) return ctx->fail(MBEFCI_EINVAL, "Hamiltonian and spaces must be set");
+    if (max_iter < 1 || !(g_tol > 0.0)) return ctx->fail(MBEFCI_EINVAL, "max_iter >= 1 and g_tol > 0 required");
+    if ((int)ctx->ref.size() > kRdmMaxActive)
+        return ctx->fail(MBEFCI_ETOOLARGE, "reference space above " + std::to_string(kRdmMaxActive) + " orbitals");
+    const double t0 = now_ms();
+    const int n = ctx->norb;
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    // spaces: frozen (never rotated), core, active = [Pi], virtual
+    std::vector<int> kind(n, 3);   // 0 frozen, 1 core, 2 active, 3 virtual
+    for (int p = 0; p < ctx->nbeta; ++p) kind[p] = 1;
+    for (int p = 0; p < ctx->nfrozen; ++p) kind[p] = 0;
+    for (int p : ctx->ref) kind[p] = 2;
+    std::vector<int> C, A, V, occ;
+    for (int p = 0; p < n; ++p) {
+        if (kind[p] == 1) C.push_back(p);
+        if (kind[p] == 2) A.push_back(p);
+        if (kind[p] == 3) V.push_back(p);
+        if (kind[p] != 3) occ.push_back(p);
+    }
+    std::vector<std::pair<int, int>> pairs;
+    for (int p : C)
+        for (int q : A) pairs.emplace_back(p, q);
+    for (int p : C)
+        for (int q : V) pairs.emplace_back(p, q);
+    for (int p : A)
+        for (int q : V) pairs.emplace_back(p, q);
+    const int np = (int)pairs.size();
+    // workspace: the starting integrals, one n^4 scratch, U, F, f, occ; the
+    // rest for the reference CASCI and its density matrices
+    Carver cv{(char *)ws, wsb};
+    double *d_eri0 = cv.take<double>(n4), *d_tmp = cv.take<double>(n4), *d_h0 = cv.take<double>(n2);
+    double *d_U = cv.take<double>(n2), *d_F = cv.take<double>(n2), *d_f = cv.take<double>(n2);
+    int32_t *d_occ = cv.take<int32_t>(occ.size() + 1);
+    if (!cv.ok) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the integral transformation");
+    char *ws2 = (char *)ws + cv.off;
+    const size_t wsb2 = wsb - cv.off;
+    HIPCHK(hipMemcpyAsync(d_eri0, ctx->eri.data(), 8 * n4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_h0, ctx->h.data(), 8 * n2, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_occ, occ.data(), 4 * occ.size(), hipMemcpyHostToDevice, ctx->stream));
+    // the reference CASCI converged tightly: the gradient comes from its
+    // density matrices, which carry the residual to first order
+    const mbefci_options saved = ctx->opt;
+    ctx->opt.r_tol = std::min(ctx->opt.r_tol, 1e-11);
+    ctx->opt.e_tol = std::min(ctx->opt.e_tol, 1e-13);
+    ctx->opt.max_iter = std::max(ctx->opt.max_iter, 600);
+    struct Restore {
+        mbefci_ctx *c;
+        const mbefci_options &o;
+        ~Restore() { c->opt = o; }
+    } restore{ctx, saved};
+    Mat F(n2), f(n2), g1(n2);
+    // integrals in the orbitals U, the reference energy, F, f and gamma
+    auto evaluate = [&](const Mat &U, double &E) -> mbefci_status {
+        HIPCHK(hipMemcpyAsync(d_U, U.data(), 8 * n2, hipMemcpyHostToDevice, ctx->stream));
+        hipError_t e = launch_rotate_integrals(d_h0, d_eri0, d_U, ctx->d_h, ctx->d_eri, d_tmp, n, ctx->stream);
+        if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        size_t wsr = wsb2;
+        mbefci_status r = grad_region(ctx, ws2, &wsr);
+        if (r != MBEFCI_OK) return r;
+        std::vector<double> w1{1.0};
+        WeightSink sink;
+        sink.w = &w1;
+        int32_t st = 0;
+        r = solve_device(ctx, 0, 1, nullptr, ws2, wsr, &E, &st, &sink);
+        if (r != MBEFCI_OK) {
+            ctx->d_gh = ctx->d_ge = nullptr;
+            return r;
+        }
+        if (st != MBEFCI_TUPLE_OK) {
+            ctx->d_gh = ctx->d_ge = nullptr;
+            return ctx->fail(MBEFCI_ENOCONV, "reference CASCI did not converge");
+        }
+        e = launch_fock(ctx->d_h, ctx->d_eri, ctx->d_gh, ctx->d_ge, d_occ, (int)occ.size(), n, d_F, d_f, ctx->stream);
+        if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        HIPCHK(hipMemcpyAsync(F.data(), d_F, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(f.data(), d_f, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(g1.data(), ctx->d_gh, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->d_gh = ctx->d_ge = nullptr;
+        return MBEFCI_OK;
+    };
+    // dE/dkappa_pq of the local rotation U exp(K), K_pq = kappa = -K_qp:
+    // 2 (F_qp - F_pq)
+    auto gradient = [&](std::vector<double> &g) {
+        g.resize(np);
+        for (int k = 0; k < np; ++k) {
+            const int p = pairs[k].first, q = pairs[k].second;
+            g[k] = 2.0 * (F[(size_t)q * n + p] - F[(size_t)p * n + q]);
+        }
+    };
+    auto rotation = [&](const std::vector<double> &d) {
+        Mat K(n2, 0.0);
+        for (int k = 0; k < np; ++k) {
+            K[(size_t)pairs[k].first * n + pairs[k].second] = d[k];
+            K[(size_t)pairs[k].second * n + pairs[k].first] = -d[k];
+        }
+        return mat_exp(K, n);
+    };
+    Mat U(n2, 0.0);
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+    double E = 0.0;
+    if ((rc = evaluate(U, E)) != MBEFCI_OK) return rc;
+    std::vector<double> g;
+    gradient(g);
+    // quasi-Newton in the frame of the current orbitals: limited-memory BFGS
+    // (8 pairs) on a diagonal estimate of the Hessian,
+    // 2 gamma_pp f_qq + 2 gamma_qq f_pp - 2 F_pp - 2 F_qq (at least 0.05),
+    // steps of at most 0.5 per rotation, halved until the energy falls by a
+    // fraction of the predicted decrease
+    std::vector<std::vector<double>> hs, hy;
+    int it = 0;
+    double gmax = 0.0;
+    for (; it < max_iter; ++it) {
+        gmax = 0.0;
+        for (double v : g) gmax = std::max(gmax, std::fabs(v));
+        if (gmax < g_tol || np == 0) break;
+        std::vector<double> H(np);
+        for (int k = 0; k < np; ++k) {
+            const size_t p = pairs[k].first, q = pairs[k].second;
+            const double h = 2.0 * g1[p * n + p] * f[q * n + q] + 2.0 * g1[q * n + q] * f[p * n + p] -
+                             2.0 * F[p * n + p] - 2.0 * F[q * n + q];
+            H[k] = std::max(std::fabs(h), 0.05);
+        }
+        std::vector<double> r(g), al(hs.size());
+        for (int m = (int)hs.size() - 1; m >= 0; --m) {
+            double ys = 0.0, sr = 0.0;
+            for (int k = 0; k < np; ++k) {
+                ys += hy[m][k] * hs[m][k];
+                sr += hs[m][k] * r[k];
+            }
+            al[m] = sr / ys;
+            for (int k = 0; k < np; ++k) r[k] -= al[m] * hy[m][k];
+        }
+        for (int k = 0; k < np; ++k) r[k] /= H[k];
+        for (size_t m = 0; m < hs.size(); ++m) {
+            double ys = 0.0, yr = 0.0;
+            for (int k = 0; k < np; ++k) {
+                ys += hy[m][k] * hs[m][k];
+                yr += hy[m][k] * r[k];
+            }
+            const double be = yr / ys;
+            for (int k = 0; k < np; ++k) r[k] += hs[m][k] * (al[m] - be);
+        }
+        std::vector<double> d(np);
+        double dg = 0.0, dmax = 0.0;
+        for (int k = 0; k < np; ++k) {
+            d[k] = -r[k];
+            dg += d[k] * g[k];
+        }
+        if (!(dg < 0.0)) {   // not a descent direction: the preconditioned gradient
+            hs.clear();
+            hy.clear();
+            dg = 0.0;
+            for (int k = 0; k < np; ++k) {
+                d[k] = -g[k] / H[k];
+                dg += d[k] * g[k];
+            }
+        }
+        for (double v : d) dmax = std::max(dmax, std::fabs(v));
+        if (dmax > 0.5) {
+            for (double &v : d) v *= 0.5 / dmax;
+            dg *= 0.5 / dmax;
+        }
+        double alpha = 1.0, En = 0.0;
+        Mat Un;
+        for (;;) {
+            std::vector<double> ds(d);
+            for (double &v : ds) v *= alpha;
+            Un = mat_mul(U, rotation(ds), n);
+            if ((rc = evaluate(Un, En)) != MBEFCI_OK) return rc;
+            // (a predicted decrease below the energy's own rounding cannot be
+            // checked: near convergence the quasi-Newton step is taken as it is)
+            if (En <= E + 1e-4 * alpha * dg || alpha < 1e-3 ||
+                std::fabs(alpha * dg) < 1e-12 * std::max(1.0, std::fabs(E)))
+                break;
+            alpha *= 0.5;
+        }
+        std::vector<double> gn;
+        gradient(gn);
+        std::vector<double> sv(np), yv(np);
+        double ys = 0.0;
+        for (int k = 0; k < np; ++k) {
+            sv[k] = alpha * d[k];
+            yv[k] = gn[k] - g[k];
+            ys += sv[k] * yv[k];
+        }
+        if (ys > 1e-14) {
+            hs.push_back(sv);
+            hy.push_back(yv);
+            if (hs.size() > 8) {
+                hs.erase(hs.begin());
+                hy.erase(hy.begin());
+            }
+        }
+        U.swap(Un);
+        E = En;
+        g.swap(gn);
+    }
+    // canonical orbitals: Fock eigenvectors in the core and virtual blocks
+    // (ascending), natural orbitals in the active block (descending
+    // occupation), each at its space's own positions; every column signed so
+    // that its largest entry is positive
+    Mat R(n2, 0.0);
+    for (int i = 0; i < n; ++i) R[(size_t)i * n + i] = 1.0;
+    auto block = [&](const std::vector<int> &B, const Mat &M, bool desc) {
+        const int m = (int)B.size();
+        if (m == 0) return;
+        Mat S((size_t)m * m), Vb;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) S[(size_t)i * m + j] = 0.5 * (M[(size_t)B[i] * n + B[j]] + M[(size_t)B[j] * n + B[i]]);
+        std::vector<double> w;
+        sym_eig(S, m, desc, w, Vb);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) R[(size_t)B[i] * n + B[j]] = Vb[(size_t)i * m + j];
+    };
+    block(C, f, false);
+    block(V, f, false);
+    block(A, g1, true);
+    Mat Uc = mat_mul(U, R, n);
+    for (int j = 0; j < n; ++j) {
+        int im = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::fabs(Uc[(size_t)i * n + j]) > std::fabs(Uc[(size_t)im * n + j])) im = i;
+        if (Uc[(size_t)im * n + j] < 0.0)
+            for (int i = 0; i < n; ++i) Uc[(size_t)i * n + j] = -Uc[(size_t)i * n + j];
+    }
+    // the context's Hamiltonian in the canonical orbitals (device and host)
+    HIPCHK(hipMemcpyAsync(d_U, Uc.data(), 8 * n2, hipMemcpyHostToDevice, ctx->stream));
+    hipError_t e = launch_rotate_integrals(d_h0, d_eri0, d_U, ctx->d_h, ctx->d_eri, d_tmp, n, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(ctx->h.data(), ctx->d_h, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->eri.data(), ctx->d_eri, 8 * n4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int p = 0; p < n; ++p)   // exact symmetry of h (rounding of the two products)
+        for (int q = 0; q < p; ++q) {
+            const double v = 0.5 * (ctx->h[(size_t)p * n + q] + ctx->h[(size_t)q * n + p]);
+            ctx->h[(size_t)p * n + q] = ctx->h[(size_t)q * n + p] = v;
+        }
+    HIPCHK(hipMemcpy(ctx->d_h, ctx->h.data(), 8 * n2, hipMemcpyHostToDevice));
+    if (U_out) std::memcpy(U_out, Uc.data(), 8 * n2);
+    if (e_out) *e_out = E;
+    if (iter_out) *iter_out = it;
+    ctx->stats.solve_ms = now_ms() - t0;
+    if (gmax >= g_tol && np > 0) return ctx->fail(MBEFCI_ENOCONV, "orbital gradient above g_tol after max_iter");
+    return MBEFCI_OK;
+}
+
+mbefci_status mbefci_get_hamiltonian(const mbefci_ctx *ctx, double *h1, double *eri, double *e_const) {
+    if (!ctx || !ctx->ham_set) return MBEFCI_EINVAL;
+    const size_t n2 = (size_t)ctx->norb * ctx->norb;
+    if (h1) std::memcpy(h1, ctx->h.data(), 8 * n2);
+    if (eri) std::memcpy(eri, ctx->eri.data(), 8 * n2 * n2);
+    if (e_const) *e_const = ctx->e_const;
     return MBEFCI_OK;
 }
 
