@@ -12,7 +12,8 @@ is then carried out in that orbital basis.  Definitions used here:
   (A, V) (rotations inside a space leave the CASCI energy unchanged);
 * h' = U^T h U, (ij|kl)' = sum U_pi U_qj U_rk U_sl (pq|rs);
 * E(U) = the lowest CASCI eigenvalue of [Pi] with h', (..|..)' (the state of
-  epsilon(()) of the MBE);
+  epsilon(()) of the MBE), or with ``spin`` = S the lowest one of total spin
+  S (oracle/spin.py), the state a spin-targeted expansion takes;
 * gradient: with the full-space density matrices gamma, Gamma of that state
   in the basis U and the generalised Fock matrix
       F_pq = sum_r gamma_pr h'_qr + sum_rst Gamma_prst (qr|st)',
@@ -42,7 +43,7 @@ import numpy as np
 import scipy.linalg as sl
 import scipy.optimize as so
 
-from . import fci, rdm
+from . import fci, rdm, spin as spin_mod
 
 
 def spaces(problem):
@@ -74,9 +75,14 @@ def transform(problem, U):
     return replace(problem, h=np.ascontiguousarray(h), eri=np.ascontiguousarray(e))
 
 
-def reference_state(problem):
-    """Energy and full-space gamma, Gamma of the reference-space CASCI."""
-    e, v, sp = fci.casci_energy(problem, (), want_vector=True)
+def reference_state(problem, spin=None):
+    """Energy and full-space gamma, Gamma of the reference-space CASCI (its
+    lowest state, or with spin = S its lowest state of total spin S)."""
+    if spin is None:
+        e, v, sp = fci.casci_energy(problem, (), want_vector=True)
+    else:
+        sp = fci.cas_space(problem, ())
+        e, v, _ = spin_mod.lowest_with_spin(problem, sp, spin, want_vector=True)
     g1, g2 = rdm.rdm12(problem, sp, v)
     return e, g1, g2
 
@@ -91,11 +97,11 @@ def fock(problem, g1):
     return problem.h + np.einsum("rs,pqrs->pq", g1, problem.eri) - 0.5 * np.einsum("rs,prsq->pq", g1, problem.eri)
 
 
-def local_gradient(problem, pairs=None):
+def local_gradient(problem, pairs=None, spin=None):
     """Energy and dE/dkappa_pq of a local rotation expm(K) at K = 0, one entry
     per pair: 2 (F_qp - F_pq)."""
     pairs = rotation_pairs(problem) if pairs is None else pairs
-    e, g1, g2 = reference_state(problem)
+    e, g1, g2 = reference_state(problem, spin)
     F = generalised_fock(problem, g1, g2)
     return e, np.array([2.0 * (F[q, p] - F[p, q]) for p, q in pairs])
 
@@ -108,7 +114,7 @@ def kappa_matrix(n, pairs, kappa):
     return K
 
 
-def energy_and_gradient(problem, U0, pairs, kappa):
+def energy_and_gradient(problem, U0, pairs, kappa, spin=None):
     """E(U0 expm(K(kappa))) and its exact gradient with respect to kappa: the
     energy changes by sum_ab M_ab dU_ab with M = 2 U F^T (F the generalised
     Fock matrix in the basis U), and dU = U0 L(K, dK) with L the Frechet
@@ -117,7 +123,7 @@ def energy_and_gradient(problem, U0, pairs, kappa):
     K = kappa_matrix(n, pairs, kappa)
     U = U0 @ sl.expm(K)
     pu = transform(problem, U)
-    e, g1, g2 = reference_state(pu)
+    e, g1, g2 = reference_state(pu, spin)
     F = generalised_fock(pu, g1, g2)
     M = 2.0 * U @ F.T
     grad = np.empty(len(pairs))
@@ -129,21 +135,21 @@ def energy_and_gradient(problem, U0, pairs, kappa):
     return e, grad
 
 
-def optimise(problem, U0=None, g_tol=1e-9, max_iter=2000):
+def optimise(problem, U0=None, g_tol=1e-9, max_iter=2000, spin=None):
     """CASSCF orbitals (not yet canonical): U minimising E, and E."""
     n = problem.norb
     U0 = np.eye(n) if U0 is None else U0
     pairs = rotation_pairs(problem)
     if not pairs:
-        return U0, reference_state(transform(problem, U0))[0]
-    res = so.minimize(lambda x: energy_and_gradient(problem, U0, pairs, x), np.zeros(len(pairs)), jac=True,
+        return U0, reference_state(transform(problem, U0), spin)[0]
+    res = so.minimize(lambda x: energy_and_gradient(problem, U0, pairs, x, spin), np.zeros(len(pairs)), jac=True,
                       method="BFGS", options={"gtol": g_tol, "maxiter": max_iter})
     x = res.x
     # BFGS stops where energy differences no longer resolve its line search
     # (|g| of about 1e-8); the stationarity condition g(kappa) = 0 is smooth
     # and is solved further from that minimum by Newton's method, the
     # Jacobian of the exact gradient by central differences
-    grad = lambda y: energy_and_gradient(problem, U0, pairs, y)[1]  # noqa: E731
+    grad = lambda y: energy_and_gradient(problem, U0, pairs, y, spin)[1]  # noqa: E731
     for _ in range(8):
         g = grad(x)
         if np.abs(g).max() <= g_tol:
@@ -156,15 +162,15 @@ def optimise(problem, U0=None, g_tol=1e-9, max_iter=2000):
             J[:, k] = (grad(x + d) - grad(x - d)) / (2.0 * hstep)
         x = x - np.linalg.solve(0.5 * (J + J.T), g)
     U = U0 @ sl.expm(kappa_matrix(n, pairs, x))
-    return U, float(energy_and_gradient(problem, U0, pairs, x)[0])
+    return U, float(energy_and_gradient(problem, U0, pairs, x, spin)[0])
 
 
-def canonicalise(problem, U):
+def canonicalise(problem, U, spin=None):
     """The canonical CASSCF orbitals from optimised orbitals U (see the module
     docstring)."""
     _, C, A, V = spaces(problem)
     pu = transform(problem, U)
-    _, g1, _ = reference_state(pu)
+    _, g1, _ = reference_state(pu, spin)
     f = fock(pu, g1)
     R = np.eye(problem.norb)
     for block, mat, descending in ((C, f, False), (V, f, False), (A, g1, True)):
@@ -181,8 +187,8 @@ def canonicalise(problem, U):
     return Uc
 
 
-def casscf(problem, U0=None, g_tol=1e-9):
+def casscf(problem, U0=None, g_tol=1e-9, spin=None):
     """(E_CASSCF, canonical U, the problem in the canonical CASSCF orbitals)."""
-    U, e = optimise(problem, U0, g_tol)
-    Uc = canonicalise(problem, U)
+    U, e = optimise(problem, U0, g_tol, spin=spin)
+    Uc = canonicalise(problem, U, spin)
     return e, Uc, transform(problem, Uc)

@@ -21,8 +21,10 @@ Outputs (JSON, one file per workload) next to this script:
   rdm_large.npz        CASCI energy and the active blocks of gamma and Gamma of
                        tuples with 10, 11 and 12 active orbitals
   casscf.json          canonical CASSCF orbitals of [Pi] (energy, U, h) and the
-                       full-order MBE in them, plain problem and a 7-orbital
-                       problem with a frozen orbital
+                       full-order MBE in them: plain problem, a 7-orbital
+                       problem with a frozen orbital, an open-shell 8-orbital
+                       problem, and the plain problem with the singlet
+                       reference state and singlet tuple energies
   plain_spin.json      full-order MBE of the plain 10-orbital problem with every
                        CASCI energy that of the tuple's lowest singlet
                        (spin-targeted; the problem's lowest states are often
@@ -292,18 +294,26 @@ def casscf():
     and the full-order MBE in them, for the plain problem and a 7-orbital
     problem with a frozen orbital."""
     from oracle import casscf as cs
+    from oracle import spin
     out = {}
-    for key, P in (("plain", synth.config_plain(0)),
-                   ("small7", synth.small_problem(7, 3, 3, [2, 3], nfrozen=1, nvec=6, seed=11, vec_std=0.15,
-                                                  offdiag_std=0.2))):
+    for key, P, S in (("plain", synth.config_plain(0), None),
+                      ("small7", synth.small_problem(7, 3, 3, [2, 3], nfrozen=1, nvec=6, seed=11, vec_std=0.15,
+                                                     offdiag_std=0.2), None),
+                      ("open8", synth.small_problem(8, 4, 2, [2, 3], nfrozen=1, nvec=6, seed=3, e_const=0.5), None),
+                      ("plain_singlet", synth.config_plain(0), 0.0)):
         t0 = time.time()
         # a tight orbital gradient: the tuples' energies are not stationary
         # under orbital rotations, so they follow the orbitals' accuracy
-        e, U, Pc = cs.casscf(P, g_tol=1e-11)
-        res = mbe.run(Pc, energy=lambda S: fci.casci_energy(Pc, S))
+        e, U, Pc = cs.casscf(P, g_tol=1e-11, spin=S)
+        if S is None:
+            res = mbe.run(Pc, energy=lambda T: fci.casci_energy(Pc, T))
+        else:
+            res = mbe.run(Pc, energy=lambda T: spin.casci_energy_spin(Pc, T, S))
         out[key] = mbe_json(Pc, res, {"e_casscf": e, "e_casci_start": fci.casci_energy(P, ()),
-                                      "h": Pc.h.tolist(), "U": U.tolist(), "fci": fci.fci_energy(P),
+                                      "h": Pc.h.tolist(), "U": U.tolist(), "spin": S,
+                                      "fci": fci.fci_energy(P) if S is None else None,
                                       "seconds": time.time() - t0})
+        print(key, e, time.time() - t0, flush=True)
     write("casscf.json", out)
 
 

@@ -135,3 +135,28 @@ def test_full_order_mbe_in_casscf_orbitals_is_fci():
     _, _, Pc = casscf.casscf(P)
     res = mbe.run(Pc, energy=lambda S: fci.casci_energy(Pc, S))
     assert abs(res.total - fci.fci_energy(P)) < 1e-9
+
+
+def test_spin_targeted_reference_state():
+    """With the reference state chosen by total spin (the plain problem's
+    lowest M_s = 0 state of CAS(2e,2o) is a triplet component): the gradient
+    of that state's energy equals finite differences, its optimum is
+    stationary, and it lies above the optimum of the lowest state."""
+    P = synth.config_plain(0)
+    pairs = casscf.rotation_pairs(P)
+    U0 = np.eye(P.norb)
+    rng = np.random.default_rng(3)
+    x = 0.05 * rng.standard_normal(len(pairs))
+    e, g = casscf.energy_and_gradient(P, U0, pairs, x, spin=0.0)
+    h = 1e-5
+    for k in rng.choice(len(pairs), 6, replace=False):
+        xp, xm = x.copy(), x.copy()
+        xp[k] += h
+        xm[k] -= h
+        fd = (casscf.energy_and_gradient(P, U0, pairs, xp, spin=0.0)[0] -
+              casscf.energy_and_gradient(P, U0, pairs, xm, spin=0.0)[0]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-8
+    es, _, Ps = casscf.casscf(P, spin=0.0)
+    assert np.abs(casscf.local_gradient(Ps, spin=0.0)[1]).max() < 1e-8
+    el, _, _ = casscf.casscf(P)
+    assert es > el + 1e-3
