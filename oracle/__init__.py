@@ -21,6 +21,9 @@ Full Configuration Interaction. II. Strongly Correlated Regime"):
 * ``casscf`` -- CASSCF orbitals of the reference space (the expansion
   reference of Sec. 2): BFGS over the non-redundant rotations with the exact
   gradient, then the canonical orbitals, and the integrals in them.
+* ``base``  -- base-model energies of tuples (the expansion of eps - eps_base
+  of MBE-FCI-b): second-order Rayleigh-Schroedinger energies of the tuple's
+  reference determinant, by brute force over the CAS determinants.
 
 Only ``tests/``, the smoke check of ``__graft_entry__`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
