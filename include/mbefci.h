@@ -172,6 +172,19 @@ typedef struct {
                                iteration); their P space is at most 32 determinants unless it holds
                                the whole CAS.  Above about 1225 determinants the batched path's
                                MFMA sigma is faster.  Same energies within the tolerances. */
+    int32_t base_model;     /* 0 (default): none.  1: the expansion of eps(S) - eps_base(S) with a
+                               second-order base (MBE-FCI-b, Sec. 4.2.1 and Table 3, where the base
+                               is CCSD(T)): eps_base(S) = <Phi|H|Phi> minus the second-order
+                               Rayleigh-Schroedinger sum over the single and double excitations of
+                               Phi within the tuple's CAS, Phi the determinant with the core doubly
+                               occupied and the active orbitals of index below n_alpha (n_beta)
+                               occupied by alpha (beta) electrons, H0 the diagonal of Phi's
+                               spin-orbital Fock operator.  The orders' eps are then eps - eps_base,
+                               screening acts on their increments, and the total adds the base
+                               energy of the whole space (mbefci_result_base).  EINVAL with
+                               options.gradient, and when an excitation does not raise the
+                               zeroth-order energy (an intruder: the orbitals must be ordered like
+                               canonical ones). */
 } mbefci_options;
 
 typedef struct {
@@ -332,7 +345,9 @@ mbefci_status mbefci_result_order(const mbefci_result *res, int32_t k, int64_t *
                                   const int16_t **tuples, const double **eps,
                                   const double **dinc, const int32_t **status,
                                   double *order_sum, double *wall_ms);
-double mbefci_result_total(const mbefci_result *res);       /* sum of the order sums */
+double mbefci_result_total(const mbefci_result *res);       /* sum of the order sums (plus the base
+                                                               energy of the whole space with a base model) */
+double mbefci_result_base(const mbefci_result *res);        /* base energy of the whole space (0: no base model) */
 void mbefci_result_free(mbefci_result *res);
 
 /* sigma = H c for the CAS of one tuple (E_core and E_const included, so H is
@@ -418,6 +433,13 @@ mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double 
  * of more than 12 orbitals; ENOMEM if the workspace is too small. */
 mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes, int32_t max_iter, double g_tol,
                             double *U, double *energy, int32_t *iterations);
+
+/* Base-model energies eps_base(S) of ntup tuples of one order (options.base_model
+ * describes the model; computed whatever that option is).  Host tuples as at
+ * mbefci_solve_tuples, host output energies [ntup].  EINVAL for an intruder.
+ * Order |X| with the tuple of every expansion orbital gives the whole space. */
+mbefci_status mbefci_tuple_base(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples,
+                                void *d_workspace, size_t ws_bytes, double *energies);
 
 /* The context's current Hamiltonian (host outputs, each may be null): h1
  * [n*n], (pq|rs) [n^4] in the full layout, the constant. */

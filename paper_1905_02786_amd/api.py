@@ -49,6 +49,7 @@ class Order:
 class Result:
     orders: list = field(default_factory=list)
     total: float = 0.0
+    e_base: float = 0.0   # base energy of the whole space (options.base_model)
 
     def tuple_lists(self):
         return [[tuple(int(x) for x in row) for row in o.tuples] for o in self.orders]
@@ -80,6 +81,7 @@ def _read_result(L, res) -> Result:
         st = np.frombuffer(ctypes.string_at(sp.value, 4 * m), dtype=np.int32).copy()
         out.orders.append(Order(k, tuples, eps, dinc, st, osum.value, wall.value))
     out.total = L.mbefci_result_total(res)
+    out.e_base = L.mbefci_result_base(res)
     return out
 
 
@@ -268,6 +270,15 @@ class Context:
         self._check(self.L.mbefci_casscf(self.ptr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                          int(max_iter), float(g_tol), _p(U), ctypes.byref(e), ctypes.byref(it)))
         return {"energy": e.value, "U": U, "iterations": it.value}
+
+    def tuple_base(self, order, tuples, workspace):
+        """Base-model energies eps_base of a list of tuples of one order."""
+        tl = list(tuples) if order > 0 else [()]
+        t = self._tuples(order, tl)
+        out = np.zeros(len(tl))
+        self._check(self.L.mbefci_tuple_base(self.ptr, order, len(tl), _p(t) if t.size else None,
+                                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _p(out)))
+        return out
 
     def hamiltonian(self):
         """(h [n, n], (pq|rs) [n, n, n, n], constant) of the context."""

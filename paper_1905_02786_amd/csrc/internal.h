@@ -235,6 +235,13 @@ bool whole_fits(const ParamLayout &pl, int64_t dim, int64_t Na, int64_t Nb, int 
 hipError_t launch_whole(const Batch &b, hipStream_t s);
 hipError_t init_whole_kernels();
 
+// base-model energies (base.hip): eps_base of ntup tuples, one workgroup
+// each; act/core: per tuple (stride sa, sc) the active and core orbitals,
+// nact/ncore their counts; NaN for a tuple with a non-positive denominator
+hipError_t launch_base(const double *h, const double *eri, int n, const int32_t *act, const int32_t *nact, int sa,
+                       const int32_t *core, const int32_t *ncore, int sc, int nalpha, int nbeta, double e_const,
+                       int ntup, double *out, hipStream_t s);
+
 // CASSCF expansion reference (casscf.hip)
 constexpr int kMaxOrb = 64;         // orbital limit of the library
 // h = U^T h0 U and eri = the four-index transformation of eri0 (full n^4

@@ -252,6 +252,9 @@ struct Result {
     };
     std::vector<Order> orders;
     double total = 0.0;
+    // base model (options.base_model): the orders hold eps - eps_base, and
+    // the total includes the base energy of the whole space
+    double e_base = 0.0;
     // gradient of the total formed by the forward run (options.gradient = 1):
     // dE/dh [n^2] and dE/d(pq|rs) [n^4], entries as independent variables
     bool has_grad = false;
@@ -1275,6 +1278,55 @@ double increment(const int16_t *S, int k, double eps, const std::unordered_map<u
     return eps - acc;
 }
 
+// Base-model energies eps_base(S) of nt tuples of order k (k = |X| with the
+// whole expansion space gives the base energy of the whole space): per tuple
+// the active and core orbital lists, one workgroup each (launch_base).
+mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *tuples, void *ws, size_t wsb,
+                            double *out) {
+    const int n = ctx->norb;
+    std::vector<int32_t> act((size_t)nt * n), core((size_t)nt * n), na((size_t)nt), nc((size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        std::vector<char> inA(n, 0);
+        for (int p : ctx->ref) inA[p] = 1;
+        for (int i = 0; i < k; ++i) inA[tuples[t * k + i]] = 1;
+        int a = 0, c = 0;
+        for (int p = 0; p < n; ++p) {
+            if (inA[p]) act[(size_t)t * n + a++] = p;
+            else if (p < ctx->nbeta) core[(size_t)t * n + c++] = p;
+        }
+        na[t] = a;
+        nc[t] = c;
+    }
+    Carver cv{(char *)ws, wsb};
+    int32_t *d_act = cv.take<int32_t>(act.size()), *d_core = cv.take<int32_t>(core.size());
+    int32_t *d_na = cv.take<int32_t>(na.size()), *d_nc = cv.take<int32_t>(nc.size());
+    double *d_out = cv.take<double>((size_t)nt);
+    if (!cv.ok) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the base-model energies");
+    HIPCHK(hipMemcpyAsync(d_act, act.data(), 4 * act.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_core, core.data(), 4 * core.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_na, na.data(), 4 * na.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_nc, nc.data(), 4 * nc.size(), hipMemcpyHostToDevice, ctx->stream));
+    hipError_t e = launch_base(ctx->d_h, ctx->d_eri, n, d_act, d_na, n, d_core, d_nc, n, ctx->nalpha, ctx->nbeta,
+                               ctx->e_const, (int)nt, d_out, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(out, d_out, 8 * (size_t)nt, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int64_t t = 0; t < nt; ++t)
+        if (!std::isfinite(out[t]))
+            return ctx->fail(MBEFCI_EINVAL, "base model: an excitation of the reference determinant does not raise "
+                                            "the zeroth-order energy (intruder)");
+    return MBEFCI_OK;
+}
+
+// tuple energies minus their base-model energies (after a solve)
+mbefci_status subtract_base(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *tuples, void *ws, size_t wsb, double *e) {
+    std::vector<double> b((size_t)nt);
+    mbefci_status rc = base_energies(ctx, k, nt, tuples, ws, wsb, b.data());
+    if (rc != MBEFCI_OK) return rc;
+    for (int64_t i = 0; i < nt; ++i) e[i] -= b[i];
+    return MBEFCI_OK;
+}
+
 template <class EnergyFn>
 mbefci_status run_planner(mbefci_ctx *ctx, EnergyFn energy, Result &R) {
     const int nX = (int)ctx->X.size();
@@ -1654,6 +1706,7 @@ void mbefci_default_options(mbefci_options *o) {
     o->restart_keep = 2;
     o->spin_shift = 0.0;
     o->whole_dim = kWholeDefaultDim;
+    o->base_model = 0;
 }
 
 mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
@@ -1828,6 +1881,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->restart_keep < 1 || o->restart_keep > 2) return ctx->fail(MBEFCI_EINVAL, "restart_keep must be 1 or 2");
     if (!(o->spin_shift >= 0.0) || !std::isfinite(o->spin_shift))
         return ctx->fail(MBEFCI_EINVAL, "spin_shift must be finite and >= 0");
+    if (o->base_model < 0 || o->base_model > 1) return ctx->fail(MBEFCI_EINVAL, "base_model must be 0 or 1");
     if (o->whole_dim < 0 || o->whole_dim > kWholeMaxDim)
         return ctx->fail(MBEFCI_EINVAL, "whole_dim must be in 0.." + std::to_string(kWholeMaxDim));
     ctx->opt = *o;
@@ -1904,12 +1958,25 @@ mbefci_status mbefci_run(mbefci_ctx *ctx, void *ws, size_t wsb, mbefci_result **
     const double t0 = now_ms();
     auto res = std::make_unique<mbefci_result>();
     const bool grad = ctx->opt.gradient != 0;
+    const bool base = ctx->opt.base_model != 0;
+    if (grad && base) return ctx->fail(MBEFCI_EINVAL, "the gradient is not available with a base model");
+    if (base) {
+        // the base energy of the whole space (the tuple of every expansion orbital)
+        std::vector<int16_t> all(ctx->X.begin(), ctx->X.end());
+        if ((rc = base_energies(ctx, (int)all.size(), 1, all.data(), ws, wsb, &res->r.e_base)) != MBEFCI_OK) return rc;
+    }
     if (!grad) {
         rc = run_planner(ctx,
                          [&](int k, int64_t nt, const int16_t *tup, double *e, int32_t *st) {
-                             return solve_device(ctx, k, nt, tup, ws, wsb, e, st);
+                             mbefci_status r = solve_device(ctx, k, nt, tup, ws, wsb, e, st);
+                             if (base && (r == MBEFCI_OK || r == MBEFCI_ENOCONV)) {
+                                 const mbefci_status rb = subtract_base(ctx, k, nt, tup, ws, wsb, e);
+                                 if (rb != MBEFCI_OK) return rb;
+                             }
+                             return r;
                          },
                          res->r);
+        res->r.total += res->r.e_base;
         ctx->stats.solve_ms = now_ms() - t0;
         if (rc == MBEFCI_OK || rc == MBEFCI_ENOCONV) *out = res.release();
         return rc;
@@ -2004,6 +2071,7 @@ mbefci_status mbefci_result_order(const mbefci_result *res, int32_t k, int64_t *
 }
 
 double mbefci_result_total(const mbefci_result *res) { return res ? res->r.total : 0.0; }
+double mbefci_result_base(const mbefci_result *res) { return res ? res->r.e_base : 0.0; }
 
 void mbefci_result_free(mbefci_result *res) { delete res; }
 
@@ -2395,6 +2463,21 @@ mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_i
     return MBEFCI_OK;
 }
 
+mbefci_status mbefci_tuple_base(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples, void *ws,
+                                size_t wsb, double *energies) {
+    if (!ctx || !energies || ntup < 0 || order < 0 || (order > 0 && ntup > 0 && !tuples)) return MBEFCI_EINVAL;
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    if (!ctx->ham_set || !ctx->spaces_set) return ctx->fail(MBEFCI_EINVAL, "Hamiltonian and spaces must be set");
+    for (int64_t t = 0; t < ntup; ++t)
+        for (int i = 0; i < order; ++i) {
+            const int p = tuples[t * order + i];
+            if (p < 0 || p >= ctx->norb || !ctx->inX[p] || (i > 0 && tuples[t * order + i - 1] >= p))
+                return ctx->fail(MBEFCI_EINVAL, "tuple orbitals must be ascending expansion orbitals");
+        }
+    return base_energies(ctx, order, ntup, tuples, ws, wsb, energies);
+}
+
 mbefci_status mbefci_get_hamiltonian(const mbefci_ctx *ctx, double *h1, double *eri, double *e_const) {
     if (!ctx || !ctx->ham_set) return MBEFCI_EINVAL;
     const size_t n2 = (size_t)ctx->norb * ctx->norb;
@@ -2471,6 +2554,10 @@ mbefci_status mbefci_order_solve(mbefci_ctx *ctx, mbefci_result *res, int64_t fi
     } else {
         rc = solve_device(ctx, k, count, tl.data(), ws, wsb, e.data(), st.data());
         if (rc != MBEFCI_OK && rc != MBEFCI_ENOCONV) return rc;
+        if (ctx->opt.base_model) {
+            const mbefci_status rb = subtract_base(ctx, k, count, tl.data(), ws, wsb, e.data());
+            if (rb != MBEFCI_OK) return rb;
+        }
     }
     // Eq. 3 against the completed lower orders (no tuple of the open order is
     // a subtuple of another)
@@ -2498,7 +2585,7 @@ mbefci_status mbefci_order_close(mbefci_ctx *ctx, mbefci_result *res) {
     o.sum = s;
     double tot = 0.0;
     for (auto &oo : R.orders) tot += oo.sum;
-    R.total = tot;
+    R.total = tot + R.e_base;
     R.open = false;
     R.solved.clear();
     std::unordered_map<uint64_t, double>().swap(R.dinc_map);
