@@ -91,6 +91,24 @@ def test_base_model_expansion_matches_oracle(ws, nsite, U):
     assert abs(res.total - e_fci) <= 1e-9     # full order: the base energies cancel
 
 
+def test_base_model_screened_expansion_matches_oracle(ws):
+    """With screening that removes tuples (a = 5 on the weakly coupled
+    problem) the screened increments are those of eps - eps_base: the tuple
+    lists equal the oracle's (every |dinc| lies at least 6 % from its
+    threshold), the energies agree to the parity bounds."""
+    P = synth.config_weak()
+    res = M.Context.from_problem(P, device=0, base_model=1).run(ws)
+    ref = mbe.run(P, energy=lambda S: fci.casci_energy(P, S) - base.base_energy(P, S))
+    assert len(res.orders) == len(ref.orders)
+    for o, ro in zip(res.orders, ref.orders):
+        assert [tuple(int(x) for x in t) for t in o.tuples] == [tuple(t) for t in ro.tuples] or o.k == 0
+        assert np.abs(o.eps - np.asarray(ro.eps)).max() <= 1e-10
+        assert np.abs(o.dinc - np.asarray(ro.dinc)).max() <= 1e-9
+    e_base = base.base_energy(P, base.full_space_tuple(P))
+    assert abs(res.e_base - e_base) <= 1e-11
+    assert abs(res.total - (ref.total + e_base)) <= 1e-9
+
+
 def test_base_model_streamed_last_order(ws):
     """The streamed last order subtracts the base energies too and the
     closed result equals the one-call run."""
