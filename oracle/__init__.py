@@ -24,6 +24,9 @@ Full Configuration Interaction. II. Strongly Correlated Regime"):
 * ``base``  -- base-model energies of tuples (the expansion of eps - eps_base
   of MBE-FCI-b): second-order Rayleigh-Schroedinger energies of the tuple's
   reference determinant, by brute force over the CAS determinants.
+* ``cc``    -- coupled-cluster base energies (the paper's CCSD(T) base): CCSD
+  as the projected similarity-transformed equations on the CAS determinants,
+  the (T) correction from the triply excited determinants.
 
 Only ``tests/``, the smoke check of ``__graft_entry__`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
