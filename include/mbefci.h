@@ -184,7 +184,14 @@ typedef struct {
                                energy of the whole space (mbefci_result_base).  EINVAL with
                                options.gradient, and when an excitation does not raise the
                                zeroth-order energy (an intruder: the orbitals must be ordered like
-                               canonical ones). */
+                               canonical ones).  2: the same expansion with a CCSD base, 3: with the
+                               paper's CCSD(T) base: spin-orbital CCSD on the same Phi within the
+                               tuple's CAS (any orbitals; at most 13 active orbitals per tuple), the
+                               amplitudes converged to a largest change of 1e-11 (ENOCONV after 300
+                               iterations; EINVAL when an orbital energy difference of Phi is not
+                               negative), and for 3 the (T) correction, which needs canonical
+                               orbitals (EINVAL unless the Fock operator of Phi is diagonal to
+                               1e-10 on the reference and expansion orbitals). */
 } mbefci_options;
 
 typedef struct {
@@ -434,10 +441,11 @@ mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double 
 mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes, int32_t max_iter, double g_tol,
                             double *U, double *energy, int32_t *iterations);
 
-/* Base-model energies eps_base(S) of ntup tuples of one order (options.base_model
- * describes the model; computed whatever that option is).  Host tuples as at
- * mbefci_solve_tuples, host output energies [ntup].  EINVAL for an intruder.
- * Order |X| with the tuple of every expansion orbital gives the whole space. */
+/* Base-model energies eps_base(S) of ntup tuples of one order, of the model
+ * options.base_model names (the second-order one when it is 0).  Host tuples
+ * as at mbefci_solve_tuples, host output energies [ntup].  Errors as listed at
+ * options.base_model.  Order |X| with the tuple of every expansion orbital
+ * gives the whole space. */
 mbefci_status mbefci_tuple_base(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples,
                                 void *d_workspace, size_t ws_bytes, double *energies);
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmbefci.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("strip.hip", "sigma.hip", "kernels.hip", "whole.hip", "casscf.hip", "base.hip", "mbefci.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("strip.hip", "sigma.hip", "kernels.hip", "whole.hip", "casscf.hip", "base.hip", "cc.hip", "mbefci.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -241,6 +241,16 @@ hipError_t init_whole_kernels();
 hipError_t launch_base(const double *h, const double *eri, int n, const int32_t *act, const int32_t *nact, int sa,
                        const int32_t *core, const int32_t *ncore, int sc, int nalpha, int nbeta, double e_const,
                        int ntup, double *out, hipStream_t s);
+// coupled-cluster base (cc.hip): CCSD / CCSD(T) per tuple, one workgroup each
+constexpr int kCcMaxActive = 13;        // active orbitals of a tuple
+constexpr int kCcMaxIter = 300;         // amplitude iterations
+constexpr double kCcTol = 1e-11;        // largest amplitude change at convergence
+constexpr double kCanonTol = 1e-10;     // off-diagonal Fock elements allowed with (T)
+int64_t cc_slice_doubles(int o, int v);
+hipError_t launch_ccsd(const double *h, const double *eri, int n, const int32_t *act, const int32_t *nact,
+                       const int32_t *core, const int32_t *ncore, int stride, int nalpha, int nbeta, double e_const,
+                       int ntup, double *work, int64_t slice, int triples, int max_iter, double tol, double *out,
+                       int32_t *status, hipStream_t s);
 
 // CASSCF expansion reference (casscf.hip)
 constexpr int kMaxOrb = 64;         // orbital limit of the library

@@ -1278,6 +1278,8 @@ double increment(const int16_t *S, int k, double eps, const std::unordered_map<u
     return eps - acc;
 }
 
+mbefci_status check_canonical(mbefci_ctx *ctx);
+
 // Base-model energies eps_base(S) of nt tuples of order k (k = |X| with the
 // whole expansion space gives the base energy of the whole space): per tuple
 // the active and core orbital lists, one workgroup each (launch_base).
@@ -1297,11 +1299,57 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
         na[t] = a;
         nc[t] = c;
     }
+    const int model = std::max(1, (int)ctx->opt.base_model);
     Carver cv{(char *)ws, wsb};
     int32_t *d_act = cv.take<int32_t>(act.size()), *d_core = cv.take<int32_t>(core.size());
     int32_t *d_na = cv.take<int32_t>(na.size()), *d_nc = cv.take<int32_t>(nc.size());
     double *d_out = cv.take<double>((size_t)nt);
     if (!cv.ok) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the base-model energies");
+    if (model >= 2) {
+        // coupled cluster: one workspace slice per tuple of a launch
+        int omax = 0, vmax = 0;
+        for (int64_t t = 0; t < nt; ++t) {
+            int o = 0;
+            for (int i = 0; i < na[t]; ++i) o += (act[(size_t)t * n + i] < ctx->nalpha) + (act[(size_t)t * n + i] < ctx->nbeta);
+            omax = std::max(omax, o);
+            vmax = std::max(vmax, 2 * na[t] - o);
+            if (na[t] > kCcMaxActive)
+                return ctx->fail(MBEFCI_EINVAL, "coupled-cluster base: more than 13 active orbitals in a tuple");
+        }
+        if (model == 3) {
+            const mbefci_status rc = check_canonical(ctx);
+            if (rc != MBEFCI_OK) return rc;
+        }
+        int32_t *d_st = cv.take<int32_t>((size_t)nt);
+        const int64_t slice = (cc_slice_doubles(omax, vmax) + 31) / 32 * 32;
+        const size_t room = cv.ok && cv.size - cv.off > 256 ? (cv.size - cv.off - 256) / 8 : 0;
+        const int64_t per = (int64_t)std::min<size_t>(room / (size_t)slice, 4096);
+        if (!cv.ok || per < 1) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the coupled-cluster base");
+        double *d_work = cv.take<double>((size_t)(per * slice));
+        HIPCHK(hipMemcpyAsync(d_act, act.data(), 4 * act.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(d_core, core.data(), 4 * core.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(d_na, na.data(), 4 * na.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(d_nc, nc.data(), 4 * nc.size(), hipMemcpyHostToDevice, ctx->stream));
+        for (int64_t t0 = 0; t0 < nt; t0 += per) {
+            const int cnt = (int)std::min<int64_t>(per, nt - t0);
+            hipError_t e = launch_ccsd(ctx->d_h, ctx->d_eri, n, d_act + t0 * n, d_na + t0, d_core + t0 * n, d_nc + t0, n,
+                                       ctx->nalpha, ctx->nbeta, ctx->e_const, cnt, d_work, slice, model == 3,
+                                       kCcMaxIter, kCcTol, d_out + t0, d_st + t0, ctx->stream);
+            if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        }
+        std::vector<int32_t> st((size_t)nt);
+        HIPCHK(hipMemcpyAsync(out, d_out, 8 * (size_t)nt, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(st.data(), d_st, 4 * (size_t)nt, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (int64_t t = 0; t < nt; ++t) {
+            if (st[t] == 1)
+                return ctx->fail(MBEFCI_EINVAL, "coupled-cluster base: an orbital energy difference of the reference "
+                                                "determinant is not negative (intruder)");
+            if (st[t] != 0 || !std::isfinite(out[t]))
+                return ctx->fail(MBEFCI_ENOCONV, "coupled-cluster base: the amplitude equations did not converge");
+        }
+        return MBEFCI_OK;
+    }
     HIPCHK(hipMemcpyAsync(d_act, act.data(), 4 * act.size(), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(d_core, core.data(), 4 * core.size(), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(d_na, na.data(), 4 * na.size(), hipMemcpyHostToDevice, ctx->stream));
@@ -1315,6 +1363,28 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
         if (!std::isfinite(out[t]))
             return ctx->fail(MBEFCI_EINVAL, "base model: an excitation of the reference determinant does not raise "
                                             "the zeroth-order energy (intruder)");
+    return MBEFCI_OK;
+}
+
+// The (T) correction assumes canonical orbitals: the Fock operator of the
+// reference determinant (every orbital below n_alpha / n_beta occupied: the
+// same determinant for every tuple) diagonal on the orbitals a tuple can hold.
+mbefci_status check_canonical(mbefci_ctx *ctx) {
+    const int n = ctx->norb;
+    std::vector<int> orbs(ctx->ref.begin(), ctx->ref.end());
+    orbs.insert(orbs.end(), ctx->X.begin(), ctx->X.end());
+    auto E = [&](int p, int q, int r, int s) { return ctx->eri[(((size_t)p * n + q) * n + r) * n + s]; };
+    for (int spin = 0; spin < 2; ++spin)
+        for (int p : orbs)
+            for (int q : orbs) {
+                if (p == q) continue;
+                double f = ctx->h[(size_t)p * n + q];
+                for (int k = 0; k < ctx->nalpha; ++k) f += E(p, q, k, k) - (spin == 0 ? E(p, k, k, q) : 0.0);
+                for (int k = 0; k < ctx->nbeta; ++k) f += E(p, q, k, k) - (spin == 1 ? E(p, k, k, q) : 0.0);
+                if (std::fabs(f) > kCanonTol)
+                    return ctx->fail(MBEFCI_EINVAL, "CCSD(T) base needs canonical orbitals: the Fock operator of the "
+                                                    "reference determinant is not diagonal");
+            }
     return MBEFCI_OK;
 }
 
@@ -1881,7 +1951,7 @@ mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (o->restart_keep < 1 || o->restart_keep > 2) return ctx->fail(MBEFCI_EINVAL, "restart_keep must be 1 or 2");
     if (!(o->spin_shift >= 0.0) || !std::isfinite(o->spin_shift))
         return ctx->fail(MBEFCI_EINVAL, "spin_shift must be finite and >= 0");
-    if (o->base_model < 0 || o->base_model > 1) return ctx->fail(MBEFCI_EINVAL, "base_model must be 0 or 1");
+    if (o->base_model < 0 || o->base_model > 3) return ctx->fail(MBEFCI_EINVAL, "base_model must be 0, 1, 2 or 3");
     if (o->whole_dim < 0 || o->whole_dim > kWholeMaxDim)
         return ctx->fail(MBEFCI_EINVAL, "whole_dim must be in 0.." + std::to_string(kWholeMaxDim));
     ctx->opt = *o;

@@ -155,6 +155,12 @@ def test_invalid_inputs_rejected():
             ctx.set_options(linked_rows=bad_lr)
     for lr in (0, 1, 2, 3, 4, 5):
         ctx.set_options(linked_rows=lr)
+    for bad_bm in (-1, 4):                     # base models: none, second order, CCSD, CCSD(T)
+        with pytest.raises(M.MBEFCIError):
+            ctx.set_options(base_model=bad_bm)
+    for bm in (0, 1, 2, 3):
+        ctx.set_options(base_model=bm)
+    ctx.set_options(base_model=0)
     # full-layout integrals must be 8-fold symmetric
     asym = np.zeros((4,) * 4)
     asym[0, 1, 2, 3] = 0.3
