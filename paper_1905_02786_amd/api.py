@@ -272,7 +272,9 @@ class Context:
         return {"energy": e.value, "U": U, "iterations": it.value}
 
     def tuple_base(self, order, tuples, workspace):
-        """Base-model energies eps_base of a list of tuples of one order."""
+        """Base-model energies eps_base of a list of tuples of one order, of
+        the model options.base_model names: 1 second order, 2 CCSD, 3 CCSD(T)
+        (0 gives the second-order one)."""
         tl = list(tuples) if order > 0 else [()]
         t = self._tuples(order, tl)
         out = np.zeros(len(tl))

@@ -19,7 +19,7 @@
 
 namespace mbefci {
 
-constexpr int kCcThreads = 512;
+constexpr int kCcThreads = 1024;
 constexpr int kCcDiis = 6;
 constexpr int kCcMaxSo = 2 * kCcMaxActive;   // spin-orbitals of one CAS
 
