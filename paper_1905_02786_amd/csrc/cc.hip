@@ -29,7 +29,7 @@ int64_t cc_slice_doubles(int o, int v) {
     const int64_t o2v2 = (int64_t)o * o * v * v;
     const int64_t N = o + v;
     return L * (2 + 2 * kCcDiis) + 3 * o2v2 + 2 * ((int64_t)v * v + (int64_t)o * o) + (int64_t)o * v +
-           (int64_t)o * o * o * o + (int64_t)v * v * v * v + o2v2 + N * N * N * N;
+           (int64_t)o * o * o * o + (int64_t)v * v * v * v + o2v2 + N * N * N * N + o2v2 + (int64_t)v * v * v * o;
 }
 
 __device__ __forceinline__ double block_max(double v, double *sh) {
@@ -173,6 +173,8 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
     double *Wmnij = Fme + ov, *Wabef = Wmnij + (int64_t)o * o * o * o, *Wmbej = Wabef + (int64_t)v * v * v * v;
     double *Fbe2 = Wmbej + o2v2, *Fmj2 = Fbe2 + (int64_t)v * v;   // F_be - t_m^b F_me / 2, F_mj + t_j^e F_me / 2
     double *G = Fmj2 + (int64_t)o * o;                            // <PQ||RS>, N^4
+    double *RQ = G + (int64_t)N * N * N * N;                      // ring term [i][a][j][b]
+    double *Y = RQ + o2v2;                                        // sum_m t_m^a <mb||ej>, [a][b][e][j]
     auto asy = [&](int P, int Q, int R, int S) { return G[((P * N + Q) * N + R) * N + S]; };
     auto t1 = [&](int i, int a) -> double & { return T[i * v + a]; };
     auto t2 = [&](int i, int j, int a, int b) -> double & { return T[ov + ((i * o + j) * v + a) * v + b]; };
@@ -249,8 +251,15 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 Fmj2[kk] = x;
             }
         }
-        for (int64_t k = tid; k < o4 + v4 + o2v2; k += nth) {
-            if (k < o4) {
+        const int64_t v3o = (int64_t)v * v * v * o;
+        for (int64_t k = tid; k < o4 + v4 + o2v2 + v3o; k += nth) {
+            if (k >= o4 + v4 + o2v2) {
+                const int64_t kk = k - o4 - v4 - o2v2;
+                const int j = kk % o, e = (kk / o) % v, b = (kk / o / v) % v, a = kk / o / v / v;
+                double x = 0.0;
+                for (int m = 0; m < o; ++m) x += t1(m, a) * asy(m, V0 + b, V0 + e, j);
+                Y[kk] = x;
+            } else if (k < o4) {
                 const int j = k % o, i = (k / o) % o, nn = (k / o / o) % o, m = k / o / o / o;
                 double x = asy(m, nn, i, j);
                 for (int e = 0; e < v; ++e)
@@ -282,6 +291,18 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
         }
         __syncthreads();
         auto wmbej = [&](int m, int b, int e, int j) { return Wmbej[((m * v + b) * v + e) * o + j]; };
+        // ring term before its permutations:
+        //   RQ(i,a,j,b) = sum_me t_im^ae W_mbej - sum_e t_i^e sum_m t_m^a <mb||ej>
+        for (int64_t k = tid; k < o2v2; k += nth) {
+            const int b = k % v, j = (k / v) % o, a = (k / v / o) % v, i = k / v / o / v;
+            double x = 0.0;
+            for (int m = 0; m < o; ++m)
+                for (int e = 0; e < v; ++e) x += t2(i, m, a, e) * wmbej(m, b, e, j);
+            for (int e = 0; e < v; ++e) x -= t1(i, e) * Y[((a * v + b) * v + e) * o + j];
+            RQ[k] = x;
+        }
+        __syncthreads();
+        auto rq = [&](int i, int a, int j, int b) { return RQ[((i * v + a) * o + j) * v + b]; };
         // new amplitudes
         for (int64_t k = tid; k < L; k += nth) {
             if (k < ov) {
@@ -323,13 +344,7 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                     for (int ff = 0; ff < v; ++ff)
                         x += 0.5 * tau[((i * o + j) * v + e) * v + ff] * Wabef[((a * v + b) * v + e) * v + ff];
                 // P(ij) P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
-                for (int m = 0; m < o; ++m)
-                    for (int e = 0; e < v; ++e) {
-                        x += t2(i, m, a, e) * wmbej(m, b, e, j) - t1(i, e) * t1(m, a) * asy(m, V0 + b, V0 + e, j);
-                        x -= t2(j, m, a, e) * wmbej(m, b, e, i) - t1(j, e) * t1(m, a) * asy(m, V0 + b, V0 + e, i);
-                        x -= t2(i, m, b, e) * wmbej(m, a, e, j) - t1(i, e) * t1(m, b) * asy(m, V0 + a, V0 + e, j);
-                        x += t2(j, m, b, e) * wmbej(m, a, e, i) - t1(j, e) * t1(m, b) * asy(m, V0 + a, V0 + e, i);
-                    }
+                x += rq(i, a, j, b) - rq(j, a, i, b) - rq(i, b, j, a) + rq(j, b, i, a);
                 // P(ij) sum_e t_i^e <ab||ej> - P(ab) sum_m t_m^a <mb||ij>
                 for (int e = 0; e < v; ++e)
                     x += t1(i, e) * asy(V0 + a, V0 + b, V0 + e, j) - t1(j, e) * asy(V0 + a, V0 + b, V0 + e, i);
