@@ -441,6 +441,25 @@ mbefci_status mbefci_backward(mbefci_ctx *ctx, const mbefci_result *res, double 
 mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes, int32_t max_iter, double g_tol,
                             double *U, double *energy, int32_t *iterations);
 
+/* Restricted closed-shell Hartree-Fock orbitals (the paper's expansion
+ * orbitals, Sec. 1 and 2; the reference of its CCSD(T) base, Sec. 4.2.1):
+ * the n_alpha = n_beta lowest-energy doubly occupied orbitals minimising
+ * <Phi|H|Phi> over orthonormal rotations of the context's orbitals, found by
+ * energy descent over the occupied-virtual rotations until the largest
+ * element of the orbital gradient 4 f_ai is below g_tol; then made canonical
+ * (the Fock matrix diagonal, ascending within the occupied and within the
+ * virtual block, occupied orbitals first, each column signed so that its
+ * largest entry is positive) and the context's Hamiltonian replaced by the
+ * one in them (frozen orbitals are rotated too: afterwards they are the
+ * lowest occupied HF orbitals; the reference space keeps its positions).
+ * Host outputs, each may be null: U [n*n] (row p, column j: coefficient of
+ * the entry orbital p in HF orbital j), the HF energy, the steps taken.
+ * EINVAL for an open shell, ENOCONV if g_tol is not reached in max_iter steps
+ * (the Hamiltonian is then replaced by the canonical form of the last
+ * orbitals), ENOMEM if the workspace cannot hold two n^4 arrays. */
+mbefci_status mbefci_hf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes, int32_t max_iter, double g_tol,
+                        double *U, double *energy, int32_t *iterations);
+
 /* Base-model energies eps_base(S) of ntup tuples of one order, of the model
  * options.base_model names (the second-order one when it is 0).  Host tuples
  * as at mbefci_solve_tuples, host output energies [ntup].  Errors as listed at

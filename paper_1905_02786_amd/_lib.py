@@ -85,6 +85,7 @@ SIGNATURES = [
     ("mbefci_tuple_base", c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("mbefci_result_base", c_double, [c_void_p]),
     ("mbefci_casscf", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
+    ("mbefci_hf", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
     ("mbefci_get_hamiltonian", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("mbefci_tuple_rdm", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,
                                    c_void_p]),

@@ -271,6 +271,18 @@ class Context:
                                          int(max_iter), float(g_tol), _p(U), ctypes.byref(e), ctypes.byref(it)))
         return {"energy": e.value, "U": U, "iterations": it.value}
 
+    def hf(self, workspace, max_iter: int = 2000, g_tol: float = 1e-10) -> dict:
+        """Restricted closed-shell Hartree-Fock orbitals; the context's
+        Hamiltonian is replaced by the one in the canonical HF orbitals.
+        Returns {"energy", "U" [n, n] (columns: new orbitals), "iterations"}."""
+        n = self.norb
+        U = np.zeros((n, n))
+        e = ctypes.c_double()
+        it = ctypes.c_int32()
+        self._check(self.L.mbefci_hf(self.ptr, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                     int(max_iter), float(g_tol), _p(U), ctypes.byref(e), ctypes.byref(it)))
+        return {"energy": e.value, "U": U, "iterations": it.value}
+
     def tuple_base(self, order, tuples, workspace):
         """Base-model energies eps_base of a list of tuples of one order, of
         the model options.base_model names: 1 second order, 2 CCSD, 3 CCSD(T)

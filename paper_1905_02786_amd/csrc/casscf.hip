@@ -95,6 +95,7 @@ __global__ __launch_bounds__(256) void k_fock(const double *h, const double *eri
             if (g != 0.0) fv += g * (eri[p * n3 + q * n2 + r * n + s] - 0.5 * eri[p * n3 + r * n2 + s * n + q]);
         }
     f[idx] = fv;
+    if (!g2h) return;   // the Fock matrix alone
     // generalised Fock matrix (zero rows without density)
     bool has = false;
     for (int i = 0; i < no; ++i) has |= occ[i] == p;

@@ -2533,6 +2533,194 @@ mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_i
     return MBEFCI_OK;
 }
 
+// Restricted closed-shell Hartree-Fock orbitals (the paper's expansion
+// orbitals, Sec. 1 and 2, and the reference of its CCSD(T) base, Sec. 4.2.1).
+// Energy descent over the occupied-virtual rotations C <- C exp(K): the
+// gradient in the current orbitals is 4 f_ai, f the closed-shell Fock matrix
+// of D = C_occ C_occ^T (built on the device from the starting integrals);
+// limited-memory BFGS steps (8 pairs, in the frame of the current orbitals)
+// on the diagonal Hessian estimate 4 (f_aa - f_ii) floored at 0.05, at most
+// 0.5 per element, halved until the energy does not rise, taken as they are
+// once the gradient is below 1e-5 (the energy no longer resolves the step).
+// Then the Fock matrix diagonalised in the occupied and the virtual block,
+// each ascending, occupied orbitals first; every column signed so that its
+// largest entry is positive; the context's Hamiltonian replaced by the one in
+// these orbitals.
+mbefci_status mbefci_hf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_iter, double g_tol, double *U_out,
+                        double *e_out, int32_t *iter_out) {
+    if (!ctx) return MBEFCI_EINVAL;
+    mbefci_status rc = check_device(ctx);
+    if (rc != MBEFCI_OK) return rc;
+    if (!ctx->ham_set || !ctx->spaces_set) return ctx->fail(MBEFCI_EINVAL, "Hamiltonian and spaces must be set");
+    if (max_iter < 1 || !(g_tol > 0.0)) return ctx->fail(MBEFCI_EINVAL, "max_iter >= 1 and g_tol > 0 required");
+    if (ctx->nalpha != ctx->nbeta) return ctx->fail(MBEFCI_EINVAL, "Hartree-Fock orbitals need a closed shell");
+    const double t0 = now_ms();
+    const int n = ctx->norb, no = ctx->nalpha, nv = n - no;
+    const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+    Carver cv{(char *)ws, wsb};
+    double *d_eri0 = cv.take<double>(n4), *d_tmp = cv.take<double>(n4), *d_h0 = cv.take<double>(n2);
+    double *d_U = cv.take<double>(n2), *d_f = cv.take<double>(n2), *d_g1 = cv.take<double>(n2);
+    int32_t *d_all = cv.take<int32_t>((size_t)n);
+    if (!cv.ok) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the Hartree-Fock orbitals");
+    std::vector<int32_t> all(n);
+    for (int p = 0; p < n; ++p) all[p] = p;
+    const Mat h0 = ctx->h;
+    HIPCHK(hipMemcpyAsync(d_eri0, ctx->eri.data(), 8 * n4, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_h0, ctx->h.data(), 8 * n2, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(d_all, all.data(), 4 * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+    // energy and the Fock matrix in the orbitals C (columns; row-major n x n)
+    Mat g1(n2), fao(n2);
+    auto evaluate = [&](const Mat &C, double &E, Mat &Fm) -> mbefci_status {
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) {
+                double d = 0.0;
+                for (int i = 0; i < no; ++i) d += C[(size_t)p * n + i] * C[(size_t)q * n + i];
+                g1[(size_t)p * n + q] = 2.0 * d;
+            }
+        HIPCHK(hipMemcpyAsync(d_g1, g1.data(), 8 * n2, hipMemcpyHostToDevice, ctx->stream));
+        hipError_t e = launch_fock(d_h0, d_eri0, d_g1, nullptr, d_all, n, n, d_f, d_f, ctx->stream);
+        if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+        HIPCHK(hipMemcpyAsync(fao.data(), d_f, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        E = ctx->e_const;
+        for (size_t k = 0; k < n2; ++k) E += 0.5 * g1[k] * (h0[k] + fao[k]);
+        Mat T = mat_mul(fao, C, n), Ct(n2);
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) Ct[(size_t)q * n + p] = C[(size_t)p * n + q];
+        Fm = mat_mul(Ct, T, n);
+        return MBEFCI_OK;
+    };
+    // start: the eigenvectors of h, ascending
+    Mat C;
+    {
+        std::vector<double> w;
+        sym_eig(h0, n, false, w, C);
+    }
+    double E = 0.0;
+    Mat Fm;
+    if ((rc = evaluate(C, E, Fm)) != MBEFCI_OK) return rc;
+    const int np = no * nv;
+    auto grad = [&](const Mat &F) {
+        std::vector<double> g((size_t)np);
+        for (int a = 0; a < nv; ++a)
+            for (int i = 0; i < no; ++i) g[(size_t)a * no + i] = 4.0 * F[(size_t)(no + a) * n + i];
+        return g;
+    };
+    std::vector<double> g = grad(Fm), g_old, step_old;
+    std::vector<std::vector<double>> Ss, Ys;
+    auto dot = [](const std::vector<double> &x, const std::vector<double> &y) {
+        double s = 0.0;
+        for (size_t k = 0; k < x.size(); ++k) s += x[k] * y[k];
+        return s;
+    };
+    double gmax = 0.0;
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        gmax = 0.0;
+        for (double x : g) gmax = std::max(gmax, std::fabs(x));
+        if (gmax < g_tol || np == 0) break;
+        if (!g_old.empty()) {
+            std::vector<double> y(np);
+            for (int k = 0; k < np; ++k) y[k] = g[k] - g_old[k];
+            if (dot(step_old, y) > 1e-16) {
+                Ss.push_back(step_old);
+                Ys.push_back(y);
+                if (Ss.size() > 8) {
+                    Ss.erase(Ss.begin());
+                    Ys.erase(Ys.begin());
+                }
+            }
+        }
+        std::vector<double> hd(np), q = g, al;
+        for (int a = 0; a < nv; ++a)
+            for (int i = 0; i < no; ++i)
+                hd[(size_t)a * no + i] =
+                    std::max(4.0 * (Fm[(size_t)(no + a) * n + no + a] - Fm[(size_t)i * n + i]), 0.05);
+        for (int k = (int)Ss.size() - 1; k >= 0; --k) {
+            const double a = dot(Ss[k], q) / dot(Ss[k], Ys[k]);
+            al.push_back(a);
+            for (int j = 0; j < np; ++j) q[j] -= a * Ys[k][j];
+        }
+        for (int j = 0; j < np; ++j) q[j] /= hd[j];
+        for (size_t k = 0; k < Ss.size(); ++k) {
+            const double b = dot(Ys[k], q) / dot(Ss[k], Ys[k]);
+            const double a = al[Ss.size() - 1 - k];
+            for (int j = 0; j < np; ++j) q[j] += (a - b) * Ss[k][j];
+        }
+        std::vector<double> step(np);
+        for (int j = 0; j < np; ++j) step[j] = -q[j];
+        if (dot(step, g) >= 0.0) {   // not a descent direction: the preconditioned gradient
+            for (int j = 0; j < np; ++j) step[j] = -g[j] / hd[j];
+            Ss.clear();
+            Ys.clear();
+        }
+        for (double &x : step) x = std::min(0.5, std::max(-0.5, x));
+        double alpha = 1.0, En = 0.0;
+        Mat Cn, Fn;
+        for (;;) {
+            Mat K(n2, 0.0);
+            for (int a = 0; a < nv; ++a)
+                for (int i = 0; i < no; ++i) {
+                    const double k = alpha * step[(size_t)a * no + i];
+                    K[(size_t)(no + a) * n + i] = k;
+                    K[(size_t)i * n + no + a] = -k;
+                }
+            Cn = mat_mul(C, mat_exp(K, n), n);
+            if ((rc = evaluate(Cn, En, Fn)) != MBEFCI_OK) return rc;
+            if (En <= E + 1e-13 * std::max(1.0, std::fabs(E)) || alpha < 1e-6 || gmax < 1e-5) break;
+            alpha *= 0.5;
+        }
+        g_old = g;
+        step_old = step;
+        for (double &x : step_old) x *= alpha;
+        C.swap(Cn);
+        Fm.swap(Fn);
+        E = En;
+        g = grad(Fm);
+    }
+    // canonical orbitals
+    Mat R(n2, 0.0);
+    auto block = [&](int b0, int m) {
+        if (m == 0) return;
+        Mat S((size_t)m * m), Vb;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                S[(size_t)i * m + j] = 0.5 * (Fm[(size_t)(b0 + i) * n + b0 + j] + Fm[(size_t)(b0 + j) * n + b0 + i]);
+        std::vector<double> w;
+        sym_eig(S, m, false, w, Vb);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) R[(size_t)(b0 + i) * n + b0 + j] = Vb[(size_t)i * m + j];
+    };
+    block(0, no);
+    block(no, nv);
+    Mat Uc = mat_mul(C, R, n);
+    for (int j = 0; j < n; ++j) {
+        int im = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::fabs(Uc[(size_t)i * n + j]) > std::fabs(Uc[(size_t)im * n + j])) im = i;
+        if (Uc[(size_t)im * n + j] < 0.0)
+            for (int i = 0; i < n; ++i) Uc[(size_t)i * n + j] = -Uc[(size_t)i * n + j];
+    }
+    HIPCHK(hipMemcpyAsync(d_U, Uc.data(), 8 * n2, hipMemcpyHostToDevice, ctx->stream));
+    hipError_t e = launch_rotate_integrals(d_h0, d_eri0, d_U, ctx->d_h, ctx->d_eri, d_tmp, n, ctx->stream);
+    if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
+    HIPCHK(hipMemcpyAsync(ctx->h.data(), ctx->d_h, 8 * n2, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->eri.data(), ctx->d_eri, 8 * n4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int p = 0; p < n; ++p)   // exact symmetry of h (rounding of the two products)
+        for (int q = 0; q < p; ++q) {
+            const double v = 0.5 * (ctx->h[(size_t)p * n + q] + ctx->h[(size_t)q * n + p]);
+            ctx->h[(size_t)p * n + q] = ctx->h[(size_t)q * n + p] = v;
+        }
+    HIPCHK(hipMemcpy(ctx->d_h, ctx->h.data(), 8 * n2, hipMemcpyHostToDevice));
+    if (U_out) std::memcpy(U_out, Uc.data(), 8 * n2);
+    if (e_out) *e_out = E;
+    if (iter_out) *iter_out = it;
+    ctx->stats.solve_ms = now_ms() - t0;
+    if (gmax >= g_tol && np > 0) return ctx->fail(MBEFCI_ENOCONV, "orbital gradient above g_tol after max_iter");
+    return MBEFCI_OK;
+}
+
 mbefci_status mbefci_tuple_base(mbefci_ctx *ctx, int32_t order, int64_t ntup, const int16_t *tuples, void *ws,
                                 size_t wsb, double *energies) {
     if (!ctx || !energies || ntup < 0 || order < 0 || (order > 0 && ntup > 0 && !tuples)) return MBEFCI_EINVAL;
