@@ -11,8 +11,8 @@ minimise
     f(D)_pq = h_pq + sum_rs D_rs (2 (pq|rs) - (pr|sq)),
 
 found by energy descent over the occupied-virtual orbital rotations (the
-plain Roothaan iteration oscillates on these synthetic problems) until the
-orbital gradient 4 f_ai is below 1e-10.  Canonical form: the Fock operator
+plain Roothaan iteration oscillates on these synthetic problems), finished by
+Newton steps, until the orbital gradient 4 f_ai is below 1e-10.  Canonical form: the Fock operator
 diagonalised in the occupied and in the virtual block, each ascending
 (occupied orbitals first), each orbital signed so that its largest entry is
 positive; the problem in them has h' = C^T h C and
@@ -50,6 +50,27 @@ def _occ_virt_fock(problem, C):
     return D, C.T @ fock(problem, D) @ C
 
 
+def _rotate(C, x, no):
+    n = C.shape[0]
+    K = np.zeros((n, n))
+    K[no:, :no] = x.reshape(n - no, no)
+    return C @ scipy.linalg.expm(K - K.T)
+
+
+def _hessian(problem, C, s: float = 1e-4):
+    """Orbital Hessian by central differences of the gradient 4 f_ai."""
+    no = problem.nalpha
+    npar = (problem.norb - no) * no
+    H = np.zeros((npar, npar))
+    for k in range(npar):
+        x = np.zeros(npar)
+        x[k] = s
+        gp = 4.0 * _occ_virt_fock(problem, _rotate(C, x, no))[1][no:, :no]
+        gm = 4.0 * _occ_virt_fock(problem, _rotate(C, -x, no))[1][no:, :no]
+        H[:, k] = (gp - gm).ravel() / (2.0 * s)
+    return 0.5 * (H + H.T)
+
+
 def rhf(problem, tol: float = 1e-10, max_iter: int = 3000):
     """(E_HF, C, eps): canonical RHF orbitals as the columns of C (occupied
     first), eps the Fock diagonal in them.  Energy descent over the
@@ -57,9 +78,10 @@ def rhf(problem, tol: float = 1e-10, max_iter: int = 3000):
     gradient at kappa = 0 is 4 f_ai in the current orbitals; steps from
     limited-memory BFGS (8 pairs, in the frame of the current orbitals)
     preconditioned by 4 (f_aa - f_ii) floored at 0.05, at most 0.5 per
-    element, halved until the energy does not rise (once the gradient is
-    below 1e-5 the step is taken as it is).  Stops when the largest gradient
-    element is below tol."""
+    element, halved until the energy does not rise; once the gradient is
+    below 1e-5, Newton steps on the Hessian from central differences of the
+    gradient (at most six; quasi-Newton converges slowly there).  Stops when
+    the largest gradient element is below tol."""
     if problem.nalpha != problem.nbeta:
         raise ValueError("RHF needs a closed-shell problem")
     n, no = problem.norb, problem.nalpha
@@ -69,10 +91,25 @@ def rhf(problem, tol: float = 1e-10, max_iter: int = 3000):
     S, Y = [], []
     g_old = None
     step_old = None
+    newton = 0
     for _ in range(max_iter):
         g = 4.0 * Fm[no:, :no]
         if np.abs(g).max() < tol:
             break
+        if np.abs(g).max() < 1e-5 and newton < 6:
+            # Newton step on the Hessian from central differences of the gradient
+            H = _hessian(problem, C)
+            try:
+                L = np.linalg.cholesky(H)
+                x = -scipy.linalg.cho_solve((L, True), g.ravel())
+                C = _rotate(C, x, no)
+                D, Fm = _occ_virt_fock(problem, C)
+                E = energy(problem, D)
+                newton += 1
+                S, Y, g_old = [], [], None
+                continue
+            except np.linalg.LinAlgError:
+                newton = 6                        # not positive definite: keep descending
         if g_old is not None:
             y = (g - g_old).ravel()
             s_ = step_old.ravel()

@@ -2540,8 +2540,9 @@ mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_i
 // of D = C_occ C_occ^T (built on the device from the starting integrals);
 // limited-memory BFGS steps (8 pairs, in the frame of the current orbitals)
 // on the diagonal Hessian estimate 4 (f_aa - f_ii) floored at 0.05, at most
-// 0.5 per element, halved until the energy does not rise, taken as they are
-// once the gradient is below 1e-5 (the energy no longer resolves the step).
+// 0.5 per element, halved until the energy does not rise; once the gradient
+// is below 1e-5, Newton steps on the Hessian from central differences of the
+// gradient (at most six; the quasi-Newton steps converge slowly there).
 // Then the Fock matrix diagonalised in the occupied and the virtual block,
 // each ascending, occupied orbitals first; every column signed so that its
 // largest entry is positive; the context's Hamiltonian replaced by the one in
@@ -2613,12 +2614,85 @@ mbefci_status mbefci_hf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_iter,
         for (size_t k = 0; k < x.size(); ++k) s += x[k] * y[k];
         return s;
     };
+    // C exp(K(x)) for rotation parameters x[a * no + i]
+    auto rotate = [&](const Mat &Cx, const std::vector<double> &x) {
+        Mat K(n2, 0.0);
+        for (int a = 0; a < nv; ++a)
+            for (int i = 0; i < no; ++i) {
+                K[(size_t)(no + a) * n + i] = x[(size_t)a * no + i];
+                K[(size_t)i * n + no + a] = -x[(size_t)a * no + i];
+            }
+        return mat_mul(Cx, mat_exp(K, n), n);
+    };
+    // Newton step on the Hessian from central differences of the gradient;
+    // ok = false (and nothing changed) when that Hessian is not positive definite
+    auto newton_step = [&](bool &ok) -> mbefci_status {
+        const double hs = 1e-4;
+        std::vector<double> H((size_t)np * np), x(np, 0.0);
+        for (int kk = 0; kk < np; ++kk) {
+            double Ep, Em;
+            Mat Fp, Fmn;
+            x[kk] = hs;
+            if ((rc = evaluate(rotate(C, x), Ep, Fp)) != MBEFCI_OK) return rc;
+            x[kk] = -hs;
+            if ((rc = evaluate(rotate(C, x), Em, Fmn)) != MBEFCI_OK) return rc;
+            x[kk] = 0.0;
+            const std::vector<double> gp = grad(Fp), gm = grad(Fmn);
+            for (int j = 0; j < np; ++j) H[(size_t)j * np + kk] = (gp[j] - gm[j]) / (2.0 * hs);
+        }
+        // symmetrise into the lower triangle, then Cholesky H = L L^T in place
+        for (int a = 0; a < np; ++a)
+            for (int b = 0; b < a; ++b) H[(size_t)a * np + b] = 0.5 * (H[(size_t)a * np + b] + H[(size_t)b * np + a]);
+        for (int j = 0; j < np; ++j) {
+            double d = H[(size_t)j * np + j];
+            for (int q = 0; q < j; ++q) d -= H[(size_t)j * np + q] * H[(size_t)j * np + q];
+            if (!(d > 0.0)) {
+                ok = false;
+                return MBEFCI_OK;
+            }
+            d = std::sqrt(d);
+            H[(size_t)j * np + j] = d;
+            for (int r = j + 1; r < np; ++r) {
+                double v = H[(size_t)r * np + j];
+                for (int q = 0; q < j; ++q) v -= H[(size_t)r * np + q] * H[(size_t)j * np + q];
+                H[(size_t)r * np + j] = v / d;
+            }
+        }
+        std::vector<double> y(np);
+        for (int r = 0; r < np; ++r) {   // L y = -g, then L^T x = y
+            double v = -g[r];
+            for (int q = 0; q < r; ++q) v -= H[(size_t)r * np + q] * y[q];
+            y[r] = v / H[(size_t)r * np + r];
+        }
+        for (int r = np - 1; r >= 0; --r) {
+            double v = y[r];
+            for (int q = r + 1; q < np; ++q) v -= H[(size_t)q * np + r] * x[q];
+            x[r] = v / H[(size_t)r * np + r];
+        }
+        C = rotate(C, x);
+        if ((rc = evaluate(C, E, Fm)) != MBEFCI_OK) return rc;
+        ok = true;
+        return MBEFCI_OK;
+    };
     double gmax = 0.0;
-    int it = 0;
+    int it = 0, newton = 0;
     for (; it < max_iter; ++it) {
         gmax = 0.0;
         for (double x : g) gmax = std::max(gmax, std::fabs(x));
         if (gmax < g_tol || np == 0) break;
+        if (gmax < 1e-5 && newton < 6) {   // quasi-Newton converges slowly here
+            bool ok = false;
+            if ((rc = newton_step(ok)) != MBEFCI_OK) return rc;
+            if (ok) {
+                ++newton;
+                g = grad(Fm);
+                g_old.clear();
+                Ss.clear();
+                Ys.clear();
+                continue;
+            }
+            newton = 6;   // not positive definite: keep descending
+        }
         if (!g_old.empty()) {
             std::vector<double> y(np);
             for (int k = 0; k < np; ++k) y[k] = g[k] - g_old[k];
