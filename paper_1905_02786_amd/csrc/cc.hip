@@ -17,6 +17,8 @@
 // and the DIIS history live in a slice of the workspace per tuple.
 #include "device.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 namespace mbefci {
 
 constexpr int kCcThreads = 1024;
@@ -58,10 +60,23 @@ struct CcArgs {
     double tol;            // on the largest amplitude change
     double *out;           // energies (NaN on failure)
     int32_t *status;       // 0 ok, 1 non-negative denominator, 2 not converged
+    int wgs;               // workgroups per tuple
+    double *part;          // [2][wgs] reduction partials (wgs > 1)
 };
 
 __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
-    const int t = blockIdx.x, tid = threadIdx.x, nth = kCcThreads;
+    // A.wgs workgroups per tuple (more than one: a cooperative launch of one
+    // tuple, the workgroups joined by grid barriers)
+    const int t = blockIdx.x / A.wgs, rk = blockIdx.x % A.wgs, tid = threadIdx.x, nth = kCcThreads;
+    const int64_t gid = (int64_t)rk * nth + tid, gst = (int64_t)A.wgs * nth;
+    auto gsync = [&]() {
+        if (A.wgs > 1) {
+            __threadfence();
+            cooperative_groups::this_grid().sync();
+        } else {
+            __syncthreads();
+        }
+    };
     const int n = A.n, nA = A.nact[t], nC = A.ncore[t];
     const int32_t *act = A.act + (int64_t)t * A.stride, *core = A.core + (int64_t)t * A.stride;
     const double *eri = A.eri, *h = A.h;
@@ -74,6 +89,20 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
     __shared__ double sh[16];
     __shared__ double B[kCcDiis + 1][kCcDiis + 1], coef[kCcDiis + 1];
     __shared__ int no_sh, nv_sh, bad_sh;
+    // sum (or max) over the tuple's threads in a fixed order: workgroup sums,
+    // then, across workgroups, their partials in two alternating slots
+    int red_cnt = 0;
+    auto grid_red = [&](double x, bool mx) -> double {
+        const double w = mx ? block_max(x, sh) : block_sum(x, sh);
+        if (A.wgs == 1) return w;
+        double *pp = A.part + (size_t)(red_cnt & 1) * A.wgs;
+        ++red_cnt;
+        if (tid == 0) pp[rk] = w;
+        gsync();
+        double r = 0.0;
+        for (int q = 0; q < A.wgs; ++q) r = mx ? fmax(r, pp[q]) : r + pp[q];
+        return r;
+    };
     if (tid == 0) {
         int o = 0;
         for (int s = 0; s < 2; ++s)
@@ -154,7 +183,7 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
         if (so_spin[k / v] == so_spin[o + k % v] && !(f[k / v][k / v] - f[o + k % v][o + k % v] < 0.0)) bad_sh = 1;
     __syncthreads();
     if (bad_sh) {
-        if (tid == 0) {
+        if (tid == 0 && rk == 0) {
             A.out[t] = __builtin_nan("");
             A.status[t] = 1;
         }
@@ -181,30 +210,30 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
     auto iovv = [&](int m, int n_, int e, int f_) { return Ioovv[((m * o + n_) * v + e) * v + f_]; };
     const int V0 = o;   // spin-orbital index of virtual 0
 
-    for (int64_t k = tid; k < L; k += nth) T[k] = 0.0;
+    for (int64_t k = gid; k < L; k += gst) T[k] = 0.0;
     const int64_t N4 = (int64_t)N * N * N * N;
-    for (int64_t k = tid; k < N4; k += nth)
+    for (int64_t k = gid; k < N4; k += gst)
         G[k] = asy_raw((int)(k / N / N / N), (int)(k / N / N % N), (int)(k / N % N), (int)(k % N));
-    __syncthreads();
-    for (int64_t k = tid; k < o2v2; k += nth) {
+    gsync();
+    for (int64_t k = gid; k < o2v2; k += gst) {
         const int b = k % v, a = (k / v) % v, j = (k / v / v) % o, i = k / v / v / o;
         Ioovv[k] = asy(i, j, V0 + a, V0 + b);
     }
-    __syncthreads();
+    gsync();
 
     double e_cc = 0.0, e_old = 0.0;
     int it = 0, nh = 0, conv = 0;
     for (; it < A.max_iter && L > 0; ++it) {
         // tau, tau~
-        for (int64_t k = tid; k < o2v2; k += nth) {
+        for (int64_t k = gid; k < o2v2; k += gst) {
             const int b = k % v, a = (k / v) % v, j = (k / v / v) % o, i = k / v / v / o;
             const double x = t1(i, a) * t1(j, b) - t1(i, b) * t1(j, a);
             tau[k] = T[ov + k] + x;
             taut[k] = T[ov + k] + 0.5 * x;
         }
-        __syncthreads();
+        gsync();
         // one-body intermediates
-        for (int k = tid; k < v * v + o * o + o * v; k += nth) {
+        for (int k = (int)gid; k < v * v + o * o + o * v; k += (int)gst) {
             if (k < v * v) {
                 const int a = k / v, e = k % v;
                 double x = (a != e) ? f[V0 + a][V0 + e] : 0.0;
@@ -235,10 +264,10 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 Fme[kk] = x;
             }
         }
-        __syncthreads();
+        gsync();
         // two-body intermediates, and the one-body ones dressed for the T2 equation
         const int64_t o4 = (int64_t)o * o * o * o, v4 = (int64_t)v * v * v * v;
-        for (int k = tid; k < v * v + o * o; k += nth) {
+        for (int k = (int)gid; k < v * v + o * o; k += (int)gst) {
             if (k < v * v) {
                 const int b = k / v, e = k % v;
                 double x = Fae[k];
@@ -252,7 +281,7 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             }
         }
         const int64_t v3o = (int64_t)v * v * v * o;
-        for (int64_t k = tid; k < o4 + v4 + o2v2 + v3o; k += nth) {
+        for (int64_t k = gid; k < o4 + v4 + o2v2 + v3o; k += gst) {
             if (k >= o4 + v4 + o2v2) {
                 const int64_t kk = k - o4 - v4 - o2v2;
                 const int j = kk % o, e = (kk / o) % v, b = (kk / o / v) % v, a = kk / o / v / v;
@@ -289,11 +318,11 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 Wmbej[kk] = x;
             }
         }
-        __syncthreads();
+        gsync();
         auto wmbej = [&](int m, int b, int e, int j) { return Wmbej[((m * v + b) * v + e) * o + j]; };
         // ring term before its permutations:
         //   RQ(i,a,j,b) = sum_me t_im^ae W_mbej - sum_e t_i^e sum_m t_m^a <mb||ej>
-        for (int64_t k = tid; k < o2v2; k += nth) {
+        for (int64_t k = gid; k < o2v2; k += gst) {
             const int b = k % v, j = (k / v) % o, a = (k / v / o) % v, i = k / v / o / v;
             double x = 0.0;
             for (int m = 0; m < o; ++m)
@@ -301,10 +330,10 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             for (int e = 0; e < v; ++e) x -= t1(i, e) * Y[((a * v + b) * v + e) * o + j];
             RQ[k] = x;
         }
-        __syncthreads();
+        gsync();
         auto rq = [&](int i, int a, int j, int b) { return RQ[((i * v + a) * o + j) * v + b]; };
         // new amplitudes
-        for (int64_t k = tid; k < L; k += nth) {
+        for (int64_t k = gid; k < L; k += gst) {
             if (k < ov) {
                 const int i = k / v, a = k % v;
                 if (so_spin[i] != so_spin[V0 + a]) {   // spin-forbidden: stays zero
@@ -353,22 +382,22 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 Tn[k] = x / (f[i][i] + f[j][j] - f[V0 + a][V0 + a] - f[V0 + b][V0 + b]);
             }
         }
-        __syncthreads();
+        gsync();
         // DIIS: store the update and its change, extrapolate
         const int slot = it % kCcDiis;
         double dmax = 0.0;
-        for (int64_t k = tid; k < L; k += nth) {
+        for (int64_t k = gid; k < L; k += gst) {
             const double d = Tn[k] - T[k];
             Hist[slot * L + k] = Tn[k];
             Err[slot * L + k] = d;
             dmax = fmax(dmax, fabs(d));
         }
-        dmax = block_max(dmax, sh);
+        dmax = grid_red(dmax, true);
         nh = nh < kCcDiis ? nh + 1 : kCcDiis;
         for (int q = 0; q < nh; ++q) {
             double d = 0.0;
-            for (int64_t k = tid; k < L; k += nth) d += Err[slot * L + k] * Err[q * L + k];
-            d = block_sum(d, sh);
+            for (int64_t k = gid; k < L; k += gst) d += Err[slot * L + k] * Err[q * L + k];
+            d = grid_red(d, false);
             if (tid == 0) {
                 B[slot][q] = d;
                 B[q][slot] = d;
@@ -419,20 +448,20 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             }
         }
         __syncthreads();
-        for (int64_t k = tid; k < L; k += nth) {
+        for (int64_t k = gid; k < L; k += gst) {
             double x = 0.0;
             for (int q = 0; q < nh; ++q) x += coef[q] * Hist[q * L + k];
             T[k] = x;
         }
-        __syncthreads();
+        gsync();
         // correlation energy
         double e = 0.0;
-        for (int64_t k = tid; k < o2v2; k += nth) {
+        for (int64_t k = gid; k < o2v2; k += gst) {
             const int b = k % v, a = (k / v) % v, j = (k / v / v) % o, i = k / v / v / o;
             e += Ioovv[k] * (0.25 * T[ov + k] + 0.5 * t1(i, a) * t1(j, b));
         }
-        for (int64_t k = tid; k < ov; k += nth) e += f[k / v][V0 + k % v] * T[k];
-        e_cc = block_sum(e, sh);
+        for (int64_t k = gid; k < ov; k += gst) e += f[k / v][V0 + k % v] * T[k];
+        e_cc = grid_red(e, false);
         __syncthreads();
         if (dmax < A.tol && fabs(e_cc - e_old) < 1e-2 * A.tol) {
             conv = 1;
@@ -459,7 +488,7 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             }
             z = y + 1 + (int)r;
         };
-        for (int64_t k = tid; k < nocc3 * nvir3; k += nth) {
+        for (int64_t k = gid; k < nocc3 * nvir3; k += gst) {
             int i, j, kk, a, b, c;
             unrank3(k / nvir3, o, i, j, kk);
             unrank3(k % nvir3, v, a, b, c);
@@ -484,9 +513,9 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             const double D = f[i][i] + f[j][j] + f[kk][kk] - f[V0 + a][V0 + a] - f[V0 + b][V0 + b] - f[V0 + c][V0 + c];
             e_t += x * (x + y) / D;
         }
-        e_t = block_sum(e_t, sh);
+        e_t = grid_red(e_t, false);
     }
-    if (tid == 0) {
+    if (tid == 0 && rk == 0) {
         A.out[t] = conv ? A.e_const + eref + e_cc + e_t : __builtin_nan("");
         A.status[t] = conv ? 0 : 2;
     }
@@ -498,9 +527,30 @@ hipError_t launch_ccsd(const double *h, const double *eri, int n, const int32_t 
                        int32_t *status, hipStream_t s) {
     if (ntup <= 0) return hipSuccess;
     CcArgs a{h, eri, n, act, nact, core, ncore, stride, nalpha, nbeta, e_const, work, slice, triples, max_iter, tol,
-             out, status};
+             out, status, 1, nullptr};
     hipLaunchKernelGGL(k_ccsd, dim3(ntup), dim3(kCcThreads), 0, s, a);
     return hipGetLastError();
+}
+
+// Workgroups that can run one tuple cooperatively (all resident at once).
+int ccsd_coop_wgs() {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_ccsd, kCcThreads, 0) != hipSuccess) return 1;
+    return std::max(1, std::min(cus * per, kCcMaxWgs));
+}
+
+// One tuple on wgs workgroups in a cooperative launch (grid barriers between
+// the phases); part holds 2 wgs doubles.
+hipError_t launch_ccsd_coop(const double *h, const double *eri, int n, const int32_t *act, const int32_t *nact,
+                            const int32_t *core, const int32_t *ncore, int stride, int nalpha, int nbeta,
+                            double e_const, double *work, int64_t slice, int triples, int max_iter, double tol,
+                            double *out, int32_t *status, int wgs, double *part, hipStream_t s) {
+    CcArgs a{h, eri, n, act, nact, core, ncore, stride, nalpha, nbeta, e_const, work, slice, triples, max_iter, tol,
+             out, status, wgs, part};
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel((const void *)k_ccsd, dim3(wgs), dim3(kCcThreads), args, 0, s);
 }
 
 }  // namespace mbefci

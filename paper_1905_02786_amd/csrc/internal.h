@@ -246,7 +246,14 @@ constexpr int kCcMaxActive = 13;        // active orbitals of a tuple
 constexpr int kCcMaxIter = 300;         // amplitude iterations
 constexpr double kCcTol = 1e-11;        // largest amplitude change at convergence
 constexpr double kCanonTol = 1e-10;     // off-diagonal Fock elements allowed with (T)
+constexpr int kCcCoopActive = 10;       // tuples of at least this many active orbitals: one cooperative launch each
+constexpr int kCcMaxWgs = 256;          // workgroups of such a launch
 int64_t cc_slice_doubles(int o, int v);
+int ccsd_coop_wgs();
+hipError_t launch_ccsd_coop(const double *h, const double *eri, int n, const int32_t *act, const int32_t *nact,
+                            const int32_t *core, const int32_t *ncore, int stride, int nalpha, int nbeta,
+                            double e_const, double *work, int64_t slice, int triples, int max_iter, double tol,
+                            double *out, int32_t *status, int wgs, double *part, hipStream_t s);
 hipError_t launch_ccsd(const double *h, const double *eri, int n, const int32_t *act, const int32_t *nact,
                        const int32_t *core, const int32_t *ncore, int stride, int nalpha, int nbeta, double e_const,
                        int ntup, double *work, int64_t slice, int triples, int max_iter, double tol, double *out,

@@ -1306,35 +1306,59 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
     double *d_out = cv.take<double>((size_t)nt);
     if (!cv.ok) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the base-model energies");
     if (model >= 2) {
-        // coupled cluster: one workspace slice per tuple of a launch
+        // coupled cluster: one workspace slice per tuple of a launch; tuples of
+        // at least kCcCoopActive active orbitals run one at a time on many
+        // workgroups (a cooperative launch), the others batched one workgroup
+        // each with slices sized for the largest of them
         int omax = 0, vmax = 0;
+        std::vector<int> occs((size_t)nt);
+        int64_t big_slice = 0;
         for (int64_t t = 0; t < nt; ++t) {
             int o = 0;
             for (int i = 0; i < na[t]; ++i) o += (act[(size_t)t * n + i] < ctx->nalpha) + (act[(size_t)t * n + i] < ctx->nbeta);
-            omax = std::max(omax, o);
-            vmax = std::max(vmax, 2 * na[t] - o);
+            occs[t] = o;
             if (na[t] > kCcMaxActive)
                 return ctx->fail(MBEFCI_EINVAL, "coupled-cluster base: more than 13 active orbitals in a tuple");
+            if (na[t] >= kCcCoopActive) {
+                big_slice = std::max(big_slice, cc_slice_doubles(o, 2 * na[t] - o));
+            } else {
+                omax = std::max(omax, o);
+                vmax = std::max(vmax, 2 * na[t] - o);
+            }
         }
         if (model == 3) {
             const mbefci_status rc = check_canonical(ctx);
             if (rc != MBEFCI_OK) return rc;
         }
         int32_t *d_st = cv.take<int32_t>((size_t)nt);
-        const int64_t slice = (cc_slice_doubles(omax, vmax) + 31) / 32 * 32;
+        double *d_part = cv.take<double>(2 * (size_t)kCcMaxWgs);
+        // (at least one aligned unit: a call may hold only large tuples)
+        const int64_t slice = std::max<int64_t>(32, (cc_slice_doubles(omax, vmax) + 31) / 32 * 32);
         const size_t room = cv.ok && cv.size - cv.off > 256 ? (cv.size - cv.off - 256) / 8 : 0;
         const int64_t per = (int64_t)std::min<size_t>(room / (size_t)slice, 4096);
-        if (!cv.ok || per < 1) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the coupled-cluster base");
-        double *d_work = cv.take<double>((size_t)(per * slice));
+        if (!cv.ok || per < 1 || (size_t)big_slice > room)
+            return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the coupled-cluster base");
+        double *d_work = cv.take<double>(std::max((size_t)(per * slice), (size_t)big_slice));
+        const int wgs = big_slice > 0 ? ccsd_coop_wgs() : 1;
         HIPCHK(hipMemcpyAsync(d_act, act.data(), 4 * act.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(d_core, core.data(), 4 * core.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(d_na, na.data(), 4 * na.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(d_nc, nc.data(), 4 * nc.size(), hipMemcpyHostToDevice, ctx->stream));
-        for (int64_t t0 = 0; t0 < nt; t0 += per) {
-            const int cnt = (int)std::min<int64_t>(per, nt - t0);
-            hipError_t e = launch_ccsd(ctx->d_h, ctx->d_eri, n, d_act + t0 * n, d_na + t0, d_core + t0 * n, d_nc + t0, n,
-                                       ctx->nalpha, ctx->nbeta, ctx->e_const, cnt, d_work, slice, model == 3,
-                                       kCcMaxIter, kCcTol, d_out + t0, d_st + t0, ctx->stream);
+        for (int64_t t0 = 0; t0 < nt;) {
+            hipError_t e;
+            if (na[t0] >= kCcCoopActive) {
+                e = launch_ccsd_coop(ctx->d_h, ctx->d_eri, n, d_act + t0 * n, d_na + t0, d_core + t0 * n, d_nc + t0, n,
+                                     ctx->nalpha, ctx->nbeta, ctx->e_const, d_work, big_slice, model == 3, kCcMaxIter,
+                                     kCcTol, d_out + t0, d_st + t0, wgs, d_part, ctx->stream);
+                ++t0;
+            } else {
+                int cnt = 0;   // a run of small tuples
+                while (t0 + cnt < nt && cnt < per && na[t0 + cnt] < kCcCoopActive) ++cnt;
+                e = launch_ccsd(ctx->d_h, ctx->d_eri, n, d_act + t0 * n, d_na + t0, d_core + t0 * n, d_nc + t0, n,
+                                ctx->nalpha, ctx->nbeta, ctx->e_const, cnt, d_work, slice, model == 3, kCcMaxIter,
+                                kCcTol, d_out + t0, d_st + t0, ctx->stream);
+                t0 += cnt;
+            }
             if (e != hipSuccess) return ctx->fail(MBEFCI_EDEVICE, hipGetErrorString(e));
         }
         std::vector<int32_t> st((size_t)nt);

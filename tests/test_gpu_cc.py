@@ -96,3 +96,24 @@ def test_cc_base_full_order_is_fci(ws):
 def replace_order(P, k):
     from dataclasses import replace
     return replace(P, max_order=k)
+
+
+def test_large_tuple_cooperative_launch(ws):
+    """A tuple of 10 active orbitals runs on many workgroups at once (one
+    cooperative launch, grid barriers between the phases): CCSD against the
+    oracle in the given orbitals, CCSD(T) in the HF orbitals, and the
+    expansion's full order (whose base energy of the whole space takes that
+    path) equal to FCI."""
+    from oracle import hf
+    P = synth.small_problem(10, 2, 2, [1, 2], nvec=5, seed=7, offdiag_std=0.05)
+    X = tuple(P.expansion_space())
+    ctx = M.Context.from_problem(P, device=0, base_model=2)
+    got = ctx.tuple_base(len(X), [X], ws)[0]
+    assert abs(got - cc.base_energy(P, X)) <= TOL
+    res = ctx.run(ws)
+    assert abs(res.total - fci.fci_energy(P)) <= 1e-9
+    _, Q, _ = hf.hf_problem(P)
+    ctx3 = M.Context.from_problem(P, device=0, base_model=3)
+    ctx3.hf(ws)
+    got3 = ctx3.tuple_base(len(X), [X], ws)[0]
+    assert abs(got3 - cc.base_energy(Q, X, triples=True)) <= 1e-8
