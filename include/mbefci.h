@@ -186,7 +186,7 @@ typedef struct {
                                zeroth-order energy (an intruder: the orbitals must be ordered like
                                canonical ones).  2: the same expansion with a CCSD base, 3: with the
                                paper's CCSD(T) base: spin-orbital CCSD on the same Phi within the
-                               tuple's CAS (any orbitals; at most 13 active orbitals per tuple), the
+                               tuple's CAS (any orbitals; at most 32 active orbitals per tuple), the
                                amplitudes converged to a largest change of 1e-11 (ENOCONV after 300
                                iterations; EINVAL when an orbital energy difference of Phi is not
                                negative), and for 3 the (T) correction, which needs canonical

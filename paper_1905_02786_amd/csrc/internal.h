@@ -242,7 +242,7 @@ hipError_t launch_base(const double *h, const double *eri, int n, const int32_t 
                        const int32_t *core, const int32_t *ncore, int sc, int nalpha, int nbeta, double e_const,
                        int ntup, double *out, hipStream_t s);
 // coupled-cluster base (cc.hip): CCSD / CCSD(T) per tuple, one workgroup each
-constexpr int kCcMaxActive = 13;        // active orbitals of a tuple
+constexpr int kCcMaxActive = 32;        // active orbitals of a tuple (the whole space of a base energy included)
 constexpr int kCcMaxIter = 300;         // amplitude iterations
 constexpr double kCcTol = 1e-11;        // largest amplitude change at convergence
 constexpr double kCanonTol = 1e-10;     // off-diagonal Fock elements allowed with (T)

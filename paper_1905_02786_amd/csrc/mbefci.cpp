@@ -1306,10 +1306,15 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
     double *d_out = cv.take<double>((size_t)nt);
     if (!cv.ok) return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the base-model energies");
     if (model >= 2) {
-        // coupled cluster: one workspace slice per tuple of a launch; tuples of
-        // at least kCcCoopActive active orbitals run one at a time on many
-        // workgroups (a cooperative launch), the others batched one workgroup
-        // each with slices sized for the largest of them
+        // coupled cluster: one workspace slice per tuple of a launch.  When a
+        // call holds few tuples (fewer than a quarter of the workgroups one
+        // cooperative launch gets), those of at least kCcCoopActive active
+        // orbitals run one at a time on many workgroups (a cooperative launch,
+        // typically the base energy of the whole space); otherwise every tuple
+        // runs batched, one workgroup each, with slices sized for the largest
+        const int coop_wgs = ccsd_coop_wgs();
+        const bool few = nt * 4 < coop_wgs;
+        auto coop = [&](int64_t t) { return few && na[t] >= kCcCoopActive; };
         int omax = 0, vmax = 0;
         std::vector<int> occs((size_t)nt);
         int64_t big_slice = 0;
@@ -1318,8 +1323,8 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
             for (int i = 0; i < na[t]; ++i) o += (act[(size_t)t * n + i] < ctx->nalpha) + (act[(size_t)t * n + i] < ctx->nbeta);
             occs[t] = o;
             if (na[t] > kCcMaxActive)
-                return ctx->fail(MBEFCI_EINVAL, "coupled-cluster base: more than 13 active orbitals in a tuple");
-            if (na[t] >= kCcCoopActive) {
+                return ctx->fail(MBEFCI_EINVAL, "coupled-cluster base: more than 32 active orbitals in a tuple");
+            if (coop(t)) {
                 big_slice = std::max(big_slice, cc_slice_doubles(o, 2 * na[t] - o));
             } else {
                 omax = std::max(omax, o);
@@ -1339,21 +1344,21 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
         if (!cv.ok || per < 1 || (size_t)big_slice > room)
             return ctx->fail(MBEFCI_ENOMEM, "workspace too small for the coupled-cluster base");
         double *d_work = cv.take<double>(std::max((size_t)(per * slice), (size_t)big_slice));
-        const int wgs = big_slice > 0 ? ccsd_coop_wgs() : 1;
+        const int wgs = coop_wgs;
         HIPCHK(hipMemcpyAsync(d_act, act.data(), 4 * act.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(d_core, core.data(), 4 * core.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(d_na, na.data(), 4 * na.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipMemcpyAsync(d_nc, nc.data(), 4 * nc.size(), hipMemcpyHostToDevice, ctx->stream));
         for (int64_t t0 = 0; t0 < nt;) {
             hipError_t e;
-            if (na[t0] >= kCcCoopActive) {
+            if (coop(t0)) {
                 e = launch_ccsd_coop(ctx->d_h, ctx->d_eri, n, d_act + t0 * n, d_na + t0, d_core + t0 * n, d_nc + t0, n,
                                      ctx->nalpha, ctx->nbeta, ctx->e_const, d_work, big_slice, model == 3, kCcMaxIter,
                                      kCcTol, d_out + t0, d_st + t0, wgs, d_part, ctx->stream);
                 ++t0;
             } else {
                 int cnt = 0;   // a run of small tuples
-                while (t0 + cnt < nt && cnt < per && na[t0 + cnt] < kCcCoopActive) ++cnt;
+                while (t0 + cnt < nt && cnt < per && !coop(t0 + cnt)) ++cnt;
                 e = launch_ccsd(ctx->d_h, ctx->d_eri, n, d_act + t0 * n, d_na + t0, d_core + t0 * n, d_nc + t0, n,
                                 ctx->nalpha, ctx->nbeta, ctx->e_const, cnt, d_work, slice, model == 3, kCcMaxIter,
                                 kCcTol, d_out + t0, d_st + t0, ctx->stream);
