@@ -117,3 +117,17 @@ def test_large_tuple_cooperative_launch(ws):
     ctx3.hf(ws)
     got3 = ctx3.tuple_base(len(X), [X], ws)[0]
     assert abs(got3 - cc.base_energy(Q, X, triples=True)) <= 1e-8
+
+
+def test_two_electrons_in_sixteen_orbitals_is_exact(ws):
+    """Beyond 13 active orbitals (the cooperative launch of one tuple): for
+    two electrons CCSD is exact, so the base energy of the whole 16-orbital
+    space equals its CASCI energy; (T) has no triples to add, so in HF orbitals
+    CCSD(T) gives FCI."""
+    P = synth.small_problem(16, 1, 1, [0, 1], nvec=4, seed=3)
+    X = tuple(P.expansion_space())
+    ctx = M.Context.from_problem(P, device=0, base_model=2)
+    assert abs(ctx.tuple_base(len(X), [X], ws)[0] - fci.casci_energy(P, X)) <= TOL
+    ctx3 = M.Context.from_problem(P, device=0, base_model=3)
+    ctx3.hf(ws)
+    assert abs(ctx3.tuple_base(len(X), [X], ws)[0] - fci.fci_energy(P)) <= 1e-9
