@@ -1316,12 +1316,10 @@ mbefci_status base_energies(mbefci_ctx *ctx, int k, int64_t nt, const int16_t *t
         const bool few = nt * 4 < coop_wgs;
         auto coop = [&](int64_t t) { return few && na[t] >= kCcCoopActive; };
         int omax = 0, vmax = 0;
-        std::vector<int> occs((size_t)nt);
         int64_t big_slice = 0;
         for (int64_t t = 0; t < nt; ++t) {
             int o = 0;
             for (int i = 0; i < na[t]; ++i) o += (act[(size_t)t * n + i] < ctx->nalpha) + (act[(size_t)t * n + i] < ctx->nbeta);
-            occs[t] = o;
             if (na[t] > kCcMaxActive)
                 return ctx->fail(MBEFCI_EINVAL, "coupled-cluster base: more than 32 active orbitals in a tuple");
             if (coop(t)) {
