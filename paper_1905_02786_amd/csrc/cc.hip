@@ -237,22 +237,28 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             if (k < v * v) {
                 const int a = k / v, e = k % v;
                 double x = (a != e) ? f[V0 + a][V0 + e] : 0.0;
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m) x -= 0.5 * f[m][V0 + e] * t1(m, a);
                 for (int m = 0; m < o; ++m)
+                    #pragma unroll 4
                     for (int ff = 0; ff < v; ++ff) x += t1(m, ff) * asy(m, V0 + a, V0 + ff, V0 + e);
                 for (int m = 0; m < o; ++m)
                     for (int nn = 0; nn < o; ++nn)
+                        #pragma unroll 4
                         for (int ff = 0; ff < v; ++ff)
                             x -= 0.5 * taut[((m * o + nn) * v + a) * v + ff] * iovv(m, nn, e, ff);
                 Fae[k] = x;
             } else if (k < v * v + o * o) {
                 const int kk = k - v * v, m = kk / o, i = kk % o;
                 double x = (m != i) ? f[m][i] : 0.0;
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e) x += 0.5 * t1(i, e) * f[m][V0 + e];
                 for (int nn = 0; nn < o; ++nn)
+                    #pragma unroll 4
                     for (int e = 0; e < v; ++e) x += t1(nn, e) * asy(m, nn, i, V0 + e);
                 for (int nn = 0; nn < o; ++nn)
                     for (int e = 0; e < v; ++e)
+                        #pragma unroll 4
                         for (int ff = 0; ff < v; ++ff)
                             x += 0.5 * taut[((i * o + nn) * v + e) * v + ff] * iovv(m, nn, e, ff);
                 Fmi[kk] = x;
@@ -260,6 +266,7 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 const int kk = k - v * v - o * o, m = kk / v, e = kk % v;
                 double x = f[m][V0 + e];
                 for (int nn = 0; nn < o; ++nn)
+                    #pragma unroll 4
                     for (int ff = 0; ff < v; ++ff) x += t1(nn, ff) * iovv(m, nn, e, ff);
                 Fme[kk] = x;
             }
@@ -271,11 +278,13 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             if (k < v * v) {
                 const int b = k / v, e = k % v;
                 double x = Fae[k];
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m) x -= 0.5 * t1(m, b) * Fme[m * v + e];
                 Fbe2[k] = x;
             } else {
                 const int kk = k - v * v, m = kk / o, j = kk % o;
                 double x = Fmi[kk];
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e) x += 0.5 * t1(j, e) * Fme[m * v + e];
                 Fmj2[kk] = x;
             }
@@ -286,23 +295,28 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 const int64_t kk = k - o4 - v4 - o2v2;
                 const int j = kk % o, e = (kk / o) % v, b = (kk / o / v) % v, a = kk / o / v / v;
                 double x = 0.0;
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m) x += t1(m, a) * asy(m, V0 + b, V0 + e, j);
                 Y[kk] = x;
             } else if (k < o4) {
                 const int j = k % o, i = (k / o) % o, nn = (k / o / o) % o, m = k / o / o / o;
                 double x = asy(m, nn, i, j);
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e)
                     x += t1(j, e) * asy(m, nn, i, V0 + e) - t1(i, e) * asy(m, nn, j, V0 + e);
                 for (int e = 0; e < v; ++e)
+                    #pragma unroll 4
                     for (int ff = 0; ff < v; ++ff) x += 0.25 * tau[((i * o + j) * v + e) * v + ff] * iovv(m, nn, e, ff);
                 Wmnij[k] = x;
             } else if (k < o4 + v4) {
                 const int64_t kk = k - o4;
                 const int ff = kk % v, e = (kk / v) % v, b = (kk / v / v) % v, a = kk / v / v / v;
                 double x = asy(V0 + a, V0 + b, V0 + e, V0 + ff);
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m)
                     x -= t1(m, b) * asy(V0 + a, m, V0 + e, V0 + ff) - t1(m, a) * asy(V0 + b, m, V0 + e, V0 + ff);
                 for (int m = 0; m < o; ++m)
+                    #pragma unroll 4
                     for (int nn = 0; nn < o; ++nn) x += 0.25 * tau[((m * o + nn) * v + a) * v + b] * iovv(m, nn, e, ff);
                 Wabef[kk] = x;
             } else {
@@ -310,9 +324,12 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 const int64_t kk = k - o4 - v4;
                 const int j = kk % o, e = (kk / o) % v, b = (kk / o / v) % v, m = kk / o / v / v;
                 double x = asy(m, V0 + b, V0 + e, j);
+                #pragma unroll 4
                 for (int ff = 0; ff < v; ++ff) x += t1(j, ff) * asy(m, V0 + b, V0 + e, V0 + ff);
+                #pragma unroll 4
                 for (int nn = 0; nn < o; ++nn) x -= t1(nn, b) * asy(m, nn, V0 + e, j);
                 for (int nn = 0; nn < o; ++nn)
+                    #pragma unroll 4
                     for (int ff = 0; ff < v; ++ff)
                         x -= (0.5 * t2(j, nn, ff, b) + t1(j, ff) * t1(nn, b)) * iovv(m, nn, e, ff);
                 Wmbej[kk] = x;
@@ -326,7 +343,9 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
             const int b = k % v, j = (k / v) % o, a = (k / v / o) % v, i = k / v / o / v;
             double x = 0.0;
             for (int m = 0; m < o; ++m)
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e) x += t2(i, m, a, e) * wmbej(m, b, e, j);
+            #pragma unroll 4
             for (int e = 0; e < v; ++e) x -= t1(i, e) * Y[((a * v + b) * v + e) * o + j];
             RQ[k] = x;
         }
@@ -341,17 +360,23 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                     continue;
                 }
                 double x = f[i][V0 + a];
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e) x += t1(i, e) * Fae[a * v + e];
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m) x -= t1(m, a) * Fmi[m * o + i];
                 for (int m = 0; m < o; ++m)
+                    #pragma unroll 4
                     for (int e = 0; e < v; ++e) x += t2(i, m, a, e) * Fme[m * v + e];
                 for (int nn = 0; nn < o; ++nn)
+                    #pragma unroll 4
                     for (int ff = 0; ff < v; ++ff) x -= t1(nn, ff) * asy(nn, V0 + a, i, V0 + ff);
                 for (int m = 0; m < o; ++m)
                     for (int e = 0; e < v; ++e)
+                        #pragma unroll 4
                         for (int ff = 0; ff < v; ++ff) x -= 0.5 * t2(i, m, e, ff) * asy(m, V0 + a, V0 + e, V0 + ff);
                 for (int m = 0; m < o; ++m)
                     for (int e = 0; e < v; ++e)
+                        #pragma unroll 4
                         for (int nn = 0; nn < o; ++nn) x -= 0.5 * t2(m, nn, a, e) * asy(nn, m, V0 + e, i);
                 Tn[k] = x / (f[i][i] - f[V0 + a][V0 + a]);
             } else {
@@ -363,20 +388,26 @@ __global__ __launch_bounds__(kCcThreads) void k_ccsd(CcArgs A) {
                 }
                 double x = iovv(i, j, a, b);
                 // P(ab) sum_e t_ij^ae (F_be - 1/2 sum_m t_m^b F_me)
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e) x += t2(i, j, a, e) * Fbe2[b * v + e] - t2(i, j, b, e) * Fbe2[a * v + e];
                 // -P(ij) sum_m t_im^ab (F_mj + 1/2 sum_e t_j^e F_me)
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m) x -= t2(i, m, a, b) * Fmj2[m * o + j] - t2(j, m, a, b) * Fmj2[m * o + i];
                 for (int m = 0; m < o; ++m)
+                    #pragma unroll 4
                     for (int nn = 0; nn < o; ++nn)
                         x += 0.5 * tau[((m * o + nn) * v + a) * v + b] * Wmnij[((m * o + nn) * o + i) * o + j];
                 for (int e = 0; e < v; ++e)
+                    #pragma unroll 4
                     for (int ff = 0; ff < v; ++ff)
                         x += 0.5 * tau[((i * o + j) * v + e) * v + ff] * Wabef[((a * v + b) * v + e) * v + ff];
                 // P(ij) P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
                 x += rq(i, a, j, b) - rq(j, a, i, b) - rq(i, b, j, a) + rq(j, b, i, a);
                 // P(ij) sum_e t_i^e <ab||ej> - P(ab) sum_m t_m^a <mb||ij>
+                #pragma unroll 4
                 for (int e = 0; e < v; ++e)
                     x += t1(i, e) * asy(V0 + a, V0 + b, V0 + e, j) - t1(j, e) * asy(V0 + a, V0 + b, V0 + e, i);
+                #pragma unroll 4
                 for (int m = 0; m < o; ++m)
                     x -= t1(m, a) * asy(m, V0 + b, i, j) - t1(m, b) * asy(m, V0 + a, i, j);
                 Tn[k] = x / (f[i][i] + f[j][j] - f[V0 + a][V0 + a] - f[V0 + b][V0 + b]);
