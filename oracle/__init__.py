@@ -24,6 +24,8 @@ Full Configuration Interaction. II. Strongly Correlated Regime"):
 * ``base``  -- base-model energies of tuples (the expansion of eps - eps_base
   of MBE-FCI-b): second-order Rayleigh-Schroedinger energies of the tuple's
   reference determinant, by brute force over the CAS determinants.
+* ``sym``   -- CASCI energies of a given spatial symmetry (Abelian irrep
+  labels): the lowest eigenvalue on the determinants of the target irrep.
 * ``hf``    -- restricted closed-shell Hartree-Fock orbitals (the paper's
   default expansion orbitals and the reference of its CCSD(T) base), by
   energy descent over the occupied-virtual rotations, and the problem in them.

@@ -179,6 +179,38 @@ def config_hubbard(U: float = 4.0, nsite: int = 10, a: float = 0.0, t: float = 1
                    [ne - 1, ne], a=a, max_order=0, meta={"U": U, "t": t, "nsite": nsite})
 
 
+def hubbard_irreps(nsite: int):
+    """Irrep labels of the hopping eigenvectors of the open chain under the
+    reflection j -> L + 1 - j: the k-th one (k = 1..L) has parity
+    (-1)^(k + 1), label (k - 1) % 2 (0 even, 1 odd)."""
+    return [c % 2 for c in range(nsite)]
+
+
+def symmetric_problem(n: int, nalpha: int, nbeta: int, ref, labels, nvec: int = 8, seed: int = 0,
+                      vec_std: float = 0.1, offdiag_std: float = 0.05, nfrozen: int = 0, a: float = 0.0) -> Problem:
+    """Seeded problem whose Hamiltonian respects Abelian irrep labels (0..7,
+    the product of two irreps is the XOR of their labels): h_pq = 0 unless
+    labels p and q agree, and (pq|rs) = sum_L B^L_pq B^L_rs with B^L_pq = 0
+    unless labels[p] ^ labels[q] equals the irrep L mod (max label + 1) of
+    vector L; orbital energies -1.0 + 0.3 p on the diagonal."""
+    rng = np.random.default_rng(seed)
+    lab = np.asarray(labels)
+    nirr = int(lab.max()) + 1
+    same = lab[:, None] == lab[None, :]
+    h = np.diag(-1.0 + 0.3 * np.arange(n))
+    off = rng.normal(0.0, offdiag_std, size=(n, n))
+    off = np.triu(off, 1)
+    off = (off + off.T) * same
+    h = h + off
+    eri = np.zeros((n, n, n, n))
+    for L in range(nvec):
+        B = _sym_normal(rng, n, vec_std) * ((lab[:, None] ^ lab[None, :]) == (L % nirr))
+        eri += np.einsum("pq,rs->pqrs", B, B)
+    eri = 0.5 * (eri + eri.transpose(2, 3, 0, 1))
+    return Problem(f"sym-n{n}-{nalpha}a{nbeta}b-s{seed}", h, eri, nalpha, nbeta, nfrozen, sorted(ref), a=a,
+                   meta={"seed": seed, "irreps": [int(x) for x in lab]})
+
+
 def config_large(seed: int = 0, a: float = 5.0, max_order: int = 4) -> Problem:
     """Large batched run: 60 orbitals, 6a+6b, orbital energies linspace(-1.5,4.0),
     off-diag N(0,0.05), 150 vectors N(0,0.05); reference CAS(8e,8o) = {2..9};
