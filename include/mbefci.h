@@ -192,6 +192,16 @@ typedef struct {
                                negative), and for 3 the (T) correction, which needs canonical
                                orbitals (EINVAL unless the Fock operator of Phi is diagonal to
                                1e-10 on the reference and expansion orbitals). */
+    double sym_shift;       /* lambda >= 0 of a level shift toward spatial symmetry irrep (0: none):
+                               sigma += lambda [irrep(I) != irrep] c(I), the irrep of a determinant
+                               the XOR of the labels (mbefci_set_orbital_irreps) of its occupied
+                               spin-orbitals; every CASCI energy is then that of the lowest state of
+                               that irrep (the paper's states of given symmetry, Sec. 4.1) when
+                               lambda exceeds its distance to the lowest state of the CAS.  Needs
+                               labels that the Hamiltonian respects (EINVAL otherwise, checked to
+                               1e-12 when a solve starts) and a determinant of the irrep in every
+                               tuple's CAS (EINVAL otherwise).  Whole-tuple mode is not used then. */
+    int32_t irrep;          /* target irrep label 0..7 (with sym_shift > 0) */
 } mbefci_options;
 
 typedef struct {
@@ -459,6 +469,13 @@ mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes,
  * orbitals), ENOMEM if the workspace cannot hold two n^4 arrays. */
 mbefci_status mbefci_hf(mbefci_ctx *ctx, void *d_workspace, size_t ws_bytes, int32_t max_iter, double g_tol,
                         double *U, double *energy, int32_t *iterations);
+
+/* Abelian point-group irrep labels of the n orbitals (host array [n], each
+ * 0..7; the product of two irreps is the XOR of their labels), for
+ * options.sym_shift (Sec. 4.1: states of a given symmetry).  EINVAL for a label
+ * out of range; the Hamiltonian is checked against them when a solve with
+ * sym_shift > 0 starts. */
+mbefci_status mbefci_set_orbital_irreps(mbefci_ctx *ctx, const int32_t *labels);
 
 /* Base-model energies eps_base(S) of ntup tuples of one order, of the model
  * options.base_model names (the second-order one when it is 0).  Host tuples

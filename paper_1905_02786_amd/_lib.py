@@ -21,7 +21,8 @@ class Options(ctypes.Structure):
                 ("gradient", c_int32), ("profile", c_int32), ("sigma_variant", c_int32),
                 ("pspace", c_int32), ("linked_rows", c_int32), ("stream_last", c_int32),
                 ("graph", c_int32), ("autotune", c_int32), ("restart_keep", c_int32),
-                ("spin_shift", c_double), ("whole_dim", c_int32), ("base_model", c_int32)]
+                ("spin_shift", c_double), ("whole_dim", c_int32), ("base_model", c_int32),
+                ("sym_shift", c_double), ("irrep", c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -85,6 +86,7 @@ SIGNATURES = [
     ("mbefci_tuple_base", c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
     ("mbefci_result_base", c_double, [c_void_p]),
     ("mbefci_casscf", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
+    ("mbefci_set_orbital_irreps", c_int32, [c_void_p, c_void_p]),
     ("mbefci_hf", c_int32, [c_void_p, c_void_p, c_size_t, c_int32, c_double, c_void_p, c_void_p, c_void_p]),
     ("mbefci_get_hamiltonian", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     ("mbefci_tuple_rdm", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p,

@@ -141,6 +141,12 @@ class Context:
         a = np.ascontiguousarray(np.asarray(list(pairs), dtype=np.int32).reshape(-1))
         self._check(self.L.mbefci_set_pi_pairs(self.ptr, _p(a) if a.size else None, int(a.size // 2)))
 
+    def set_orbital_irreps(self, labels):
+        """Abelian irrep labels (0..7) of the orbitals, for options
+        sym_shift / irrep (states of a given spatial symmetry)."""
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        self._check(self.L.mbefci_set_orbital_irreps(self.ptr, _p(lab)))
+
     def set_options(self, **kw):
         o = default_options()
         for k, v in kw.items():

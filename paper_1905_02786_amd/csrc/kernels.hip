@@ -127,6 +127,8 @@ __global__ __launch_bounds__(256) void k_hdiag(Batch b, double *out, int64_t ost
         // level shift toward the lowest spin of the sector: lambda times the
         // diagonal of S_- S_+, n_b - (orbitals holding both spins)
         if (b.spin_shift != 0.0) e += b.spin_shift * (double)(b.nb - __popc(ma & mb));
+        // level shift away from the other irreps (spatial symmetry targeting)
+        if (b.sym_shift != 0.0) e += sym_pen(b, t, ma, mb);
         out[(int64_t)t * ostride + d] = e + ec;
     }
 }
@@ -331,6 +333,7 @@ __global__ __launch_bounds__(256) void k_psp_build(Batch b) {
         for (int u = 0; u < na; ++u)
             for (int w2 = 0; w2 < nb; ++w2) x += ca[u] * cb2[w2] * prm[pl.off_eri + Pa[u] * pl.Kpad + Pb[w2]];
         v += 2.0 * x;   // stored as 1/2 (P|Q)
+        if (b.sym_shift != 0.0 && I == J) v += sym_pen(b, t, b.strA[ia], b.strB[ib]);
         if (b.spin_shift != 0.0) {
             const uint32_t mia = b.strA[ia], mja = b.strA[ja], mib = b.strB[ib], mjb = b.strB[jb];
             if (I == J) {

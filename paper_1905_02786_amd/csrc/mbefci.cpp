@@ -289,7 +289,10 @@ struct mbefci_ctx {
     // Hamiltonian
     int norb = 0;
     bool ham_set = false;
+    bool sym_checked = false;   // the Hamiltonian checked against the irrep labels
     std::vector<double> h, eri;
+    std::vector<int32_t> irr;          // orbital irrep labels (empty: not set)
+    int32_t *d_irr = nullptr;
     double e_const = 0.0;
     double *d_h = nullptr, *d_eri = nullptr;
     mbefci_eri_layout eri_layout = MBEFCI_ERI_FULL;
@@ -341,6 +344,8 @@ struct TupleShape {
     int nC;
     std::vector<int32_t> act, core;
 };
+
+mbefci_status check_symmetry(mbefci_ctx *ctx, int order, int64_t ntup, const std::vector<TupleShape> &shapes);
 
 mbefci_status tuple_shape(mbefci_ctx *ctx, int order, const int16_t *tup, TupleShape &ts) {
     for (int i = 0; i < order; ++i) {
@@ -437,6 +442,7 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.linked = cls || cp.linked_dv || cp.linked_w;
     // whole-tuple mode for small classes (not with per-launch sigma timing)
     cp.whole = davidson && cp.variant == SIGMA_STRIP && !ctx->opt.profile && cp.dim <= ctx->opt.whole_dim &&
+               ctx->opt.sym_shift == 0.0 &&
                whole_fits(cp.pl, cp.dim, cp.ta->nstr, cp.tb->nstr, cp.ta->nent, cp.tb->nent,
                           key.na == key.nb);
     // a smaller P space there unless it holds the whole CAS: its
@@ -544,6 +550,9 @@ bool carve_batch(mbefci_ctx *ctx, const ClassPlan &cp, int B, Carver &cv, Batch 
     b.max_space = davidson ? ctx->opt.max_space : 0;
     b.restart_keep = ctx->opt.max_space >= 3 ? ctx->opt.restart_keep : 1;
     b.spin_shift = ctx->opt.spin_shift;
+    b.sym_shift = ctx->opt.sym_shift;
+    b.irrep = ctx->opt.irrep;
+    b.orb_irrep = ctx->d_irr;
     b.whole = cp.whole ? 1 : 0;
     b.max_iter = ctx->opt.max_iter;
     b.e_tol = ctx->opt.e_tol;
@@ -1023,6 +1032,7 @@ mbefci_status solve_device(mbefci_ctx *ctx, int order, int64_t ntup, const int16
         if (rc != MBEFCI_OK) return rc;
         groups[{shapes[i].key, shapes[i].nC}].push_back(i);
     }
+    if (ctx->opt.sym_shift != 0.0 && (rc = check_symmetry(ctx, order, ntup, shapes)) != MBEFCI_OK) return rc;
     const mbefci_options first_opt = ctx->opt;
     std::vector<int64_t> retry;
     for (auto &g : groups) {
@@ -1804,6 +1814,8 @@ void mbefci_default_options(mbefci_options *o) {
     o->spin_shift = 0.0;
     o->whole_dim = kWholeDefaultDim;
     o->base_model = 0;
+    o->sym_shift = 0.0;
+    o->irrep = 0;
 }
 
 mbefci_status mbefci_create(mbefci_ctx **out, int32_t dev, void *stream) {
@@ -1832,6 +1844,7 @@ void mbefci_destroy(mbefci_ctx *ctx) {
     if (!ctx) return;
     if (!ctx->host_only) {
         (void)hipSetDevice(ctx->device);
+        if (ctx->d_irr) (void)hipFree(ctx->d_irr);
         if (ctx->d_h) (void)hipFree(ctx->d_h);
         if (ctx->d_eri) (void)hipFree(ctx->d_eri);
         for (auto e : ctx->ev)
@@ -1893,6 +1906,7 @@ mbefci_status mbefci_set_hamiltonian(mbefci_ctx *ctx, int32_t n, const double *h
     ctx->eri.swap(full);
     ctx->e_const = e_const;
     ctx->ham_set = true;
+    ctx->sym_checked = false;
     if (!ctx->host_only) {
         HIPCHK(hipSetDevice(ctx->device));
         if (ctx->d_h) (void)hipFree(ctx->d_h);
@@ -1966,8 +1980,73 @@ mbefci_status mbefci_set_pi_pairs(mbefci_ctx *ctx, const int32_t *orbs, int32_t 
     return MBEFCI_OK;
 }
 
+mbefci_status mbefci_set_orbital_irreps(mbefci_ctx *ctx, const int32_t *labels) {
+    if (!ctx || !labels) return MBEFCI_EINVAL;
+    if (!ctx->ham_set) return ctx->fail(MBEFCI_ESTATE, "set the Hamiltonian first");
+    for (int p = 0; p < ctx->norb; ++p)
+        if (labels[p] < 0 || labels[p] > 7) return ctx->fail(MBEFCI_EINVAL, "irrep labels must be 0..7");
+    ctx->irr.assign(labels, labels + ctx->norb);
+    ctx->sym_checked = false;
+    if (ctx->device >= 0) {
+        if (!ctx->d_irr) HIPCHK(hipMalloc(&ctx->d_irr, sizeof(int32_t) * kMaxOrb));
+        HIPCHK(hipMemcpy(ctx->d_irr, ctx->irr.data(), sizeof(int32_t) * ctx->norb, hipMemcpyHostToDevice));
+    }
+    return MBEFCI_OK;
+}
+
+namespace {
+
+// Symmetry targeting needs labels that the Hamiltonian respects, and a
+// determinant of the target irrep in every tuple's CAS (the irreps that a
+// spin's electrons can reach on the active orbitals, by counting).
+mbefci_status check_symmetry(mbefci_ctx *ctx, int order, int64_t ntup, const std::vector<TupleShape> &shapes) {
+    if (ctx->irr.size() != (size_t)ctx->norb)
+        return ctx->fail(MBEFCI_EINVAL, "sym_shift needs orbital irrep labels (mbefci_set_orbital_irreps)");
+    if (!ctx->sym_checked) {
+        const int n = ctx->norb;
+        const std::vector<int32_t> &g = ctx->irr;
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) {
+                if (g[p] != g[q] && std::fabs(ctx->h[(size_t)p * n + q]) > 1e-12)
+                    return ctx->fail(MBEFCI_EINVAL, "the Hamiltonian does not respect the irrep labels (h)");
+                for (int r = 0; r < n; ++r)
+                    for (int s = 0; s < n; ++s)
+                        if ((g[p] ^ g[q] ^ g[r] ^ g[s]) != 0 &&
+                            std::fabs(ctx->eri[(((size_t)p * n + q) * n + r) * n + s]) > 1e-12)
+                            return ctx->fail(MBEFCI_EINVAL, "the Hamiltonian does not respect the irrep labels (eri)");
+            }
+        ctx->sym_checked = true;
+    }
+    for (int64_t i = 0; i < ntup; ++i) {
+        const TupleShape &ts = shapes[i];
+        // reach[k] = bit set of irreps of k electrons on the active orbitals seen so far
+        auto reach = [&](int ne) {
+            std::vector<uint32_t> r(ne + 1, 0u);
+            r[0] = 1u;
+            for (int32_t p : ts.act)
+                for (int k = ne; k >= 1; --k)
+                    for (int x = 0; x < 8; ++x)
+                        if (r[k - 1] >> x & 1u) r[k] |= 1u << (x ^ ctx->irr[p]);
+            return r[ne];
+        };
+        const uint32_t ra = reach(ts.key.na), rb = reach(ts.key.nb);
+        bool ok = false;
+        for (int x = 0; x < 8 && !ok; ++x)
+            for (int y = 0; y < 8 && !ok; ++y)
+                ok = (ra >> x & 1u) && (rb >> y & 1u) && (x ^ y) == ctx->opt.irrep;
+        if (!ok) return ctx->fail(MBEFCI_EINVAL, "no determinant of the target irrep in the CAS of a tuple of order " +
+                                                 std::to_string(order));
+    }
+    return MBEFCI_OK;
+}
+
+}  // namespace
+
 mbefci_status mbefci_set_options(mbefci_ctx *ctx, const mbefci_options *o) {
     if (!ctx || !o) return MBEFCI_EINVAL;
+    if (!(o->sym_shift >= 0.0) || !std::isfinite(o->sym_shift))
+        return ctx->fail(MBEFCI_EINVAL, "sym_shift must be finite and >= 0");
+    if (o->irrep < 0 || o->irrep > 7) return ctx->fail(MBEFCI_EINVAL, "irrep must be 0..7");
     if (!std::isfinite(o->a)) return ctx->fail(MBEFCI_EINVAL, "non-finite a");
     if (o->max_space < 2 || o->max_space > kMaxSpace) return ctx->fail(MBEFCI_EINVAL, "max_space must be in 2..32");
     if (o->max_iter < 1) return ctx->fail(MBEFCI_EINVAL, "max_iter must be >= 1");
@@ -2552,6 +2631,7 @@ mbefci_status mbefci_casscf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_i
             ctx->h[(size_t)p * n + q] = ctx->h[(size_t)q * n + p] = v;
         }
     HIPCHK(hipMemcpy(ctx->d_h, ctx->h.data(), 8 * n2, hipMemcpyHostToDevice));
+    ctx->sym_checked = false;
     if (U_out) std::memcpy(U_out, Uc.data(), 8 * n2);
     if (e_out) *e_out = E;
     if (iter_out) *iter_out = it;
@@ -2814,6 +2894,7 @@ mbefci_status mbefci_hf(mbefci_ctx *ctx, void *ws, size_t wsb, int32_t max_iter,
             ctx->h[(size_t)p * n + q] = ctx->h[(size_t)q * n + p] = v;
         }
     HIPCHK(hipMemcpy(ctx->d_h, ctx->h.data(), 8 * n2, hipMemcpyHostToDevice));
+    ctx->sym_checked = false;
     if (U_out) std::memcpy(U_out, Uc.data(), 8 * n2);
     if (e_out) *e_out = E;
     if (iter_out) *iter_out = it;

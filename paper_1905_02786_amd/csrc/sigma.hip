@@ -390,6 +390,25 @@ static hipError_t launch_spin_sigma(const Batch &b, VecRef c, VecRef sig, bool s
     return hipGetLastError();
 }
 
+// Level shift away from the irreps other than the target one: sigma +=
+// lambda [irrep(I) != target] c(I), diagonal in the determinants (the
+// Hamiltonian does not couple irreps).
+__global__ __launch_bounds__(256) void k_sym_sigma(Batch b, VecRef cref, VecRef sref, int skip_done) {
+    const int t = blockIdx.y;
+    if (skip_done && b.status[t] != ST_RUNNING) return;
+    const double *c = vref(cref, t, b.dim);
+    double *sg = const_cast<double *>(vref(sref, t, b.dim));
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < b.dim; d += (int64_t)gridDim.x * 256)
+        sg[d] += sym_pen(b, t, b.strA[d / b.Nb], b.strB[d % b.Nb]) * c[d];
+}
+
+static hipError_t launch_sym_sigma(const Batch &b, VecRef c, VecRef sig, bool skip_done, hipStream_t s) {
+    if (b.sym_shift == 0.0) return hipSuccess;
+    hipLaunchKernelGGL(k_sym_sigma, dim3(grid_for(b.dim, 256, 4096), b.B), dim3(256), 0, s, b, c, sig,
+                       skip_done ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool skip_done, bool dots,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t evg, hipEvent_t ev2) {
     if (b.sigma_variant == SIGMA_STRIP) {
@@ -399,6 +418,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
         if (evg) (void)hipEventRecord(evg, s);
         // (before the GEMM, whose epilogue forms the Davidson dots of the final sigma)
         if ((e = launch_spin_sigma(b, c, sig, skip_done, s)) != hipSuccess) return e;
+        if ((e = launch_sym_sigma(b, c, sig, skip_done, s)) != hipSuccess) return e;
         e = launch_gemm_h(b, c, sig, skip_done ? 1 : 0, dots ? 1 : 0, s);
         if (ev2) (void)hipEventRecord(ev2, s);
         return e;
@@ -421,6 +441,7 @@ hipError_t launch_sigma(const Batch &b, VecRef c, VecRef sig, double shift, bool
     hipLaunchKernelGGL(k_sigma_g, grid, dim3(256), 0, s, b, c, sig, shift, skip_done ? 1 : 0);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch_spin_sigma(b, c, sig, skip_done, s);
+    if (e == hipSuccess) e = launch_sym_sigma(b, c, sig, skip_done, s);
     if (ev2) (void)hipEventRecord(ev2, s);
     return e;
 }

@@ -1,0 +1,96 @@
+"""Spatial-symmetry targeting (options.sym_shift / irrep with orbital irrep
+labels) against the oracle (oracle/sym.py: the lowest eigenvalue on the
+determinants of the target irrep).  lambda = 2 E_h exceeds the distance of
+every target irrep's lowest state to the lowest state of the CAS in these
+problems (at most 1.2 E_h), so the shifted lowest state is the target's.
+Tolerance 1e-10 as in the other parity tests."""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fci, mbe, sym
+
+torch = pytest.importorskip("torch")
+import paper_1905_02786_amd as M  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+LAM = 2.0
+
+
+@pytest.fixture(scope="module")
+def ws():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return M.workspace(2 << 30)
+
+
+LAB4 = [0, 1, 2, 3, 0, 1, 2, 3]
+PROBLEMS = {
+    "hubbard8": (lambda: synth.config_hubbard(4.0, nsite=8), synth.hubbard_irreps(8), (0, 1)),
+    "sym4": (lambda: synth.symmetric_problem(8, 3, 3, [2, 3], LAB4, seed=1), LAB4, (0, 1, 2, 3)),
+}
+
+
+def _ctx(P, lab, g):
+    ctx = M.Context.from_problem(P, device=0, sym_shift=LAM, irrep=g)
+    ctx.set_orbital_irreps(lab)
+    return ctx
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_irrep_energies_match_oracle(ws, name):
+    make, lab, targets = PROBLEMS[name]
+    P = make()
+    X = P.expansion_space()
+    worst = 0.0
+    for g in targets:
+        ctx = _ctx(P, lab, g)
+        for k in (0, 1, 2):
+            tl = list(itertools.combinations(X, k)) if k else [()]
+            ok = []
+            for S in tl:
+                try:
+                    ok.append((S, sym.casci_energy_irrep(P, S, lab, g)))
+                except ValueError:
+                    pass
+            if len(ok) < len(tl):   # a tuple without the irrep makes the whole call an error
+                with pytest.raises(M.MBEFCIError, match="target irrep"):
+                    ctx.solve_tuples(k, tl, ws)
+            if not ok:
+                continue
+            e, st = ctx.solve_tuples(k, [S for S, _ in ok], ws)
+            assert (st == 0).all()
+            worst = max(worst, float(np.abs(e - np.array([r for _, r in ok])).max()))
+    print(f"{name}: max |dE| {worst:.1e}", flush=True)
+    assert worst <= 1e-10
+
+
+@pytest.mark.parametrize("g", [0, 1])
+def test_irrep_expansion_matches_oracle(ws, g):
+    """Full-order MBE of the 8-site chain for each reflection irrep: every
+    increment against the oracle's, the total equal to the irrep's FCI."""
+    P = synth.config_hubbard(4.0, nsite=8)
+    lab = synth.hubbard_irreps(8)
+    res = _ctx(P, lab, g).run(ws)
+    ref = mbe.run(P, energy=lambda S: sym.casci_energy_irrep(P, S, lab, g))
+    for o, ro in zip(res.orders, ref.orders):
+        assert [tuple(int(x) for x in t) for t in o.tuples] == [tuple(t) for t in ro.tuples] or o.k == 0
+        assert np.abs(o.eps - np.asarray(ro.eps)).max() <= 1e-10
+        assert np.abs(o.dinc - np.asarray(ro.dinc)).max() <= 1e-9
+    e_fci = sym.casci_energy_irrep(P, tuple(P.expansion_space()), lab, g)
+    assert abs(res.total - e_fci) <= 1e-9
+    if g == 0:   # the chain's ground state is even: the plain expansion agrees
+        assert abs(res.total - fci.fci_energy(P)) <= 1e-9
+
+
+def test_symmetry_errors(ws):
+    P = synth.config_hubbard(4.0, nsite=8)
+    ctx = M.Context.from_problem(P, device=0, sym_shift=LAM, irrep=1)
+    with pytest.raises(M.MBEFCIError, match="labels"):
+        ctx.solve_tuples(0, [()], ws)             # labels not set
+    Q = synth.small_problem(8, 4, 4, [3, 4], nvec=4, seed=3)
+    ctx = _ctx(Q, synth.hubbard_irreps(8), 1)
+    with pytest.raises(M.MBEFCIError, match="respect"):
+        ctx.solve_tuples(0, [()], ws)             # a Hamiltonian without the symmetry
