@@ -94,3 +94,40 @@ def test_symmetry_errors(ws):
     ctx = _ctx(Q, synth.hubbard_irreps(8), 1)
     with pytest.raises(M.MBEFCIError, match="respect"):
         ctx.solve_tuples(0, [()], ws)             # a Hamiltonian without the symmetry
+
+
+def _irrep_vector(P, S, lab, g):
+    """The oracle's lowest irrep-g eigenvector, embedded in the CAS."""
+    sp = fci.cas_space(P, S)
+    idx = sym.irrep_indices(P, sp, lab, g)
+    H = fci.hamiltonian_matrix(P, sp)
+    w, V = np.linalg.eigh(H[np.ix_(idx, idx)])
+    v = np.zeros(sp.dim)
+    v[idx] = V[:, 0]
+    return w[0], v, sp
+
+
+def test_irrep_density_matrices_and_gradient(ws):
+    """The density matrices of a symmetry-targeted tuple state, and the
+    full-order gradient of the odd-irrep expansion, against the oracle's
+    density matrices of the irrep eigenvector (the shift does not depend on
+    the integrals, so dE/dh = gamma and dE/d(pq|rs) = Gamma / 2 of that
+    state)."""
+    from oracle import rdm as ordm
+    P = synth.config_hubbard(4.0, nsite=8)
+    lab = synth.hubbard_irreps(8)
+    ctx = M.Context.from_problem(P, device=0, sym_shift=LAM, irrep=1, r_tol=1e-10, e_tol=1e-13)
+    ctx.set_orbital_irreps(lab)
+    S = (1, 6)
+    e, g1, g2 = ctx.tuple_rdm(len(S), S, ws)
+    e_ref, v, sp = _irrep_vector(P, S, lab, 1)
+    r1, r2 = ordm.rdm12(P, sp, v)
+    assert abs(e - e_ref) <= 1e-10
+    assert np.abs(g1 - r1).max() <= 1e-7 and np.abs(g2 - r2).max() <= 1e-7
+    res, handle = ctx.run(ws, keep=True)
+    gh, ge = ctx.backward(handle, ws)
+    e_ref, v, sp = _irrep_vector(P, tuple(P.expansion_space()), lab, 1)
+    r1, r2 = ordm.rdm12(P, sp, v)
+    assert abs(res.total - e_ref) <= 1e-9
+    assert np.abs(gh - r1).max() <= 1e-7
+    assert np.abs(ge - 0.5 * r2).max() <= 1e-7
