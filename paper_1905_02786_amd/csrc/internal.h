@@ -123,9 +123,6 @@ struct Batch {
     // quotient
     int restart_keep;
     double spin_shift;      // lambda of the level shift lambda S_- S_+ (0: none)
-    double sym_shift;       // lambda of the level shift away from other irreps (0: none)
-    int irrep;              // target irrep label
-    const int32_t *orb_irrep;   // [n] irrep labels of the orbitals (device)
     int whole;              // whole-tuple mode: one workgroup per tuple runs the whole Davidson solve
     double *y2, *zp;        // [B][kMaxSpace]
     double *mu;             // [B]
@@ -147,6 +144,10 @@ struct Batch {
     double *rdm_part;       // [B][nblk_r][NP*NP]
     double *rdm_G;          // [B][NP*NP]
     double *rdm_w;          // [B] weights of the device embedding into the gradient
+    // spatial symmetry targeting
+    double sym_shift;       // lambda of the level shift away from other irreps (0: none)
+    int irrep;              // target irrep label
+    const int32_t *orb_irrep;   // [n] irrep labels of the orbitals (device)
 };
 
 // kernels.hip, sigma.hip and strip.hip

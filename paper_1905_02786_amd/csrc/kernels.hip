@@ -12,6 +12,7 @@
 //   E_core = E_const + sum_c 2 h_cc + sum_cd [2(cc|dd) - (cd|dc)],
 // over p, q, r, s in A and c in the core C.
 #include "device.h"
+#include "symmetry.h"
 
 namespace mbefci {
 

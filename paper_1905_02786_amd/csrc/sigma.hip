@@ -6,6 +6,7 @@
 //   H = E_core + sum_pq k_pq E_pq + 1/2 sum_pqrs (pq|rs) E_pq E_rs,
 // with k and E_core as formed by k_gather.
 #include "device.h"
+#include "symmetry.h"
 
 namespace mbefci {
 
