@@ -161,6 +161,13 @@ def test_invalid_inputs_rejected():
     for bm in (0, 1, 2, 3):
         ctx.set_options(base_model=bm)
     ctx.set_options(base_model=0)
+    for bad in (dict(sym_shift=-1.0), dict(sym_shift=float("inf")), dict(irrep=-1), dict(irrep=8)):
+        with pytest.raises(M.MBEFCIError):
+            ctx.set_options(**bad)
+    ctx.set_options(sym_shift=0.0, irrep=0)
+    with pytest.raises(M.MBEFCIError):
+        ctx.set_orbital_irreps([0, 1, 2, 8])         # labels 0..7 only
+    ctx.set_orbital_irreps([0, 1, 0, 1])
     # full-layout integrals must be 8-fold symmetric
     asym = np.zeros((4,) * 4)
     asym[0, 1, 2, 3] = 0.3
