@@ -200,7 +200,7 @@ typedef struct {
                                lambda exceeds its distance to the lowest state of the CAS.  Needs
                                labels that the Hamiltonian respects (EINVAL otherwise, checked to
                                1e-12 when a solve starts) and a determinant of the irrep in every
-                               tuple's CAS (EINVAL otherwise).  Whole-tuple mode is not used then. */
+                               tuple's CAS (EINVAL otherwise). */
     int32_t irrep;          /* target irrep label 0..7 (with sym_shift > 0) */
 } mbefci_options;
 

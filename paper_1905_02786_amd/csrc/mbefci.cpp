@@ -442,7 +442,6 @@ void plan_class(mbefci_ctx *ctx, const ClassKey &key, int nC, ClassPlan &cp, boo
     cp.linked = cls || cp.linked_dv || cp.linked_w;
     // whole-tuple mode for small classes (not with per-launch sigma timing)
     cp.whole = davidson && cp.variant == SIGMA_STRIP && !ctx->opt.profile && cp.dim <= ctx->opt.whole_dim &&
-               ctx->opt.sym_shift == 0.0 &&
                whole_fits(cp.pl, cp.dim, cp.ta->nstr, cp.tb->nstr, cp.ta->nent, cp.tb->nent,
                           key.na == key.nb);
     // a smaller P space there unless it holds the whole CAS: its

@@ -18,6 +18,7 @@
 // kernels apply.  On exit theta, status, iteration count, m and the Ritz
 // coefficients y on V are written as the batched iteration leaves them.
 #include "device.h"
+#include "symmetry.h"
 
 namespace mbefci {
 
@@ -351,6 +352,7 @@ __global__ __launch_bounds__(kWholeThreads) void k_whole(Batch b) {
         }
         acc += 2.0 * ab;   // the table holds (P|Q) / 2
         if (lam != 0.0) acc += lam * spin_ss(b, cL, Ia, Ib);
+        if (b.sym_shift != 0.0) acc += sym_pen(b, t, b.strA[Ia], b.strB[Ib]) * cL[d];
         return acc;
     };
 
