@@ -131,3 +131,39 @@ def test_irrep_density_matrices_and_gradient(ws):
     assert abs(res.total - e_ref) <= 1e-9
     assert np.abs(gh - r1).max() <= 1e-7
     assert np.abs(ge - 0.5 * r2).max() <= 1e-7
+
+
+def test_spin_and_symmetry_together(ws):
+    """Both shifts: the lowest singlet of the odd irrep (the lowest odd state
+    of the chain's tuples is often a triplet component) against the oracle's
+    lowest eigenvector of the irrep block with <S^2> = 0."""
+    from oracle import spin
+    P = synth.config_hubbard(4.0, nsite=8)
+    lab = synth.hubbard_irreps(8)
+    # the odd singlet lies up to 1.49 E_h above the lowest odd state here, so
+    # lambda_sym = 3 keeps the shifted even states clear of it
+    ctx = M.Context.from_problem(P, device=0, sym_shift=3.0, irrep=1, spin_shift=1.0)
+    ctx.set_orbital_irreps(lab)
+    X = P.expansion_space()
+    worst, differs = 0.0, 0
+    for k in (0, 1, 2):
+        tl = list(itertools.combinations(X, k)) if k else [()]
+        ref = []
+        for S in tl:
+            sp = fci.cas_space(P, S)
+            idx = sym.irrep_indices(P, sp, lab, 1)
+            H = fci.hamiltonian_matrix(P, sp)
+            w, V = np.linalg.eigh(H[np.ix_(idx, idx)])
+            for c in range(len(w)):
+                v = np.zeros(sp.dim)
+                v[idx] = V[:, c]
+                if abs(spin.s2_expectation(sp, v)) < 1e-8:
+                    ref.append(w[c])
+                    differs += c > 0
+                    break
+        e, st = ctx.solve_tuples(k, tl, ws)
+        assert (st == 0).all()
+        worst = max(worst, float(np.abs(e - np.array(ref)).max()))
+    print(f"max |dE| {worst:.1e}; tuples whose odd singlet is not the odd ground state: {differs}")
+    assert differs > 0
+    assert worst <= 1e-10
