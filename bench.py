@@ -46,10 +46,10 @@ KERNEL_NAMES = {0: "k_sigma_strip", 1: "k_sigma_linked_gat", 2: "k_sigma_linked_
 TRAFFIC = {
     # kernel id -> (sources sha1, calibrated bytes per application), from
     # profiles/hbm-traffic-large-n60-order4.md
-    "large": {3: ("9a4ddb6179af090931b121c789577c546b69bde1", 6531875.1),
-              5: ("9a4ddb6179af090931b121c789577c546b69bde1", 257788770.6)},
+    "large": {3: ("319ed2d3d5382e41fe85f255564b95618c69dca5", 6610398.3),
+              5: ("319ed2d3d5382e41fe85f255564b95618c69dca5", 245556498.8)},
     # profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md
-    "sweep": {2: ("9a4ddb6179af090931b121c789577c546b69bde1", 1360333.7)},
+    "sweep": {2: ("319ed2d3d5382e41fe85f255564b95618c69dca5", 1360333.7)},
 }
 
 

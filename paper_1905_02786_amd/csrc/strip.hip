@@ -87,6 +87,11 @@ __device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, i
 // Sum of x over the four lanes l, l^16, l^32, l^48 (the (lane >> 4) groups of
 // an MFMA output column), as ((x0 + x1) + (x2 + x3)) in every one of them:
 // row swaps of 16 and 32 lanes on the vector ALU, no LDS round trip.
+// A compile-time flag passed to generic lambdas.
+template <bool B> struct BoolC {
+    static constexpr bool value = B;
+};
+
 __device__ __forceinline__ double sum_over_kr(double x) {
     const unsigned lo = __double2loint(x), hi = __double2hiint(x);
     const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
@@ -1069,9 +1074,23 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
     uint32_t dtgt = Na;    // its target row (the string itself; the discard row before the first pair)
     __syncthreads();
 
-    // MFMAs of pair q, and in the h = 0 waves the diagonal sum of string g
-    auto mphase = [&](uint32_t q) {
+    // MFMAs of pair q, and in the h = 0 waves (DG) the diagonal sum of string
+    // g.  The diagonal sum's LDS reads are issued together ahead of the
+    // chain's operands (taken one at a time after the chain, each one's
+    // latency delayed the barrier that ends the phase); the scheduling
+    // barriers keep them there and keep the chain ahead of that barrier.
+    auto mphase = [&](uint32_t q, auto dgc) {
+        constexpr bool DG = decltype(dgc)::value;
+        constexpr int NG = DG ? (KS + 1) / 2 : 1;
         double bv[KS], af[KS];
+        dbl2v gv[NG];
+        if constexpr (DG) {
+            const uint32_t grow = gd + (uint32_t)kr * 16u;
+#pragma unroll
+            for (int j = 0; j < KS / 2; ++j) gv[j] = *reinterpret_cast<const dbl2v *>(lds_at(grow + 64u * j));
+            if (KS & 1) gv[NG - 1][0] = *lds_at(grow + 64u * (KS / 2));
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) bv[ks] = *lds_at(dr + ks * 4u * kStrip * (uint32_t)sizeof(double));
         const uint32_t arow = A0 + ra + (uint32_t)kr * 16u;
@@ -1086,17 +1105,12 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], bv[ks], a, 0, 0, 0);
         acc = a;
-        if (h == 0) {
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (DG) {
             // lane (kr, ar): sum over k = 4 ks + kr of G_k D_k(ar), in ks order
-            const uint32_t grow = gd + (uint32_t)kr * 16u;
             double s = 0.0;
 #pragma unroll
-            for (int j = 0; j < KS / 2; ++j) {
-                const dbl2v v = *reinterpret_cast<const dbl2v *>(lds_at(grow + 64u * j));
-                s = __builtin_fma(v[0], bv[2 * j], s);
-                s = __builtin_fma(v[1], bv[2 * j + 1], s);
-            }
-            if (KS & 1) s = __builtin_fma(*lds_at(grow + 64u * (KS / 2)), bv[KS - 1], s);
+            for (int ks = 0; ks < KS; ++ks) s = __builtin_fma(gv[ks / 2][ks & 1], bv[ks], s);
             dsum = sum_over_kr(s);
             dtgt = trow(str(q, g));
         }
@@ -1124,23 +1138,31 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
         if (dgl) dg = load_dg(str(p + 3, g));
         rap = load_row(str(p + 3, g));
     };
-    // phases 0 .. 2k - 1 cover the last pair's scatter in phase lpairs
+    // phases 0 .. 2k - 1 cover the last pair's scatter in phase lpairs; the
+    // loop is compiled once with the diagonal sum (h = 0 waves) and once
+    // without
     const uint32_t nph = (uint32_t)b.lpairs + 1;
-    if (z == 0) {
-        for (uint32_t p = 0; p < nph; p += 2) {
-            mphase(p);
-            __syncthreads();
-            nphase(p + 1);
-            __syncthreads();
+    auto run = [&](auto dgc) {
+        if (z == 0) {
+            for (uint32_t p = 0; p < nph; p += 2) {
+                mphase(p, dgc);
+                __syncthreads();
+                nphase(p + 1);
+                __syncthreads();
+            }
+        } else {
+            for (uint32_t p = 0; p < nph; p += 2) {
+                nphase(p);
+                __syncthreads();
+                mphase(p + 1, dgc);
+                __syncthreads();
+            }
         }
-    } else {
-        for (uint32_t p = 0; p < nph; p += 2) {
-            nphase(p);
-            __syncthreads();
-            mphase(p + 1);
-            __syncthreads();
-        }
-    }
+    };
+    if (h == 0)
+        run(BoolC<true>{});
+    else
+        run(BoolC<false>{});
     for (uint32_t i = tid; i < Na * kStrip; i += 512) {
         const uint32_t row = i / kStrip, col = i % kStrip;
         if (B0 + col < Nb) {
