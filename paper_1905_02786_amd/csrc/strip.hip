@@ -1135,8 +1135,12 @@ __global__ __launch_bounds__(512) void k_sigma_linked_dv(Batch b, VecRef cref, V
 #pragma unroll
         for (int i = 0; i < NDI; ++i)
             if (item_on(i)) cb[i] = load_c(str(p + 3, item_str(i)), i);
-        if (dgl) dg = load_dg(str(p + 3, g));
-        rap = load_row(str(p + 3, g));
+        // the string index as a scalar, so that the row load's offset is one
+        // (a vector offset there costs a waterfall loop and a register copy
+        // that waits for every load just issued)
+        const uint32_t s3 = (uint32_t)__builtin_amdgcn_readfirstlane((int)str(p + 3, g));
+        if (dgl) dg = load_dg(s3);
+        rap = load_row(s3);
     };
     // phases 0 .. 2k - 1 cover the last pair's scatter in phase lpairs; the
     // loop is compiled once with the diagonal sum (h = 0 waves) and once
