@@ -46,10 +46,10 @@ KERNEL_NAMES = {0: "k_sigma_strip", 1: "k_sigma_linked_gat", 2: "k_sigma_linked_
 TRAFFIC = {
     # kernel id -> (sources sha1, calibrated bytes per application), from
     # profiles/hbm-traffic-large-n60-order4.md
-    "large": {3: ("6f0c862312694c5772c95b39247840045c18a582", 6583818.2),
-              5: ("6f0c862312694c5772c95b39247840045c18a582", 245659318.1)},
+    "large": {3: ("585e181301a003da4f6be845fb36597025553baf", 6583818.2),
+              5: ("585e181301a003da4f6be845fb36597025553baf", 245659318.1)},
     # profiles/hbm-traffic-sweep-n24-cas66-orders1-5.md
-    "sweep": {2: ("6f0c862312694c5772c95b39247840045c18a582", 1360333.7)},
+    "sweep": {2: ("585e181301a003da4f6be845fb36597025553baf", 1360333.7)},
 }
 
 

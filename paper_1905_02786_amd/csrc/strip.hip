@@ -84,14 +84,14 @@ __device__ __forceinline__ bool xcd_map(int64_t L, int nstrips, int B, int &t, i
     return t < B;
 }
 
-// Sum of x over the four lanes l, l^16, l^32, l^48 (the (lane >> 4) groups of
-// an MFMA output column), as ((x0 + x1) + (x2 + x3)) in every one of them:
-// row swaps of 16 and 32 lanes on the vector ALU, no LDS round trip.
 // A compile-time flag passed to generic lambdas.
 template <bool B> struct BoolC {
     static constexpr bool value = B;
 };
 
+// Sum of x over the four lanes l, l^16, l^32, l^48 (the (lane >> 4) groups of
+// an MFMA output column), as ((x0 + x1) + (x2 + x3)) in every one of them:
+// row swaps of 16 and 32 lanes on the vector ALU, no LDS round trip.
 __device__ __forceinline__ double sum_over_kr(double x) {
     const unsigned lo = __double2loint(x), hi = __double2hiint(x);
     const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
